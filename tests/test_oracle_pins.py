@@ -1,0 +1,287 @@
+"""Pins of the CPU oracle against constructions independent of it.
+
+Each test fixes one part of the oracle by something other than the oracle
+itself: Kronecker-product assembly of the operator, triangular solves of the
+Gauss-Seidel splitting on the colour-permuted matrix, an explicit injection
+matrix, dense LU, least squares, closed forms and invariants.  Non-cubic grids
+are used where a swapped axis would otherwise go unnoticed.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_2507_11512_amd import inputs
+from tests import refimpl
+
+
+def oracle_matrix(o, d, beta=0.5, faces_only=False):
+    """Assemble the oracle's operator column by column from unit vectors."""
+    nx, ny, nz = refimpl.dims3(d)
+    n = nx * ny * nz
+    A = np.zeros((n, n))
+    e = np.zeros(n)
+    for j in range(n):
+        e[j] = 1.0
+        A[:, j] = o.spmv(d, e, beta, faces_only)
+        e[j] = 0.0
+    return A
+
+
+# ---------------------------------------------------------------- operator --
+@pytest.mark.parametrize("d", [(4, 5, 6), (3, 3, 3), (6, 4, 2)])
+@pytest.mark.parametrize("beta", [0.0, 0.5, -0.3])
+@pytest.mark.parametrize("faces_only", [False, True])
+def test_operator_equals_kronecker_assembly(oracle_mod, d, beta, faces_only):
+    A = oracle_matrix(oracle_mod, d, beta, faces_only)
+    K = refimpl.kron_matrix(d, beta, faces_only).toarray()
+    assert np.array_equal(A, K)
+
+
+@pytest.mark.parametrize("d", [(4, 5, 6), (5, 5, 5)])
+def test_operator_structure(oracle_mod, d):
+    nx, ny, nz = d
+    A = oracle_matrix(oracle_mod, d, 0.5)
+    # nonzero count of a Dirichlet-truncated 27-point stencil
+    assert np.count_nonzero(A) == (3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2)
+    assert np.all(np.diag(A) == 26.0)
+    off = np.abs(A).sum(axis=1) - np.abs(np.diag(A))
+    assert np.all(off <= 26.0 + 1e-15)                 # weak diagonal dominance
+    i, j, k = refimpl.grid_coords(d)
+    boundary = (i == 0) | (i == nx - 1) | (j == 0) | (j == ny - 1) | (k == 0) | (k == nz - 1)
+    assert np.all(off[boundary] < 26.0)                # strict on boundary rows
+    assert np.all(off[~boundary] == 26.0)
+    row_sum = A.sum(axis=1)
+    assert np.all(row_sum[~boundary] == 0.0)           # interior (A 1)_i = 0
+
+
+@pytest.mark.parametrize("faces_only", [False, True])
+def test_transpose_is_negated_shift(oracle_mod, faces_only):
+    d = (4, 5, 3)
+    A = oracle_matrix(oracle_mod, d, 0.5, faces_only)
+    At = oracle_matrix(oracle_mod, d, -0.5, faces_only)
+    assert np.array_equal(A.T, At)
+
+
+def test_spmv_rows_and_absrow(oracle_mod):
+    d = (7, 6, 5)
+    x = inputs.uniform(d, 3)
+    y = oracle_mod.spmv(d, x)
+    rows = np.array([0, 1, 17, 100, 209, 7 * 6 * 5 - 1])
+    assert np.array_equal(oracle_mod.spmv_rows(d, x, rows), y[rows])
+    K = refimpl.kron_matrix(d, 0.5)
+    assert np.allclose(oracle_mod.absrow(d, x), abs(K) @ np.abs(x), rtol=1e-15, atol=0)
+
+
+def test_spmv_matches_kronecker_on_larger_grid(oracle_mod):
+    d = (16, 12, 10)
+    x = inputs.uniform(d, 4)
+    y = oracle_mod.spmv(d, x)
+    K = refimpl.kron_matrix(d, 0.5)
+    scale = abs(K) @ np.abs(x)
+    assert np.all(np.abs(y - K @ x) <= 1e-14 * scale)
+
+
+# ------------------------------------------------------------------ colours --
+def test_colouring_is_independent_and_minimal(oracle_mod):
+    d = (6, 5, 4)
+    nx, ny, nz = d
+    c = np.array([oracle_mod.color(i, j, k) for k in range(nz) for j in range(ny) for i in range(nx)])
+    assert np.array_equal(c, refimpl.colour_of(d))
+    assert set(c.tolist()) == set(range(8))
+    K = sp.coo_matrix(refimpl.kron_matrix(d, 0.5))
+    off = K.row != K.col
+    assert np.all(c[K.row[off]] != c[K.col[off]])      # each colour is an independent set
+    # a 2x2x2 block is a clique of the stencil graph, so 8 colours are needed
+    blk = [i + nx * (j + ny * k) for k in (1, 2) for j in (1, 2) for i in (1, 2)]
+    assert len(set(c[blk].tolist())) == 8
+    # the injection points (all coordinates even) form the single colour 4
+    i, j, k = refimpl.grid_coords(d)
+    even = (i % 2 == 0) & (j % 2 == 0) & (k % 2 == 0)
+    assert np.all(c[even] == 4) and np.all(c[c == 4] == c[even][0])
+
+
+# ------------------------------------------------------------- Gauss-Seidel --
+@pytest.mark.parametrize("d", [(8, 8, 8), (6, 5, 4), (16, 8, 12)])
+@pytest.mark.parametrize("sweep", [0, 1, 2])
+def test_gs_equals_triangular_solves(oracle_mod, d, sweep):
+    r = inputs.uniform(d, 10)
+    z0 = inputs.uniform(d, 11)
+    A = refimpl.kron_matrix(d, 0.5)
+    ref = refimpl.gs_triangular(A, refimpl.colour_perm(d), r, z0, sweep)
+    got = oracle_mod.gs(d, r, z0, sweep)
+    assert np.allclose(got, ref, rtol=0, atol=1e-14 * np.abs(ref).max())
+
+
+def test_gs_fixed_point_is_the_solution(oracle_mod):
+    d = (6, 6, 6)
+    x = inputs.uniform(d, 12)
+    r = oracle_mod.spmv(d, x)
+    z = oracle_mod.gs(d, r, x, 0)
+    assert np.allclose(z, x, rtol=0, atol=1e-14)
+
+
+# ------------------------------------------------------------ grid transfer --
+@pytest.mark.parametrize("d", [(8, 8, 8), (4, 6, 10)])
+def test_injection_and_prolongation(oracle_mod, d):
+    R = refimpl.injection_matrix(d)
+    v = inputs.uniform(d, 20)
+    nc = R.shape[0]
+    w = np.random.default_rng(21).uniform(-1, 1, nc)
+    assert np.array_equal(oracle_mod.inject(d, v), R @ v)
+    z = inputs.uniform(d, 22)
+    assert np.array_equal(oracle_mod.prolong_add(d, w, z), z + R.T @ w)
+    # adjointness <R v, w> = <v, P w> and R P = I
+    Pw = oracle_mod.prolong_add(d, w, np.zeros(v.size))
+    assert np.isclose(oracle_mod.inject(d, v) @ w, v @ Pw, rtol=1e-14)
+    assert np.array_equal(oracle_mod.inject(d, Pw), w)
+
+
+@pytest.mark.parametrize("d", [(8, 8, 8), (4, 6, 10)])
+def test_fused_restriction_equals_unfused(oracle_mod, d):
+    r = inputs.uniform(d, 30)
+    z = inputs.uniform(d, 31)
+    fused = oracle_mod.restrict_fused(d, r, z)
+    unfused = oracle_mod.inject(d, r - oracle_mod.spmv(d, z))
+    assert np.array_equal(fused, unfused)
+    K = refimpl.kron_matrix(d, 0.5)
+    assert np.allclose(fused, refimpl.injection_matrix(d) @ (r - K @ z), rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------------------ V-cycle --
+@pytest.mark.parametrize("d,levels", [((8, 8, 8), 1), ((8, 8, 8), 2), ((16, 16, 16), 3),
+                                      ((8, 12, 16), 3), ((16, 16, 16), 4)])
+@pytest.mark.parametrize("sweep", [0, 2])
+def test_vcycle_equals_composed_reference(oracle_mod, d, levels, sweep):
+    r = inputs.uniform(d, 40)
+    ref = refimpl.vcycle_ref(d, r, levels, 1, 1, 1, sweep)
+    got = oracle_mod.vcycle(d, r, levels, 1, 1, 1, sweep)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_vcycle_sweep_counts(oracle_mod):
+    d = (8, 8, 8)
+    r = inputs.uniform(d, 41)
+    ref = refimpl.vcycle_ref(d, r, 3, 2, 3, 2, 0)
+    got = oracle_mod.vcycle(d, r, 3, 2, 3, 2, 0)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_vcycle_is_linear(oracle_mod):
+    d = (16, 16, 16)
+    u, v = inputs.uniform(d, 42), inputs.uniform(d, 43)
+    a, b = 0.75, -2.5
+    lhs = oracle_mod.vcycle(d, a * u + b * v, 3)
+    rhs = a * oracle_mod.vcycle(d, u, 3) + b * oracle_mod.vcycle(d, v, 3)
+    assert np.linalg.norm(lhs - rhs) <= 1e-13 * np.linalg.norm(rhs)
+
+
+def test_colour_order_keeps_coarse_correction(oracle_mod):
+    """With the injection colour relaxed fifth, the restricted residual after
+    pre-smoothing is nonzero and the coarse correction survives the
+    post-smoother (both fail if that colour is placed first or last)."""
+    d = (16, 16, 16)
+    r = inputs.uniform(d, 44)
+    z = oracle_mod.gs(d, r, np.zeros(r.size), 0)
+    rc = oracle_mod.restrict_fused(d, r, z)
+    assert np.linalg.norm(rc) > 1e-3 * np.linalg.norm(r)
+    with_coarse = oracle_mod.vcycle(d, r, 2)
+    no_coarse = oracle_mod.gs(d, r, z, 0)   # the same cycle with a zero correction
+    assert np.linalg.norm(with_coarse - no_coarse) > 1e-3 * np.linalg.norm(with_coarse)
+
+
+# ------------------------------------------------------------------- GMRES --
+@pytest.mark.parametrize("d,levels", [((4, 4, 4), 2), ((8, 8, 8), 3), ((16, 16, 16), 3), ((6, 8, 10), 2)])
+def test_solve_matches_dense_lu(oracle_mod, d, levels):
+    A = refimpl.kron_matrix(d, 0.5).toarray()
+    b = inputs.uniform(d, 50)
+    xs = np.linalg.solve(A, b)
+    x, st = oracle_mod.gmres_ir(d, b, levels=levels, sweep=0, restart=30, tol=1e-12)
+    assert st.converged and st.final_rel_res < 1e-12
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("sweep", [0, 2])
+def test_solve_all_ones_closed_form(oracle_mod, sweep):
+    d = (16, 16, 16)
+    b = oracle_mod.spmv(d, inputs.ones(d))
+    x, st = oracle_mod.gmres_ir(d, b, levels=3, sweep=sweep, tol=1e-11)
+    assert st.converged
+    assert np.linalg.norm(x - 1.0) / np.sqrt(x.size) < 1e-9
+
+
+def test_arnoldi_relation_and_orthogonality(oracle_mod):
+    d = (8, 8, 8)
+    b = inputs.uniform(d, 51)
+    _, st, cyc = oracle_mod.gmres_ir(d, b, levels=3, restart=6, max_iters=6, tol=0.0,
+                                     want_first_cycle=True)
+    k, Q, Hbar = cyc["k"], cyc["Q"], cyc["Hbar"]
+    assert k == 6 and Q.shape == (b.size, k + 1) and Hbar.shape == (k + 1, k)
+    K = refimpl.kron_matrix(d, 0.5)
+    MQ = np.column_stack([refimpl.vcycle_ref(d, Q[:, j], 3) for j in range(k)])
+    lhs = K @ MQ
+    assert np.linalg.norm(lhs - Q @ Hbar) <= 1e-13 * np.linalg.norm(Hbar)
+    assert np.linalg.norm(Q.T @ Q - np.eye(k + 1)) <= 1e-14 * (k + 1)
+    assert np.allclose(Q[:, 0], b / np.linalg.norm(b), rtol=0, atol=1e-15)
+
+
+def test_givens_solution_equals_least_squares(oracle_mod):
+    d = (8, 8, 8)
+    b = inputs.uniform(d, 52)
+    _, st, cyc = oracle_mod.gmres_ir(d, b, levels=3, restart=8, max_iters=8, tol=0.0,
+                                     want_first_cycle=True)
+    k, Hbar, y = cyc["k"], cyc["Hbar"], cyc["y"]
+    rhs = np.zeros(k + 1)
+    rhs[0] = np.linalg.norm(b)
+    ys, *_ = np.linalg.lstsq(Hbar, rhs, rcond=None)
+    assert np.linalg.norm(y - ys) <= 1e-10 * np.linalg.norm(ys)
+    # the Givens estimate equals the least-squares residual norm
+    res = np.linalg.norm(Hbar @ ys - rhs) / rhs[0]
+    assert np.isclose(st.est_rel_res, res, rtol=1e-8)
+
+
+def test_estimate_equals_true_residual_without_restart(oracle_mod):
+    d = (8, 8, 8)
+    b = inputs.uniform(d, 53)
+    x, st = oracle_mod.gmres_ir(d, b, levels=3, restart=40, tol=1e-10)
+    assert st.converged and st.restarts == 1
+    assert abs(st.est_rel_res - st.final_rel_res) <= 1e-12
+
+
+@pytest.mark.parametrize("d", [(2, 2, 2), (3, 3, 3), (2, 3, 4)])
+def test_unpreconditioned_finite_termination(oracle_mod, d):
+    n = int(np.prod(d))
+    b = inputs.uniform(d, 54)
+    x, st = oracle_mod.gmres_ir(d, b, levels=0, restart=n, max_iters=n, tol=1e-12)
+    assert st.converged and st.iters <= n
+    A = refimpl.kron_matrix(d, 0.5).toarray()
+    assert np.linalg.norm(A @ x - b) <= 1e-11 * np.linalg.norm(b)
+
+
+def test_restarts_and_fp32_emulation(oracle_mod):
+    d = (16, 16, 16)
+    b = oracle_mod.spmv(d, inputs.ones(d))
+    x5, st5 = oracle_mod.gmres_ir(d, b, levels=3, restart=5, tol=1e-9)
+    assert st5.converged and st5.restarts >= 3 and st5.final_rel_res < 1e-9
+    x32, st32 = oracle_mod.gmres_ir(d, b, levels=3, sweep=2, tol=1e-9, f32=True)
+    assert st32.converged and st32.final_rel_res < 1e-9
+    assert np.linalg.norm(x32 - 1) / np.sqrt(x32.size) < 1e-8
+
+
+def test_edge_cases(oracle_mod):
+    d = (8, 8, 8)
+    x, st = oracle_mod.gmres_ir(d, np.zeros(512), levels=3)
+    assert st.converged and st.iters == 0 and np.all(x == 0)
+    b = oracle_mod.spmv(d, inputs.ones(d))
+    x, st = oracle_mod.gmres_ir(d, b, levels=3, max_iters=3, tol=1e-9)
+    assert not st.converged and st.iters == 3
+    b[5] = np.nan
+    with pytest.raises(RuntimeError):
+        oracle_mod.gmres_ir(d, b, levels=3)
+
+
+def test_random_start_same_solution(oracle_mod):
+    d = (16, 16, 16)
+    b = oracle_mod.spmv(d, inputs.ones(d))
+    x, st = oracle_mod.gmres_ir(d, b, x0=inputs.random_x0(d), levels=3, tol=1e-11)
+    assert st.converged
+    assert np.linalg.norm(x - 1.0) / np.sqrt(x.size) < 1e-9
