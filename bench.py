@@ -1,0 +1,268 @@
+#!/usr/bin/env python3
+"""HPG-MxP-style benchmark of the MI355X GMRES-IR / multigrid hot path.
+
+Workload: one GPU's full share of the paper's runs (Table 1): a 320^3 grid,
+nonsymmetric 27-point stencil (beta = 0.5), b = A 1, x0 = 0, GMRES(30),
+4-level V-cycle with one forward multicolour Gauss-Seidel sweep before and
+after the coarse-grid correction and one on the coarsest grid, tolerance
+1e-9, at most 300 inner steps per timed solve.
+
+Phases (Sec. 3 "The HPG-MxP benchmark"):
+  1. validation: FP64 GMRES to a 1e-9 relative residual gives n_d, the
+     FP32-inner GMRES-IR to the same tolerance gives n_ir;
+  2. timed mixed-precision phase: `--steps` solves of 300 inner steps each
+     (one step = one solve), after `--warmup` untimed ones;
+  3. timed FP64 phase, same shape;
+  4. one profiled solve (HIP events around every launch) for per-kernel
+     HBM bandwidth, a streaming-copy bandwidth reference, and the CPU oracle
+     timed on a bounded sample of the same workload.
+`value` = flops(model) / time of the mixed-precision solves x min(1, n_d/n_ir).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MxP vs FP64 GMRES-MG GFLOP/s at 1e-9 rel. residual; kernel HBM GB/s"
+PEAK_HBM_GBPS = 8000.0
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=320, help="grid edge (the workload is n^3)")
+    ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--iters", type=int, default=300, help="inner steps per timed solve")
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--cpu-iters", type=int, default=2, help="inner steps of the CPU-oracle sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-validation", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
+    """Algorithmic bytes per (kernel id, level) over one solve with the given cycles."""
+    from collections import defaultdict
+    B = defaultdict(float)
+    L = pm.level_dims(cfg.dims, cfg.levels)
+
+    def vcyc():
+        for l, d in enumerate(L):
+            rows = pm.nrows(d)
+            coarsest = l == cfg.levels - 1
+            nsweeps_zero = 1 if (cfg.coarsest if coarsest else cfg.pre) > 0 else 0
+            for c in range(8):
+                cr = rows // 8  # even dims on every level but possibly the coarsest
+                B[(hp.K_GS_ZERO, l)] += nsweeps_zero * pm.gs_colour_bytes(
+                    cr, pm.zero_guess_active_slots(c), dtype)
+            full = (cfg.coarsest - 1) if coarsest else (cfg.pre - 1 + cfg.post)
+            B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.gs_colour_bytes(rows // 8, pm.SLOTS, dtype)
+            if not coarsest:
+                rc = pm.nrows(L[l + 1])
+                B[(hp.K_RESTRICT, l)] += pm.restrict_bytes(rc, dtype)
+                B[(hp.K_PROLONG, l)] += pm.prolong_bytes(rc, dtype)
+
+    N = pm.nrows(cfg.dims)
+    w = pm.wb(dtype)
+    for kk in cycles:
+        B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
+        B[(hp.K_CAST, 0)] += N * (8 + w)
+        for k in range(kk):
+            vcyc()
+            B[(hp.K_SPMV_DOT, 0)] += pm.spmv_dot_bytes(N, k + 1, dtype)
+            B[(hp.K_CGS_DOT, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_NORMALIZE, 0)] += 2 * N * w
+        B[(hp.K_GEMV, 0)] += N * (kk + 1) * w
+        vcyc()
+        B[(hp.K_UPDATE, 0)] += N * (16 + w)
+    B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
+    B[(hp.K_PERMUTE, 0)] += 3 * 2 * N * 8
+    return B
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in ("stencil_kernels.hip", "krylov_kernels.hip", "api.hip", "hpgmx_internal.hpp"):
+        with open(os.path.join(ROOT, "paper_2507_11512_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_name, per_launch_bytes):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+    except Exception:
+        return None
+    if t.get("source_sha") != source_sha():
+        return None
+    k = t.get("kernels", {}).get(kernel_name)
+    if not k:
+        return None
+    return k.get("hbm_bytes_per_launch")
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2507_11512_amd import hpgmx as hp
+    from paper_2507_11512_amd import perfmodel as pm
+
+    torch.cuda.set_device(0)
+    n, L, m = args.n, args.levels, args.restart
+    cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=0, restart=m)
+    N = n ** 3
+    log(f"setup {n}^3 levels={L} (device: {torch.cuda.get_device_name(0)})")
+    t = time.time()
+    P = hp.Problem(n, beta=0.5, levels=L, sweep="forward")
+    b = P.rhs_from_x(torch.ones(N, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    log(f"setup done in {time.time() - t:.2f}s")
+
+    # ---- 1. validation ---------------------------------------------------------------
+    n_d = n_ir = None
+    val = {}
+    if not args.no_validation:
+        for prec in ("fp64", "mxp"):
+            x, st = P.solve(b, tol=1e-9, restart=m, max_iters=10000, precision=prec)
+            err = (x - 1.0).norm().item() / (N ** 0.5)
+            val[prec] = {"iters": st.iters, "restarts": st.restarts, "converged": st.converged,
+                         "final_rel_res": st.final_rel_res, "time_to_1e-9_s": st.solve_ms / 1e3,
+                         "x_err_vs_ones": err}
+            log(f"validation {prec}: iters={st.iters} res={st.final_rel_res:.3e} "
+                f"|x-1|/|1|={err:.3e} time={st.solve_ms / 1e3:.3f}s")
+        n_d, n_ir = val["fp64"]["iters"], val["mxp"]["iters"]
+    penalty = min(1.0, n_d / n_ir) if n_d and n_ir else 1.0
+
+    # ---- 2./3. timed phases ------------------------------------------------------------------
+    cycles = pm.fixed_iteration_cycles(args.iters, m)
+    flops = pm.solve_flops(cfg, cycles)
+    res = {}
+    for prec in ("mxp", "fp64"):
+        for _ in range(args.warmup):
+            P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec)
+            assert st.iters == args.iters
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[prec] = {"s_per_solve": dt, "gflops_raw": flops / dt / 1e9, "rel_res_after": st.final_rel_res}
+        log(f"timed {prec}: {dt * 1e3:.1f} ms/solve ({args.iters} iters) -> "
+            f"{flops / dt / 1e9:.1f} GFLOP/s raw")
+    value = res["mxp"]["gflops_raw"] * penalty
+    fp64_gflops = res["fp64"]["gflops_raw"]
+
+    # ---- 4a. per-kernel profile (HIP events around each launch) ---------------------------
+    kernels = {}
+    dominant = None
+    for prec, dt_code in (("mxp", hp.F32), ("fp64", hp.F64)):
+        _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec, profile=True)
+        B = kernel_bytes_table(cfg, cycles, dt_code, hp, pm)
+        for (kid, lvl), nbytes in sorted(B.items()):
+            ms, cnt = hp.profile_get(P.h, kid, lvl)
+            if cnt == 0 or ms <= 0:
+                continue
+            name = f"{hp.KERNEL_NAMES[kid]}_l{lvl}_{prec}"
+            gbps = nbytes / (ms / 1e3) / 1e9
+            kernels[name] = {"launches": cnt, "total_ms": round(ms, 4), "avg_us": round(ms / cnt * 1e3, 3),
+                             "bytes_per_launch": nbytes / cnt, "GBps": round(gbps, 1),
+                             "frac_peak": round(gbps / PEAK_HBM_GBPS, 4)}
+        log(f"profiled {prec} solve: {st.solve_ms:.1f} ms with events")
+    mxp_k = {k: v for k, v in kernels.items() if k.endswith("_mxp")}
+    dom_name = max(mxp_k, key=lambda k: mxp_k[k]["total_ms"])
+    dominant = mxp_k[dom_name]
+    for k, v in sorted(mxp_k.items(), key=lambda kv: -kv[1]["total_ms"])[:8]:
+        log(f"  {k:24s} {v['total_ms']:9.2f} ms  {v['launches']:6d} launches  {v['GBps']:7.1f} GB/s")
+
+    # ---- 4b. streaming copy reference ---------------------------------------------------------
+    nbytes = 1 << 31
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    cms = hp.stream_copy(P.h, src, dst, nbytes, reps=10)
+    copy_gbps = 2 * nbytes / (cms / 1e3) / 1e9
+    del src, dst
+    log(f"stream copy: {copy_gbps:.1f} GB/s (read+write)")
+
+    # ---- 4c. CPU oracle on a bounded sample ------------------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        bh = oracle.spmv(n, np.ones(N))
+        t0 = time.perf_counter()
+        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0)
+        dt = time.perf_counter() - t0
+        cflops = pm.solve_flops(cfg, [args.cpu_iters])
+        cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{n}^3 FP64 oracle, one GMRES({m}) cycle cut at {args.cpu_iters} inner steps "
+                         f"(2 outer residuals, {args.cpu_iters} V-cycle+SpMV+CGS2 steps, end-of-cycle "
+                         f"V-cycle), {dt:.1f} s wall"}
+        log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
+
+    dom_kid = dom_name.rsplit("_", 2)[0]
+    traffic = load_traffic(dom_name, dominant["bytes_per_launch"])
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["mxp"]["s_per_solve"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": "synthetic: generated 27-point stencil, b = A*1, x0 = 0",
+        "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta=0.5, GMRES({m})-IR, {L}-level "
+                               f"V-cycle fwd multicolour GS 1/1/1, {args.iters} inner steps per solve",
+                   "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L,
+                   "iters_per_solve": args.iters},
+        "fp64_gflops": round(fp64_gflops, 2),
+        "speedup_vs_fp64": round(value / fp64_gflops, 4),
+        "raw_speedup_vs_fp64": round(res["mxp"]["gflops_raw"] / fp64_gflops, 4),
+        "penalty": round(penalty, 4),
+        "n_d": n_d, "n_ir": n_ir,
+        "validation": val,
+        "fp64_ms_per_step": round(res["fp64"]["s_per_solve"] * 1e3, 3),
+        "flops_per_solve": flops,
+        "roofline": {"bound": "hbm", "kernel": dom_name,
+                     "achieved": dominant["GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+                     "frac": dominant["frac_peak"],
+                     "bytes_per_launch": dominant["bytes_per_launch"], "avg_us": dominant["avg_us"],
+                     "traffic": traffic, "copy_GBps": round(copy_gbps, 1)},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    del dom_kid
+    P.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,209 @@
+/*
+ * hpgmx.h -- C ABI of the MI355X (gfx950) HPG-MxP hot path: restarted,
+ * right-preconditioned GMRES with iterative refinement (GMRES-IR, CGS2
+ * orthogonalisation, Givens least squares) and a geometric-multigrid V-cycle
+ * (multicolour Gauss-Seidel smoother, injection restriction fused with the
+ * residual, prolongation P = R^T) on a nonsymmetric 27-point stencil.
+ *
+ * Paper: Kashi et al., "Scaling the memory wall using mixed-precision --
+ * HPG-MxP on an exascale machine", SC'25, arXiv 2507.11512.  Section
+ * references below are to that paper.
+ *
+ * Conventions shared by every entry point
+ *  - All vector arguments are DEVICE pointers to contiguous arrays in the
+ *    natural lexicographic order I = i + nx*(j + ny*k) of the level they
+ *    belong to (0-based, i fastest).  The library's internal colour-blocked
+ *    ordering is never visible through the ABI.
+ *  - Vectors are float64 for HPGMX_F64 and float32 for HPGMX_F32, HPGMX_F16
+ *    and HPGMX_BF16 (the 16-bit types describe how the matrix is stored; the
+ *    vectors stay float32).
+ *  - The caller owns every pointer it passes.  The library owns its
+ *    matrices, hierarchy and Krylov workspace: they live in memory the caller
+ *    bound with hpgmx_bind_workspace, or else in memory the library
+ *    allocates itself and frees in hpgmx_destroy.
+ *  - Work is enqueued on the HIP stream given to hpgmx_setup_problem.
+ *    hpgmx_spmv, hpgmx_smooth, hpgmx_vcycle, hpgmx_restrict_residual,
+ *    hpgmx_prolong_add and hpgmx_rhs_from_x are stream-ordered and return
+ *    before the work finishes.  hpgmx_gmres_ir_solve returns after the solve
+ *    has finished, because it reads the residual estimate every iteration.
+ *  - Errors are returned, never thrown: a negative hpgmx_status.  EINVAL
+ *    (bad argument) leaves the handle usable.  EHIP (a HIP runtime error)
+ *    poisons the handle: every later call except hpgmx_last_error and
+ *    hpgmx_destroy returns ESTATE.  hpgmx_last_error gives a message.
+ *  - A solve that does not reach the tolerance within max_iters is not an
+ *    error: it returns HPGMX_OK with stats->converged = 0.
+ *  - One handle must not be used from two host threads at once.
+ */
+#ifndef HPGMX_H
+#define HPGMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hpgmx_ctx *hpgmx_handle;
+
+typedef enum {
+    HPGMX_OK = 0,
+    HPGMX_EINVAL = -1,     /* invalid argument; the handle stays usable      */
+    HPGMX_ENOMEM = -2,     /* device memory or bound workspace exhausted      */
+    HPGMX_EHIP = -3,       /* HIP runtime error; the handle is poisoned       */
+    HPGMX_ESTATE = -4,     /* call out of order, or handle poisoned           */
+    HPGMX_ENONFINITE = -5  /* NaN or Inf in the right-hand side or residual  */
+} hpgmx_status;
+
+typedef enum { HPGMX_F64 = 0, HPGMX_F32 = 1, HPGMX_F16 = 2, HPGMX_BF16 = 3 } hpgmx_dtype;
+
+typedef enum {
+    HPGMX_GS_FORWARD = 0,   /* colours 0..7: the smoother of Sec. 3           */
+    HPGMX_GS_BACKWARD = 1,  /* colours 7..0                                    */
+    HPGMX_GS_SYMMETRIC = 2  /* forward then backward, eqs. (1)-(2) (Sec. 2)    */
+} hpgmx_sweep;
+
+/* The operator (Sec. 2, Sec. 3): 27-point stencil on an nx*ny*nz grid with
+ * Dirichlet truncation at the boundary; diagonal 26, off-diagonal -1, except
+ * that every entry coupling to an x-neighbour at i-1 is -1-beta and at i+1 is
+ * -1+beta (beta = 0 is the symmetric matrix of Sec. 3). */
+typedef struct {
+    int nx, ny, nz;
+    double beta;
+} hpgmx_problem_desc;
+
+/* The V-cycle (Sec. 2 Fig. 1 applied recursively; Sec. 3): `levels` grids,
+ * each coarser one half the size in every dimension (coarse point (I,J,K) is
+ * fine point (2I,2J,2K)); pre/post smoothing sweeps on every level but the
+ * coarsest, which gets coarsest_sweeps sweeps; `sweep` is an hpgmx_sweep.
+ * Every dimension must be divisible by 2^(levels-1) and the coarsest level
+ * must be at least 2 in every dimension.  1 <= levels <= 8. */
+typedef struct {
+    int levels, pre_sweeps, post_sweeps, coarsest_sweeps;
+    int sweep;
+} hpgmx_mg_desc;
+
+/* Solve flags. */
+#define HPGMX_SOLVE_PROFILE 1  /* time every kernel launch with HIP events   */
+
+/* Alg. 3 parameters.  restart = m (1..63), max_iters counts inner steps over
+ * all restarts, tol is the relative residual ||b - A x|| / ||b|| to reach
+ * (strict "<").  inner_dtype selects the precision of the steps Alg. 3
+ * allows in low precision: HPGMX_F64 gives the plain FP64 GMRES-MG,
+ * HPGMX_F32 the FP32-inner GMRES-IR, HPGMX_F16 / HPGMX_BF16 the FP32-inner
+ * solver with the multigrid matrices stored in 16 bits.  The outer residual
+ * and the solution update are always FP64.  If res_hist_host is not NULL the
+ * estimated relative residual after each inner step is written there (host
+ * memory, res_hist_len entries at most). */
+typedef struct {
+    int restart, max_iters;
+    double tol;
+    int inner_dtype;
+    double *res_hist_host;
+    int res_hist_len;
+    int flags;
+} hpgmx_solve_desc;
+
+typedef struct {
+    int iters;          /* inner steps, summed over restarts                 */
+    int restarts;       /* completed restart cycles                          */
+    int converged;      /* final relative residual < tol                     */
+    int breakdown;      /* a new Krylov vector had norm <= 1e-300            */
+    double rho0;        /* ||b||                                             */
+    double final_rel_res; /* ||b - A x|| / ||b|| in FP64 at exit             */
+    double est_rel_res; /* last Givens estimate |t_{k+1}| / ||b||             */
+    double solve_ms;    /* device time of the whole solve (HIP events)       */
+} hpgmx_solve_stats;
+
+/* Creates a handle for one problem on the current HIP device.  hip_stream
+ * is a hipStream_t (NULL = the null stream); the library enqueues all of its
+ * work there.  No device memory is touched until hpgmx_mg_setup. */
+hpgmx_status hpgmx_setup_problem(const hpgmx_problem_desc *desc, void *hip_stream,
+                                 hpgmx_handle *out);
+
+/* Device bytes the hierarchy of `mg` plus the Krylov workspace for a
+ * restart length `restart` need, for every inner dtype whose bit
+ * (1 << hpgmx_dtype) is set in dtype_mask. */
+hpgmx_status hpgmx_workspace_bytes(hpgmx_handle h, const hpgmx_mg_desc *mg, int restart,
+                                   unsigned dtype_mask, size_t *bytes);
+
+/* Hands the library a caller-owned device region (e.g. a torch tensor) to
+ * carve all of its buffers from.  Must precede hpgmx_mg_setup; the region
+ * must stay alive until hpgmx_destroy.  Without it the library allocates. */
+hpgmx_status hpgmx_bind_workspace(hpgmx_handle h, void *dev_ptr, size_t bytes);
+
+/* Builds the multigrid hierarchy on the device: for every level the ELL
+ * matrix (26 off-diagonal slots of values and int32 column indices plus the
+ * diagonal, Sec. 3.2 "ELLPACK matrix format") in FP64, FP32, FP16 and BF16
+ * values, in the colour-blocked order of the multicolour smoother
+ * (Sec. 3.2).  Blocks until done. */
+hpgmx_status hpgmx_mg_setup(hpgmx_handle h, const hpgmx_mg_desc *mg);
+
+/* Alg. 3.  b: FP64 right-hand side (device, natural order, N = nx*ny*nz).
+ * x: FP64 initial guess on entry, solution on exit.  stats may be NULL.
+ * Returns ENONFINITE if b or an outer residual is not finite. */
+hpgmx_status hpgmx_gmres_ir_solve(hpgmx_handle h, const double *b, double *x,
+                                  const hpgmx_solve_desc *desc, hpgmx_solve_stats *stats);
+
+/* y = A_level x with the level's matrix stored in `dtype` (the SpMV of
+ * Alg. 3).  x and y must not overlap. */
+hpgmx_status hpgmx_spmv(hpgmx_handle h, int level, int dtype, const void *x, void *y);
+
+/* One Gauss-Seidel sweep of kind `sweep` (an hpgmx_sweep) for A_level z = r,
+ * in place on z (relaxation form of eq. (1), multicolour order of Sec. 3.2).
+ * zero_guess != 0 treats z as zero on entry (its contents are ignored). */
+hpgmx_status hpgmx_smooth(hpgmx_handle h, int level, int dtype, int sweep, const void *r,
+                          void *z, int zero_guess);
+
+/* z = M^{-1} r: one V-cycle from z = 0 on level 0 (Sec. 2 Fig. 1, Sec. 3). */
+hpgmx_status hpgmx_vcycle(hpgmx_handle h, int dtype, const void *r, void *z);
+
+/* r_coarse = R (r - A_level z): the fused residual-restriction of eq. (6),
+ * evaluated only at the coarse points.  r, z on `level`, r_coarse on
+ * level + 1 (level < levels - 1). */
+hpgmx_status hpgmx_restrict_residual(hpgmx_handle h, int level, int dtype, const void *r,
+                                     const void *z, void *r_coarse);
+
+/* z += P z_coarse with P = R^T (eq. (3)): z on `level`, z_coarse on
+ * level + 1. */
+hpgmx_status hpgmx_prolong_add(hpgmx_handle h, int level, int dtype, const void *z_coarse,
+                               void *z);
+
+/* b = A x on level 0 in FP64 (device, natural order). */
+hpgmx_status hpgmx_rhs_from_x(hpgmx_handle h, const double *x, double *b);
+
+/* Per-kernel timing of the last solve run with HPGMX_SOLVE_PROFILE.
+ * Kernel ids are HPGMX_K_*; `level` selects the grid for the per-level
+ * kernels (ignored otherwise).  Returns the summed device time in ms and the
+ * number of launches. */
+#define HPGMX_K_GS 0           /* one colour of a Gauss-Seidel sweep          */
+#define HPGMX_K_GS_ZERO 1      /* one colour of a sweep from a zero guess     */
+#define HPGMX_K_RESTRICT 2     /* fused residual-restriction                  */
+#define HPGMX_K_PROLONG 3      /* prolongation-correction                    */
+#define HPGMX_K_SPMV_DOT 4     /* w = A z fused with h1 = Q^T w               */
+#define HPGMX_K_CGS_DOT 5      /* w -= Q h1 fused with h2 = Q^T w             */
+#define HPGMX_K_CGS_NORM 6     /* w -= Q h2 fused with ||w||^2 and Givens     */
+#define HPGMX_K_NORMALIZE 7    /* q_{k+1} = w / ||w||                         */
+#define HPGMX_K_RESID64 8      /* r = b - A x in FP64 with ||r||^2            */
+#define HPGMX_K_CAST 9         /* q_1 = r / rho (cast to the inner dtype)      */
+#define HPGMX_K_TRSM 10        /* y = H^{-1} t                                */
+#define HPGMX_K_GEMV 11        /* u = Q y                                      */
+#define HPGMX_K_UPDATE 12      /* x += z in FP64                              */
+#define HPGMX_K_PERMUTE 13     /* natural <-> colour-blocked order            */
+#define HPGMX_K_COUNT 14
+hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *total_ms,
+                               long long *launches);
+
+/* Streaming copy of `bytes` (multiple of 16) from src to dst, `reps` times,
+ * timed with HIP events: the measured-bandwidth reference for the roofline
+ * and the scale for hardware byte counters.  Blocks; *ms = average per copy. */
+hpgmx_status hpgmx_stream_copy(hpgmx_handle h, const void *src, void *dst, size_t bytes,
+                               int reps, double *ms);
+
+hpgmx_status hpgmx_destroy(hpgmx_handle h);
+const char *hpgmx_last_error(hpgmx_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPGMX_H */

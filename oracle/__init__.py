@@ -6,6 +6,6 @@ the ``cpu_baseline`` leg of ``bench.py`` may import this package; the product
 library never does, and the two share no code.
 """
 from .oracle import (  # noqa: F401
-    Stats, absrow, build_lib, color, gmres_ir, gs, inject, load, prolong_add,
+    Stats, absrow, build_lib, color, gmres_ir, gs, inject, load, num_threads, prolong_add,
     restrict_fused, spmv, spmv_rows, vcycle,
 )

@@ -21,11 +21,15 @@
  * products, scipy triangular solves, dense LU, lstsq, closed forms).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 typedef int64_t idx_t;
+
+/* Threads the OpenMP loops of this library use. */
+int or_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------- */
 /* Problem definition: the 27-point stencil (Sec. 2 "Background": 27 nonzeros */

@@ -50,6 +50,8 @@ def load():
         build_lib()
     lib = C.CDLL(_LIB_PATH)
     i, d = C.c_int, C.c_double
+    lib.or_num_threads.argtypes = []
+    lib.or_num_threads.restype = i
     lib.or_coef.argtypes = [d, i, i, i, i]
     lib.or_coef.restype = d
     lib.or_spmv.argtypes = [i, i, i, d, i, _dp, _dp]
@@ -102,6 +104,10 @@ def absrow(dims, x, beta=0.5, faces_only=False):
     y = np.empty(nx * ny * nz)
     load().or_absrow(nx, ny, nz, beta, int(faces_only), _f64(x), y)
     return y
+
+
+def num_threads():
+    return load().or_num_threads()
 
 
 def color(i, j, k):

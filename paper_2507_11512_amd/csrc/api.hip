@@ -1,0 +1,833 @@
+// C ABI of hpgmx: handle lifecycle, device memory, the V-cycle and the
+// GMRES-IR driver (Alg. 3).  The host side only sequences kernels on the
+// handle's stream; all arithmetic runs on the device.
+#include "hpgmx_internal.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+using namespace hpgmx;
+
+namespace {
+
+struct Error {
+    hpgmx_status st;
+    std::string msg;
+};
+
+[[noreturn]] void fail(hpgmx_status st, const std::string &m) { throw Error{st, m}; }
+
+void hip_check(hipError_t e, const char *what)
+{
+    if (e != hipSuccess) fail(HPGMX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+inline size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
+
+struct Level {
+    Matrix A;
+    void *r[2] = {nullptr, nullptr};  // work vectors, [0] double, [1] float (levels >= 1)
+    void *z[2] = {nullptr, nullptr};
+};
+
+struct Krylov {
+    int m = 0;
+    void *Q = nullptr;  // (m + 1) columns of N
+    void *z = nullptr;
+    void *u = nullptr;
+};
+
+inline int vt_of(Prec p) { return p == P64 ? 0 : 1; }
+
+}  // namespace
+
+struct hpgmx_ctx {
+    hpgmx_problem_desc prob{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool mg_ready = false;
+    bool poisoned = false;
+    hpgmx_mg_desc mg{};
+    std::vector<Level> lv;
+
+    // memory: bound workspace (bump allocation) or owned hipMalloc blocks
+    char *ws_base = nullptr;
+    size_t ws_size = 0, ws_used = 0;
+    std::vector<void *> owned;
+
+    Krylov kry[4];
+    double *b_int = nullptr, *x_int = nullptr, *r64 = nullptr;
+    double *partials = nullptr;
+    Ctrl *ctrl = nullptr;
+    double *host_scal = nullptr;   // pinned copy of the Ctrl scalar block
+    void *tmp[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+
+    // profiling
+    bool prof = false;
+    struct Ev {
+        hipEvent_t a, b;
+        int kernel, level;
+    };
+    std::vector<Ev> evpool;
+    size_t evused = 0;
+    double prof_ms[HPGMX_K_COUNT][kMaxLevels] = {};
+    long long prof_n[HPGMX_K_COUNT][kMaxLevels] = {};
+
+    std::string err;
+
+    void *dalloc(size_t bytes)
+    {
+        bytes = round_up(bytes ? bytes : 1);
+        if (ws_base) {
+            if (ws_used + bytes > ws_size)
+                fail(HPGMX_ENOMEM, "bound workspace exhausted (need " + std::to_string(ws_used + bytes) +
+                                       " bytes, have " + std::to_string(ws_size) + ")");
+            void *p = ws_base + ws_used;
+            ws_used += bytes;
+            return p;
+        }
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            fail(HPGMX_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+        }
+        owned.push_back(p);
+        return p;
+    }
+
+    // profiling scopes around single launches
+    void prof_begin(int kernel, int level)
+    {
+        if (!prof) return;
+        if (evused == evpool.size()) {
+            Ev e{};
+            hip_check(hipEventCreate(&e.a), "hipEventCreate");
+            hip_check(hipEventCreate(&e.b), "hipEventCreate");
+            evpool.push_back(e);
+        }
+        Ev &e = evpool[evused];
+        e.kernel = kernel;
+        e.level = level;
+        hip_check(hipEventRecord(e.a, stream), "hipEventRecord");
+    }
+    void prof_end()
+    {
+        if (!prof) return;
+        hip_check(hipEventRecord(evpool[evused].b, stream), "hipEventRecord");
+        ++evused;
+    }
+    void prof_collect()
+    {
+        hip_check(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        for (size_t i = 0; i < evused; ++i) {
+            float ms = 0.f;
+            hip_check(hipEventElapsedTime(&ms, evpool[i].a, evpool[i].b), "hipEventElapsedTime");
+            prof_ms[evpool[i].kernel][evpool[i].level] += ms;
+            prof_n[evpool[i].kernel][evpool[i].level] += 1;
+        }
+        evused = 0;
+    }
+};
+
+namespace {
+
+struct ProfScope {
+    hpgmx_ctx *c;
+    ProfScope(hpgmx_ctx *c_, int k, int l) : c(c_) { c->prof_begin(k, l); }
+    ~ProfScope() { c->prof_end(); }
+};
+
+// ---- allocation plan ---------------------------------------------------------------------
+void alloc_matrix_prec(hpgmx_ctx *c, Matrix &A, Prec p)
+{
+    const size_t N = (size_t)A.g.N;
+    switch (p) {
+    case P64:
+        if (!A.v64) { A.v64 = (double *)c->dalloc(kSlots * N * 8); A.d64 = (double *)c->dalloc(N * 8); }
+        break;
+    case P32:
+        if (!A.v32) { A.v32 = (float *)c->dalloc(kSlots * N * 4); A.d32 = (float *)c->dalloc(N * 4); }
+        break;
+    case P16:
+        if (!A.v16) { A.v16 = (__half *)c->dalloc(kSlots * N * 2); A.d16 = (__half *)c->dalloc(N * 2); }
+        break;
+    case PB16:
+        if (!A.vb16) { A.vb16 = (bf16 *)c->dalloc(kSlots * N * 2); A.db16 = (bf16 *)c->dalloc(N * 2); }
+        break;
+    }
+}
+
+bool has_prec(const Matrix &A, Prec p)
+{
+    switch (p) {
+    case P64: return A.v64 != nullptr;
+    case P32: return A.v32 != nullptr;
+    case P16: return A.v16 != nullptr;
+    case PB16: return A.vb16 != nullptr;
+    }
+    return false;
+}
+
+// Generates the values of precision p on every level (and the columns once).
+void ensure_prec(hpgmx_ctx *c, Prec p)
+{
+    for (auto &L : c->lv) {
+        if (has_prec(L.A, p)) continue;
+        alloc_matrix_prec(c, L.A, p);
+        Matrix only = L.A;  // generate just this precision (and nothing else)
+        only.col = nullptr;
+        if (p != P64) only.v64 = nullptr, only.d64 = nullptr;
+        if (p != P32) only.v32 = nullptr, only.d32 = nullptr;
+        if (p != P16) only.v16 = nullptr, only.d16 = nullptr;
+        if (p != PB16) only.vb16 = nullptr, only.db16 = nullptr;
+        launch_generate(only, c->prob.beta, c->stream);
+    }
+}
+
+void ensure_level_vectors(hpgmx_ctx *c, Prec p)
+{
+    const int vt = vt_of(p);
+    for (size_t l = 1; l < c->lv.size(); ++l) {
+        Level &L = c->lv[l];
+        if (!L.r[vt]) {
+            L.r[vt] = c->dalloc((size_t)L.A.g.N * vec_bytes(p));
+            L.z[vt] = c->dalloc((size_t)L.A.g.N * vec_bytes(p));
+        }
+    }
+}
+
+void ensure_tmp(hpgmx_ctx *c, Prec p)
+{
+    const int vt = vt_of(p);
+    const size_t N0 = (size_t)c->lv[0].A.g.N;
+    for (int i = 0; i < 3; ++i)
+        if (!c->tmp[vt][i]) c->tmp[vt][i] = c->dalloc(N0 * vec_bytes(p));
+}
+
+void ensure_common(hpgmx_ctx *c)
+{
+    if (!c->ctrl) {
+        c->ctrl = (Ctrl *)c->dalloc(sizeof(Ctrl));
+        hip_check(hipMemsetAsync(c->ctrl, 0, sizeof(Ctrl), c->stream), "hipMemsetAsync");
+        c->partials = (double *)c->dalloc((size_t)kMaxRedBlocks * kMaxBasis * 8);
+    }
+}
+
+void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
+{
+    ensure_common(c);
+    const size_t N0 = (size_t)c->lv[0].A.g.N;
+    if (!c->b_int) {
+        c->b_int = (double *)c->dalloc(N0 * 8);
+        c->x_int = (double *)c->dalloc(N0 * 8);
+        c->r64 = (double *)c->dalloc(N0 * 8);
+    }
+    Krylov &K = c->kry[p];
+    if (K.m < m) {
+        if (!c->ws_base && K.Q) {
+            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+            for (auto it = c->owned.begin(); it != c->owned.end(); ++it)
+                if (*it == K.Q) { (void)hipFree(K.Q); c->owned.erase(it); break; }
+        }
+        K.Q = c->dalloc(N0 * (m + 1) * vec_bytes(p));
+        K.m = m;
+    }
+    if (!K.z) {
+        K.z = c->dalloc(N0 * vec_bytes(p));
+        K.u = c->dalloc(N0 * vec_bytes(p));
+    }
+    ensure_level_vectors(c, p);
+    ensure_prec(c, p);
+    if (p != P64) ensure_prec(c, P64);
+}
+
+size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, unsigned mask)
+{
+    size_t tot = 0;
+    auto add = [&](size_t b) { tot += round_up(b ? b : 1); };
+    int nx = pd.nx, ny = pd.ny, nz = pd.nz;
+    const size_t N0 = (size_t)nx * ny * nz;
+    for (int l = 0; l < mg.levels; ++l) {
+        const size_t N = (size_t)nx * ny * nz;
+        add(kSlots * N * 4);                              // columns
+        for (int p = 0; p < 4; ++p) {
+            const bool want = (mask >> p) & 1u || p == P64;  // FP64 always (outer residual)
+            if (!want) continue;
+            const size_t vb = p == P64 ? 8 : p == P32 ? 4 : 2;
+            add(kSlots * N * vb);
+            add(N * vb);
+        }
+        if (l >= 1) {
+            for (int vt = 0; vt < 2; ++vt) {
+                const bool want = vt == 0 ? (mask & 1u) : (mask & 0xEu);
+                if (want) { add(N * (vt == 0 ? 8 : 4)); add(N * (vt == 0 ? 8 : 4)); }
+            }
+        }
+        nx /= 2; ny /= 2; nz /= 2;
+    }
+    add(sizeof(Ctrl));
+    add((size_t)kMaxRedBlocks * kMaxBasis * 8);
+    add(N0 * 8); add(N0 * 8); add(N0 * 8);                // b, x, r in FP64
+    for (int p = 0; p < 4; ++p) {
+        if (!((mask >> p) & 1u)) continue;
+        const size_t vb = p == P64 ? 8 : 4;
+        add(N0 * (m + 1) * vb);
+        add(N0 * vb); add(N0 * vb);
+    }
+    for (int vt = 0; vt < 2; ++vt) {                       // ABI staging buffers
+        const bool want = vt == 0 ? true : (mask & 0xEu) != 0;
+        if (want) for (int i = 0; i < 3; ++i) add(N0 * (vt == 0 ? 8 : 4));
+    }
+    return tot;
+}
+
+// ---- smoothing and the V-cycle ---------------------------------------------------------------------
+void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool forward, bool zero,
+                   int skip_first_colour)
+{
+    const Matrix &A = c->lv[l].A;
+    for (int n = 0; n < 8; ++n) {
+        const int col = forward ? n : 7 - n;
+        if (n == 0 && skip_first_colour) continue;
+        const unsigned mask = zero ? earlier_colour_mask(col, forward) : (1u << kSlots) - 1u;
+        ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
+        launch_gs_colour(A, p, col, mask, r, z, c->stream);
+    }
+}
+
+// `nsweeps` sweeps of kind `kind` on level l; the first starts from z = 0
+// when `zero` is set.
+void smooth_level(hpgmx_ctx *c, int l, Prec p, int kind, const void *r, void *z, bool zero,
+                  int nsweeps)
+{
+    if (nsweeps <= 0) {
+        if (zero)
+            hip_check(hipMemsetAsync(z, 0, (size_t)c->lv[l].A.g.N * vec_bytes(p), c->stream),
+                      "hipMemsetAsync");
+        return;
+    }
+    for (int s = 0; s < nsweeps; ++s) {
+        const bool zg = zero && s == 0;
+        if (kind == HPGMX_GS_FORWARD) {
+            sweep_colours(c, l, p, r, z, true, zg, 0);
+        } else if (kind == HPGMX_GS_BACKWARD) {
+            sweep_colours(c, l, p, r, z, false, zg, 0);
+        } else {
+            sweep_colours(c, l, p, r, z, true, zg, 0);
+            // The backward half begins by relaxing colour 7 again with
+            // unchanged neighbours, which reproduces its value: skip it.
+            sweep_colours(c, l, p, r, z, false, false, 1);
+        }
+    }
+}
+
+// z = M^{-1} r on level l (z is overwritten; the cycle starts from zero).
+void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z)
+{
+    const hpgmx_mg_desc &mg = c->mg;
+    const int vt = vt_of(p);
+    if (l == mg.levels - 1) {
+        smooth_level(c, l, p, mg.sweep, r, z, true, mg.coarsest_sweeps);
+        return;
+    }
+    Level &C = c->lv[l + 1];
+    smooth_level(c, l, p, mg.sweep, r, z, true, mg.pre_sweeps);
+    {
+        ProfScope ps(c, HPGMX_K_RESTRICT, l);
+        launch_restrict(c->lv[l].A, C.A.g, p, r, z, C.r[vt], c->stream);
+    }
+    vcycle(c, l + 1, p, C.r[vt], C.z[vt]);
+    {
+        ProfScope ps(c, HPGMX_K_PROLONG, l);
+        launch_prolong(c->lv[l].A.g, C.A.g, p, C.z[vt], z, c->stream);
+    }
+    smooth_level(c, l, p, mg.sweep, r, z, false, mg.post_sweeps);
+}
+
+// ---- GMRES-IR (Alg. 3) ----------------------------------------------------------------------------------
+struct Scal {  // mirrors the scalar block of Ctrl
+    double rho, inv_rho, beta, inv_beta, nrm2, rho0;
+    int breakdown, nonfinite;
+};
+
+Scal read_scal(hpgmx_ctx *c)
+{
+    hip_check(hipMemcpyAsync(c->host_scal, &c->ctrl->rho, sizeof(Scal), hipMemcpyDeviceToHost,
+                             c->stream), "hipMemcpyAsync");
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    Scal s;
+    std::memcpy(&s, c->host_scal, sizeof(Scal));
+    return s;
+}
+
+hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_desc *d,
+                   hpgmx_solve_stats *st)
+{
+    const int m = d->restart;
+    const Prec p = (Prec)d->inner_dtype;
+    ensure_krylov(c, p, m);
+    Krylov &K = c->kry[p];
+    const Matrix &A0 = c->lv[0].A;
+    const Geom &g0 = A0.g;
+    const i64 N = g0.N;
+    const size_t vb = vec_bytes(p);
+    char *Q = (char *)K.Q;
+    auto col = [&](int j) { return (void *)(Q + (size_t)j * N * vb); };
+
+    c->prof = (d->flags & HPGMX_SOLVE_PROFILE) != 0;
+    if (c->prof) {
+        std::memset(c->prof_ms, 0, sizeof(c->prof_ms));
+        std::memset(c->prof_n, 0, sizeof(c->prof_n));
+        c->evused = 0;
+    }
+    hpgmx_solve_stats S{};
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    hip_check(hipEventRecord(e0, c->stream), "hipEventRecord");
+
+    {
+        ProfScope ps(c, HPGMX_K_PERMUTE, 0);
+        launch_nat2int(g0, P64, b, P64, c->b_int, c->stream);
+    }
+    {
+        ProfScope ps(c, HPGMX_K_PERMUTE, 0);
+        launch_nat2int(g0, P64, x, P64, c->x_int, c->stream);
+    }
+    launch_norm64(N, c->b_int, c->partials, c->ctrl, c->stream);
+    Scal sc = read_scal(c);
+    const double rho0 = sc.rho0;
+    S.rho0 = rho0;
+    hpgmx_status status = HPGMX_OK;
+    if (sc.nonfinite) {
+        status = HPGMX_ENONFINITE;
+        c->err = "right-hand side is not finite";
+    } else if (rho0 == 0.0) {
+        hip_check(hipMemsetAsync(x, 0, (size_t)N * 8, c->stream), "hipMemsetAsync");
+        S.converged = 1;
+        S.final_rel_res = 0.0;
+    } else {
+        int its = 0;
+        for (;;) {
+            {
+                ProfScope ps(c, HPGMX_K_RESID64, 0);
+                launch_resid64(A0, c->x_int, c->b_int, c->r64, c->partials, c->ctrl, m, c->stream);
+            }
+            sc = read_scal(c);
+            double rho = sc.rho;
+            S.final_rel_res = rho / rho0;
+            if (sc.nonfinite) { status = HPGMX_ENONFINITE; c->err = "outer residual is not finite"; break; }
+            if (rho / rho0 < d->tol) { S.converged = 1; break; }
+            if (its >= d->max_iters) break;
+            {
+                ProfScope ps(c, HPGMX_K_CAST, 0);
+                launch_cast(N, p, c->r64, c->ctrl, col(0), c->stream);
+            }
+            int kk = 0;
+            for (int k = 0; k < m; ++k) {
+                if (rho / rho0 < d->tol) break;
+                vcycle(c, 0, p, col(k), K.z);
+                {
+                    ProfScope ps(c, HPGMX_K_SPMV_DOT, 0);
+                    launch_spmv_dot(A0, p, K.z, K.Q, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                }
+                {
+                    ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
+                    launch_cgs_dot(N, p, K.Q, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                }
+                {
+                    ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
+                    launch_cgs_norm(N, p, K.Q, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
+                }
+                {
+                    ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
+                    launch_normalize(N, p, col(k + 1), c->ctrl, c->stream);
+                }
+                sc = read_scal(c);
+                rho = sc.rho;
+                kk = k + 1;
+                ++its;
+                if (d->res_hist_host && its - 1 < d->res_hist_len) d->res_hist_host[its - 1] = rho / rho0;
+                S.est_rel_res = rho / rho0;
+                if (sc.nonfinite) break;
+                if (sc.breakdown) { S.breakdown = 1; break; }
+                if (its >= d->max_iters) break;
+            }
+            if (sc.nonfinite) { status = HPGMX_ENONFINITE; c->err = "Krylov vector is not finite"; break; }
+            {
+                ProfScope ps(c, HPGMX_K_TRSM, 0);
+                launch_trsm(c->ctrl, kk, m, c->stream);
+            }
+            {
+                ProfScope ps(c, HPGMX_K_GEMV, 0);
+                launch_gemv(N, p, K.Q, kk, c->ctrl, K.u, c->stream);
+            }
+            vcycle(c, 0, p, K.u, K.z);
+            {
+                ProfScope ps(c, HPGMX_K_UPDATE, 0);
+                launch_update(N, p, K.z, c->x_int, c->stream);
+            }
+            ++S.restarts;
+        }
+        S.iters = its;
+        {
+            ProfScope ps(c, HPGMX_K_PERMUTE, 0);
+            launch_int2nat(g0, P64, c->x_int, P64, x, c->stream);
+        }
+    }
+    hip_check(hipEventRecord(e1, c->stream), "hipEventRecord");
+    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    S.solve_ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (c->prof) c->prof_collect();
+    c->prof = false;
+    if (st) *st = S;
+    return status;
+}
+
+// ---- argument checks --------------------------------------------------------------------------
+void check_ready(hpgmx_ctx *c)
+{
+    if (c->poisoned) fail(HPGMX_ESTATE, "handle poisoned by an earlier HIP error: " + c->err);
+    if (!c->mg_ready) fail(HPGMX_ESTATE, "hpgmx_mg_setup has not been called");
+    hip_check(hipSetDevice(c->device), "hipSetDevice");
+}
+
+Prec check_dtype(int dtype)
+{
+    if (dtype < HPGMX_F64 || dtype > HPGMX_BF16) fail(HPGMX_EINVAL, "dtype out of range");
+    return (Prec)dtype;
+}
+
+void check_level(hpgmx_ctx *c, int level, bool need_coarser)
+{
+    const int top = (int)c->lv.size() - (need_coarser ? 1 : 0);
+    if (level < 0 || level >= top) fail(HPGMX_EINVAL, "level out of range");
+}
+
+void check_ptr(const void *p, const char *name)
+{
+    if (!p) fail(HPGMX_EINVAL, std::string(name) + " is NULL");
+}
+
+template <typename F>
+hpgmx_status guarded(hpgmx_ctx *c, F &&f)
+{
+    if (!c) return HPGMX_EINVAL;
+    try {
+        return f();
+    } catch (const Error &e) {
+        c->err = e.msg;
+        if (e.st == HPGMX_EHIP) c->poisoned = true;
+        return e.st;
+    } catch (const std::bad_alloc &) {
+        c->err = "host allocation failed";
+        return HPGMX_ENOMEM;
+    } catch (const std::exception &e) {  // kernel launch errors
+        c->err = e.what();
+        c->poisoned = true;
+        return HPGMX_EHIP;
+    }
+}
+
+}  // namespace
+
+// =====================================================================================================
+extern "C" {
+
+hpgmx_status hpgmx_setup_problem(const hpgmx_problem_desc *desc, void *hip_stream, hpgmx_handle *out)
+{
+    if (!desc || !out) return HPGMX_EINVAL;
+    *out = nullptr;
+    if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1) return HPGMX_EINVAL;
+    if (!std::isfinite(desc->beta)) return HPGMX_EINVAL;
+    const double N = (double)desc->nx * desc->ny * desc->nz;
+    if (N >= 2147483647.0) return HPGMX_EINVAL;  // int32 column indices
+    hpgmx_ctx *c = new (std::nothrow) hpgmx_ctx();
+    if (!c) return HPGMX_ENOMEM;
+    c->prob = *desc;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return HPGMX_EHIP;
+    }
+    *out = c;
+    return HPGMX_OK;
+}
+
+hpgmx_status hpgmx_workspace_bytes(hpgmx_handle h, const hpgmx_mg_desc *mg, int restart,
+                                   unsigned dtype_mask, size_t *bytes)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ptr(mg, "mg");
+        check_ptr(bytes, "bytes");
+        if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
+        if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
+        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0xFu);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_bind_workspace(hpgmx_handle h, void *dev_ptr, size_t bytes)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ptr(dev_ptr, "dev_ptr");
+        if (h->mg_ready || h->ws_base || !h->owned.empty())
+            fail(HPGMX_ESTATE, "workspace must be bound once, before hpgmx_mg_setup");
+        if (((uintptr_t)dev_ptr) % kAlign != 0) fail(HPGMX_EINVAL, "workspace must be 256-byte aligned");
+        h->ws_base = (char *)dev_ptr;
+        h->ws_size = bytes;
+        h->ws_used = 0;
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_mg_setup(hpgmx_handle h, const hpgmx_mg_desc *mg)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ptr(mg, "mg");
+        if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
+        if (h->mg_ready) fail(HPGMX_ESTATE, "hpgmx_mg_setup already called on this handle");
+        if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels must be 1..8");
+        if (mg->pre_sweeps < 0 || mg->post_sweeps < 0 || mg->coarsest_sweeps < 0)
+            fail(HPGMX_EINVAL, "sweep counts must be >= 0");
+        if (mg->sweep < HPGMX_GS_FORWARD || mg->sweep > HPGMX_GS_SYMMETRIC)
+            fail(HPGMX_EINVAL, "unknown sweep kind");
+        const int f = 1 << (mg->levels - 1);
+        const hpgmx_problem_desc &pd = h->prob;
+        if (pd.nx % f || pd.ny % f || pd.nz % f)
+            fail(HPGMX_EINVAL, "every dimension must be divisible by 2^(levels-1)");
+        if (pd.nx / f < 2 || pd.ny / f < 2 || pd.nz / f < 2)
+            fail(HPGMX_EINVAL, "the coarsest level must be at least 2 in every dimension");
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        h->mg = *mg;
+        h->lv.resize(mg->levels);
+        int nx = pd.nx, ny = pd.ny, nz = pd.nz;
+        for (int l = 0; l < mg->levels; ++l) {
+            Matrix &A = h->lv[l].A;
+            A.g = make_geom(nx, ny, nz);
+            A.col = (int *)h->dalloc((size_t)kSlots * A.g.N * 4);
+            alloc_matrix_prec(h, A, P64);
+            alloc_matrix_prec(h, A, P32);
+            launch_generate(A, pd.beta, h->stream);
+            nx /= 2; ny /= 2; nz /= 2;
+        }
+        ensure_common(h);
+        if (!h->host_scal) hip_check(hipHostMalloc((void **)&h->host_scal, 256, hipHostMallocDefault), "hipHostMalloc");
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        h->mg_ready = true;
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_gmres_ir_solve(hpgmx_handle h, const double *b, double *x,
+                                  const hpgmx_solve_desc *desc, hpgmx_solve_stats *stats)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_ptr(b, "b");
+        check_ptr(x, "x");
+        check_ptr(desc, "desc");
+        if (desc->restart < 1 || desc->restart > kMaxRestart) fail(HPGMX_EINVAL, "restart must be 1..63");
+        if (desc->max_iters < 0) fail(HPGMX_EINVAL, "max_iters must be >= 0");
+        if (!(desc->tol >= 0.0)) fail(HPGMX_EINVAL, "tol must be >= 0");
+        check_dtype(desc->inner_dtype);
+        if (desc->res_hist_len < 0) fail(HPGMX_EINVAL, "res_hist_len must be >= 0");
+        return solve(h, b, x, desc, stats);
+    });
+}
+
+hpgmx_status hpgmx_spmv(hpgmx_handle h, int level, int dtype, const void *x, void *y)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, false);
+        const Prec p = check_dtype(dtype);
+        check_ptr(x, "x");
+        check_ptr(y, "y");
+        ensure_prec(h, p);
+        ensure_tmp(h, p);
+        const int vt = vt_of(p);
+        const Matrix &A = h->lv[level].A;
+        const Prec pv = p == P64 ? P64 : P32;
+        launch_nat2int(A.g, pv, x, pv, h->tmp[vt][0], h->stream);
+        launch_spmv(A, p, h->tmp[vt][0], h->tmp[vt][1], h->stream);
+        launch_int2nat(A.g, pv, h->tmp[vt][1], pv, y, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_smooth(hpgmx_handle h, int level, int dtype, int sweep, const void *r, void *z,
+                          int zero_guess)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, false);
+        const Prec p = check_dtype(dtype);
+        if (sweep < HPGMX_GS_FORWARD || sweep > HPGMX_GS_SYMMETRIC) fail(HPGMX_EINVAL, "unknown sweep kind");
+        check_ptr(r, "r");
+        check_ptr(z, "z");
+        ensure_prec(h, p);
+        ensure_tmp(h, p);
+        const int vt = vt_of(p);
+        const Matrix &A = h->lv[level].A;
+        const Prec pv = p == P64 ? P64 : P32;
+        launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
+        if (!zero_guess) launch_nat2int(A.g, pv, z, pv, h->tmp[vt][1], h->stream);
+        smooth_level(h, level, p, sweep, h->tmp[vt][0], h->tmp[vt][1], zero_guess != 0, 1);
+        launch_int2nat(A.g, pv, h->tmp[vt][1], pv, z, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_vcycle(hpgmx_handle h, int dtype, const void *r, void *z)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        const Prec p = check_dtype(dtype);
+        check_ptr(r, "r");
+        check_ptr(z, "z");
+        ensure_prec(h, p);
+        ensure_tmp(h, p);
+        ensure_level_vectors(h, p);
+        const int vt = vt_of(p);
+        const Matrix &A = h->lv[0].A;
+        const Prec pv = p == P64 ? P64 : P32;
+        launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
+        vcycle(h, 0, p, h->tmp[vt][0], h->tmp[vt][1]);
+        launch_int2nat(A.g, pv, h->tmp[vt][1], pv, z, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_restrict_residual(hpgmx_handle h, int level, int dtype, const void *r,
+                                     const void *z, void *r_coarse)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, true);
+        const Prec p = check_dtype(dtype);
+        check_ptr(r, "r");
+        check_ptr(z, "z");
+        check_ptr(r_coarse, "r_coarse");
+        ensure_prec(h, p);
+        ensure_tmp(h, p);
+        const int vt = vt_of(p);
+        const Matrix &A = h->lv[level].A;
+        const Geom &gc = h->lv[level + 1].A.g;
+        const Prec pv = p == P64 ? P64 : P32;
+        launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
+        launch_nat2int(A.g, pv, z, pv, h->tmp[vt][1], h->stream);
+        launch_restrict(A, gc, p, h->tmp[vt][0], h->tmp[vt][1], h->tmp[vt][2], h->stream);
+        launch_int2nat(gc, pv, h->tmp[vt][2], pv, r_coarse, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_prolong_add(hpgmx_handle h, int level, int dtype, const void *z_coarse, void *z)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, true);
+        const Prec p = check_dtype(dtype);
+        check_ptr(z_coarse, "z_coarse");
+        check_ptr(z, "z");
+        ensure_tmp(h, p);
+        const int vt = vt_of(p);
+        const Geom &gf = h->lv[level].A.g;
+        const Geom &gc = h->lv[level + 1].A.g;
+        const Prec pv = p == P64 ? P64 : P32;
+        launch_nat2int(gc, pv, z_coarse, pv, h->tmp[vt][0], h->stream);
+        launch_nat2int(gf, pv, z, pv, h->tmp[vt][1], h->stream);
+        launch_prolong(gf, gc, p, h->tmp[vt][0], h->tmp[vt][1], h->stream);
+        launch_int2nat(gf, pv, h->tmp[vt][1], pv, z, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_rhs_from_x(hpgmx_handle h, const double *x, double *b)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_ptr(x, "x");
+        check_ptr(b, "b");
+        ensure_tmp(h, P64);
+        const Matrix &A = h->lv[0].A;
+        launch_nat2int(A.g, P64, x, P64, h->tmp[0][0], h->stream);
+        launch_spmv(A, P64, h->tmp[0][0], h->tmp[0][1], h->stream);
+        launch_int2nat(A.g, P64, h->tmp[0][1], P64, b, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *total_ms,
+                               long long *launches)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        if (kernel < 0 || kernel >= HPGMX_K_COUNT || level < 0 || level >= kMaxLevels)
+            fail(HPGMX_EINVAL, "kernel or level out of range");
+        if (total_ms) *total_ms = h->prof_ms[kernel][level];
+        if (launches) *launches = h->prof_n[kernel][level];
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_stream_copy(hpgmx_handle h, const void *src, void *dst, size_t bytes, int reps,
+                               double *ms)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
+        check_ptr(src, "src");
+        check_ptr(dst, "dst");
+        check_ptr(ms, "ms");
+        if (bytes == 0 || bytes % 16 || reps < 1) fail(HPGMX_EINVAL, "bytes must be a positive multiple of 16, reps >= 1");
+        hip_check(hipSetDevice(h->device), "hipSetDevice");
+        hipEvent_t e0, e1;
+        hip_check(hipEventCreate(&e0), "hipEventCreate");
+        hip_check(hipEventCreate(&e1), "hipEventCreate");
+        launch_copy(src, dst, bytes, h->stream);  // warm-up
+        hip_check(hipEventRecord(e0, h->stream), "hipEventRecord");
+        for (int i = 0; i < reps; ++i) launch_copy(src, dst, bytes, h->stream);
+        hip_check(hipEventRecord(e1, h->stream), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float t = 0.f;
+        hip_check(hipEventElapsedTime(&t, e0, e1), "hipEventElapsedTime");
+        *ms = t / reps;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_destroy(hpgmx_handle h)
+{
+    if (!h) return HPGMX_EINVAL;
+    (void)hipSetDevice(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    for (auto &e : h->evpool) {
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    for (void *p : h->owned) (void)hipFree(p);
+    if (h->host_scal) (void)hipHostFree(h->host_scal);
+    delete h;
+    return HPGMX_OK;
+}
+
+const char *hpgmx_last_error(hpgmx_handle h)
+{
+    if (!h) return "invalid handle";
+    return h->err.c_str();
+}
+
+}  // extern "C"

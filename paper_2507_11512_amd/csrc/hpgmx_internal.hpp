@@ -1,0 +1,151 @@
+// Internal declarations of the hpgmx library (gfx950 HIP).
+//
+// Data layout in HBM (per multigrid level):
+//  * Rows are stored in a colour-blocked order.  The 8 colours of the
+//    multicolour Gauss-Seidel smoother (Sec. 3.2) are the 8 parity classes of
+//    (i, j, k); colour c = (i&1) + 2(j&1) + 4((k+1)&1), so the class of
+//    all-even points -- the injection points of the restriction, eq. (3) --
+//    is colour 4.  Each colour is one contiguous block, lexicographic in
+//    (i>>1, j>>1, k>>1) inside the block.  A colour launch therefore streams
+//    a contiguous slice of every array, every stencil neighbour of a row sits
+//    at a regular offset in another block (gathers stay coalesced across a
+//    wavefront), and the colour-4 block of a fine level is exactly the coarse
+//    level in its natural order.
+//  * The matrix is ELLPACK (Sec. 3.2) with the diagonal split off: 26
+//    off-diagonal slots, slot-major (value and int32 column of slot s for row
+//    p at [s*N + p]), plus a diagonal array.  Rows with fewer neighbours pad
+//    with value 0 and column = the row itself.  Column indices are shared by
+//    all value precisions (FP64, FP32, FP16, BF16).
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "hpgmx.h"
+
+namespace hpgmx {
+
+using i64 = long long;
+
+constexpr int kSlots = 26;        // off-diagonal ELL slots
+constexpr int kMaxLevels = 8;
+constexpr int kMaxRestart = 63;   // m; the basis holds m + 1 vectors
+constexpr int kMaxBasis = 64;     // kMaxRestart + 1
+constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
+constexpr int kMaxRedBlocks = 2048;  // workgroups of the grid-stride reductions
+
+using bf16 = __hip_bfloat16;
+
+// Colour-blocked geometry of one level.
+struct Geom {
+    int nx, ny, nz;
+    int bx[8], by[8], bz[8];  // block extents per colour
+    i64 off[9];               // block offsets; off[8] = N
+    i64 N;
+};
+
+__host__ __device__ inline int colour_of(int i, int j, int k)
+{
+    return (i & 1) + 2 * (j & 1) + 4 * ((k + 1) & 1);
+}
+
+__host__ __device__ inline i64 to_internal(const Geom &g, int i, int j, int k)
+{
+    const int c = colour_of(i, j, k);
+    return g.off[c] + (i >> 1) + (i64)g.bx[c] * ((j >> 1) + (i64)g.by[c] * (k >> 1));
+}
+
+__host__ __device__ inline void from_internal(const Geom &g, i64 p, int &i, int &j, int &k)
+{
+    int c = 0;
+    while (c < 7 && p >= g.off[c + 1]) ++c;
+    const i64 q = p - g.off[c];
+    const int ii = (int)(q % g.bx[c]);
+    const int jj = (int)((q / g.bx[c]) % g.by[c]);
+    const int kk = (int)(q / ((i64)g.bx[c] * g.by[c]));
+    i = 2 * ii + (c & 1);
+    j = 2 * jj + ((c >> 1) & 1);
+    k = 2 * kk + (((c >> 2) & 1) ^ 1);
+}
+
+Geom make_geom(int nx, int ny, int nz);
+
+// Neighbour colour of slot s for a row of colour c (slot s enumerates the 26
+// off-diagonal offsets (di,dj,dk) in the order dk, dj, di = -1..1 with the
+// centre skipped).
+__host__ __device__ inline void slot_offset(int s, int &di, int &dj, int &dk)
+{
+    const int t = s < 13 ? s : s + 1;
+    di = t % 3 - 1;
+    dj = (t / 3) % 3 - 1;
+    dk = t / 9 - 1;
+}
+
+// Bit s set when slot s of a colour-c row couples to a colour relaxed before c
+// in the given direction (forward: lower colour index).
+unsigned earlier_colour_mask(int c, bool forward);
+
+struct Matrix {
+    Geom g;
+    int *col = nullptr;  // [26][N]
+    double *v64 = nullptr, *d64 = nullptr;
+    float *v32 = nullptr, *d32 = nullptr;
+    __half *v16 = nullptr, *d16 = nullptr;
+    bf16 *vb16 = nullptr, *db16 = nullptr;
+};
+
+// Precision of a call: vector type double for P64, float otherwise; matrix
+// values in the named type.
+enum Prec { P64 = HPGMX_F64, P32 = HPGMX_F32, P16 = HPGMX_F16, PB16 = HPGMX_BF16 };
+inline size_t vec_bytes(Prec p) { return p == P64 ? 8 : 4; }
+
+// Device-side control block of one Krylov cycle (FP64): Hessenberg matrix
+// (rotated) and its unrotated copy, Givens rotations, right-hand side t,
+// projected solution y, CGS2 coefficients, scalars and reduction counters.
+struct Ctrl {
+    double H[kMaxBasis * kMaxRestart];
+    double Hbar[kMaxBasis * kMaxRestart];
+    double t[kMaxBasis], cs[kMaxBasis], sn[kMaxBasis], y[kMaxBasis];
+    double h1[kMaxBasis], h2[kMaxBasis];
+    // scalars read back by the host after every inner step (keep together)
+    double rho, inv_rho, beta, inv_beta, nrm2, rho0;
+    int breakdown, nonfinite;
+    unsigned counter[4];
+};
+
+// ---- launchers (stream-ordered) -------------------------------------------
+void launch_generate(const Matrix &A, double beta, hipStream_t s);
+void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s);
+void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s);
+void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s);
+// One colour of a Gauss-Seidel sweep: rows of colour c, neighbours in `mask`.
+void launch_gs_colour(const Matrix &A, Prec p, int c, unsigned mask, const void *r, void *z,
+                      hipStream_t s);
+void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
+                     void *rc, hipStream_t s);
+void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void *z,
+                    hipStream_t s);
+
+// Krylov kernels.  Q is column-major with leading dimension ldq = N.
+int red_blocks(i64 N);
+void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, int kb, void *w,
+                     double *partials, Ctrl *ctrl, hipStream_t s);
+void launch_cgs_dot(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
+                    hipStream_t s);
+void launch_cgs_norm(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
+                     int k, int m, hipStream_t s);
+void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s);
+void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
+                    double *partials, Ctrl *ctrl, int m, hipStream_t s);
+void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStream_t s);
+void launch_cast(i64 N, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s);
+void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s);
+void launch_gemv(i64 N, Prec p, const void *Q, int kk, const Ctrl *ctrl, void *u, hipStream_t s);
+void launch_update(i64 N, Prec p, const void *z, double *x, hipStream_t s);
+void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+}  // namespace hpgmx

@@ -1,0 +1,496 @@
+// Krylov-side kernels of Alg. 3: the SpMV fused with the first CGS2 inner
+// products, the two fused CGS2 update passes, the normalisation, the FP64
+// outer residual, the projected least-squares solve, the basis combination
+// and the mixed-precision solution update.
+//
+// Reductions (inner products and norms) are deterministic: every workgroup
+// of a fixed-size grid-stride launch writes its partial sums, and the last
+// workgroup to finish (found with a device-scope counter) adds them in block
+// order and writes the result -- no second launch and no floating-point
+// atomics.  The Givens update of the Hessenberg column (Alg. 3, "Update QR
+// with Given's rotations") runs in FP64 in that last workgroup of the norm
+// pass, so the whole inner step needs no host round trip except the 8-byte
+// residual-estimate read.
+#include "hpgmx_internal.hpp"
+
+#include <stdexcept>
+
+namespace hpgmx {
+
+template <typename V> struct VecOf2 { using T = float; };
+template <> struct VecOf2<double> { using T = double; };
+
+template <typename V> __device__ __forceinline__ V ldnt(const V *p) { return __builtin_nontemporal_load(p); }
+template <> __device__ __forceinline__ __half ldnt<__half>(const __half *p)
+{
+    return __ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
+}
+template <> __device__ __forceinline__ bf16 ldnt<bf16>(const bf16 *p)
+{
+    return __ushort_as_bfloat16(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
+}
+template <typename T, typename V> __device__ __forceinline__ T cv(V v) { return (T)v; }
+template <> __device__ __forceinline__ float cv<float, __half>(__half v) { return __half2float(v); }
+template <> __device__ __forceinline__ float cv<float, bf16>(bf16 v) { return __bfloat162float(v); }
+
+#define HPGMX_LAUNCH_CHECK()                                                    \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));  \
+    } while (0)
+
+int red_blocks(i64 N)
+{
+    const i64 b = (N + kBlock - 1) / kBlock;
+    return (int)(b < kMaxRedBlocks ? (b < 1 ? 1 : b) : kMaxRedBlocks);
+}
+
+// ---- reduction helpers -------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Writes this workgroup's sums of acc[0..kb) to partials[blockIdx.x * kMaxBasis + j].
+template <int KB>
+__device__ __forceinline__ void store_partials(const double (&acc)[KB], int kb, double *partials)
+{
+    __shared__ double red[kBlock / 64][KB];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        if (j < kb) {
+            const double v = wave_sum(acc[j]);
+            if (lane == 0) red[wave][j] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kb) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
+        __hip_atomic_store(partials + (i64)blockIdx.x * kMaxBasis + threadIdx.x, s, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// True in exactly one workgroup: the last one to arrive.  Partial sums
+// written before the call are visible to it after the call.
+__device__ __forceinline__ bool arrive_last(unsigned *counter)
+{
+    __shared__ int last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = prev == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// In the last workgroup: out[j] = sum over workgroups b (in order) of
+// partials[b][j], j < kb.  Lane l of wave w adds workgroups b = w, w+4, ...
+__device__ __forceinline__ void finish_sums(const double *partials, int kb, double *out,
+                                            unsigned *counter)
+{
+    __shared__ double fin[kBlock / 64][kMaxBasis];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int nb = gridDim.x;
+    if (lane < kb) {
+        double s = 0.0;
+        for (int b = wave; b < nb; b += kBlock / 64)
+            s += __hip_atomic_load(partials + (i64)b * kMaxBasis + lane, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        fin[wave][lane] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < kb) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += fin[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    if (threadIdx.x == 0)
+        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// ---- w = A z fused with h1 = Q_{1:kb}^T w (Alg. 3: SpMV, then the first GEMVT) ----
+template <typename V, int KB>
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, const V *__restrict__ offv,
+                                                     const int *__restrict__ offc,
+                                                     const V *__restrict__ diag,
+                                                     const typename VecOf2<V>::T *__restrict__ z,
+                                                     const typename VecOf2<V>::T *__restrict__ Q,
+                                                     int kb, typename VecOf2<V>::T *__restrict__ w,
+                                                     double *partials, Ctrl *ctrl)
+{
+    using T = typename VecOf2<V>::T;
+    double acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        T v = cv<T>(ldnt(diag + p)) * z[p];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const i64 e = (i64)s * N + p;
+            v += cv<T>(ldnt(offv + e)) * z[ldnt(offc + e)];
+        }
+        w[p] = v;
+        const double vd = (double)v;
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < kb) acc[j] += (double)Q[(i64)j * N + p] * vd;
+    }
+    store_partials<KB>(acc, kb, partials);
+    if (arrive_last(&ctrl->counter[0])) finish_sums(partials, kb, ctrl->h1, &ctrl->counter[0]);
+}
+
+// ---- w -= Q h1 fused with h2 = Q^T w (the reorthogonalisation GEMV and GEMVT) ----
+template <typename T, int KB>
+__global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 N, const T *__restrict__ Q, int kb,
+                                                    T *__restrict__ w, double *partials,
+                                                    Ctrl *ctrl)
+{
+    double acc[KB], c[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) {
+        acc[j] = 0.0;
+        c[j] = j < kb ? ctrl->h1[j] : 0.0;
+    }
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        T q[KB];
+        double v = (double)w[p];
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < kb) {
+                q[j] = Q[(i64)j * N + p];
+                v -= c[j] * (double)q[j];
+            }
+        const T vt = (T)v;
+        w[p] = vt;
+        const double vd = (double)vt;
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < kb) acc[j] += (double)q[j] * vd;
+    }
+    store_partials<KB>(acc, kb, partials);
+    if (arrive_last(&ctrl->counter[1])) finish_sums(partials, kb, ctrl->h2, &ctrl->counter[1]);
+}
+
+// Givens update of Hessenberg column k (0-based) in FP64, done by one thread:
+// H(0:k,k) = h1 + h2, H(k+1,k) = beta; rotate by the earlier rotations (each
+// rotation reads both entries before writing either); form the rotation that
+// annihilates H(k+1,k); update t and the residual estimate rho = |t(k+1)|.
+__device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
+{
+    double *Hk = c->H + (i64)k * (m + 1);
+    double *Hb = c->Hbar + (i64)k * (m + 1);
+    for (int j = 0; j <= k; ++j) Hk[j] = c->h1[j] + c->h2[j];
+    const double beta = sqrt(nrm2);
+    Hk[k + 1] = beta;
+    for (int j = 0; j <= k + 1; ++j) Hb[j] = Hk[j];
+    for (int j = 0; j < k; ++j) {
+        const double a = Hk[j], b = Hk[j + 1];
+        Hk[j] = c->cs[j] * a + c->sn[j] * b;
+        Hk[j + 1] = -c->sn[j] * a + c->cs[j] * b;
+    }
+    const double mu = sqrt(Hk[k] * Hk[k] + Hk[k + 1] * Hk[k + 1]);
+    double ck = 1.0, sk = 0.0;
+    if (mu > 0.0) {
+        ck = Hk[k] / mu;
+        sk = Hk[k + 1] / mu;
+    }
+    c->cs[k] = ck;
+    c->sn[k] = sk;
+    Hk[k] = mu;
+    Hk[k + 1] = 0.0;
+    const double tk = c->t[k];
+    c->t[k + 1] = -sk * tk;
+    c->t[k] = ck * tk;
+    c->rho = fabs(c->t[k + 1]);
+    c->beta = beta;
+    c->nrm2 = nrm2;
+    c->breakdown = !(beta > 1e-300);
+    c->inv_beta = c->breakdown ? 0.0 : 1.0 / beta;
+    c->nonfinite = !isfinite(nrm2);
+}
+
+// ---- w -= Q h2 fused with ||w||^2, then the Givens step -------------------------------------
+template <typename T, int KB>
+__global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 N, const T *__restrict__ Q, int kb,
+                                                     T *__restrict__ w, double *partials,
+                                                     Ctrl *ctrl, int k, int m)
+{
+    double acc[1] = {0.0}, c[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) c[j] = j < kb ? ctrl->h2[j] : 0.0;
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        double v = (double)w[p];
+#pragma unroll
+        for (int j = 0; j < KB; ++j)
+            if (j < kb) v -= c[j] * (double)Q[(i64)j * N + p];
+        const T vt = (T)v;
+        w[p] = vt;
+        acc[0] += (double)vt * (double)vt;
+    }
+    store_partials<1>(acc, 1, partials);
+    if (arrive_last(&ctrl->counter[2])) {
+        finish_sums(partials, 1, &ctrl->nrm2, &ctrl->counter[2]);
+        if (threadIdx.x == 0) givens_column(ctrl, k, m, ctrl->nrm2);
+    }
+}
+
+// ---- q_{k+1} = w / beta -------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_normalize(i64 N, T *__restrict__ w, const Ctrl *ctrl)
+{
+    const double s = ctrl->inv_beta;
+    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (p < N) w[p] = (T)((double)w[p] * s);
+}
+
+// ---- FP64 outer residual r = b - A x with ||r||^2 (Alg. 3, residual step) ----
+__global__ __launch_bounds__(kBlock) void k_resid64(i64 N, const double *__restrict__ offv,
+                                                    const int *__restrict__ offc,
+                                                    const double *__restrict__ diag,
+                                                    const double *__restrict__ x,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ r, double *partials,
+                                                    Ctrl *ctrl, int m)
+{
+    double acc[1] = {0.0};
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        double v = ldnt(diag + p) * x[p];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const i64 e = (i64)s * N + p;
+            v += ldnt(offv + e) * x[ldnt(offc + e)];
+        }
+        const double rv = b[p] - v;
+        r[p] = rv;
+        acc[0] += rv * rv;
+    }
+    store_partials<1>(acc, 1, partials);
+    if (arrive_last(&ctrl->counter[3])) {
+        finish_sums(partials, 1, &ctrl->nrm2, &ctrl->counter[3]);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const double rho = sqrt(ctrl->nrm2);
+            ctrl->rho = rho;
+            ctrl->inv_rho = rho > 0.0 ? 1.0 / rho : 0.0;
+            ctrl->nonfinite = !isfinite(rho);
+            ctrl->breakdown = 0;
+        }
+        // new cycle: t = (rho, 0, ..., 0)
+        for (int j = threadIdx.x; j < kMaxBasis; j += kBlock) ctrl->t[j] = 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0) ctrl->t[0] = ctrl->rho;
+    }
+}
+
+// ---- rho0 = ||b|| (Alg. 3, first step) -----------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_norm64(i64 N, const double *__restrict__ v,
+                                                   double *partials, Ctrl *ctrl)
+{
+    double acc[1] = {0.0};
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) acc[0] += v[p] * v[p];
+    store_partials<1>(acc, 1, partials);
+    if (arrive_last(&ctrl->counter[3])) {
+        finish_sums(partials, 1, &ctrl->nrm2, &ctrl->counter[3]);
+        if (threadIdx.x == 0) {
+            ctrl->rho0 = sqrt(ctrl->nrm2);
+            ctrl->nonfinite = !isfinite(ctrl->rho0);
+        }
+    }
+}
+
+// ---- q_1 = r / rho in the inner dtype --------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cast(i64 N, const double *__restrict__ r,
+                                                 const Ctrl *ctrl, T *__restrict__ q)
+{
+    const double s = ctrl->inv_rho;
+    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (p < N) q[p] = (T)(r[p] * s);
+}
+
+// ---- y = H(0:kk,0:kk)^{-1} t(0:kk) by back substitution (FP64, one thread) ----
+__global__ void k_trsm(Ctrl *c, int kk, int m)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int i = kk - 1; i >= 0; --i) {
+        double acc = c->t[i];
+        for (int j = i + 1; j < kk; ++j) acc -= c->H[(i64)j * (m + 1) + i] * c->y[j];
+        c->y[i] = acc / c->H[(i64)i * (m + 1) + i];
+    }
+}
+
+// ---- u = Q(:,0:kk) y ------------------------------------------------------------------------------
+template <typename T, int KB>
+__global__ __launch_bounds__(kBlock) void k_gemv(i64 N, const T *__restrict__ Q, int kk,
+                                                 const Ctrl *ctrl, T *__restrict__ u)
+{
+    double c[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) c[j] = j < kk ? ctrl->y[j] : 0.0;
+    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (p >= N) return;
+    double v = 0.0;
+#pragma unroll
+    for (int j = 0; j < KB; ++j)
+        if (j < kk) v += c[j] * (double)Q[(i64)j * N + p];
+    u[p] = (T)v;
+}
+
+// ---- x += z with the sum in FP64 (Alg. 3: the update must be double) ----
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_update(i64 N, const T *__restrict__ z, double *__restrict__ x)
+{
+    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (p < N) x[p] += (double)z[p];
+}
+
+// ---- streaming copy (bandwidth reference) -------------------------------------------------------------
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(kBlock) void k_copy(i64 n16, const u32x4 *__restrict__ src, u32x4 *__restrict__ dst)
+{
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 i = (i64)blockIdx.x * kBlock + threadIdx.x; i < n16; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+// =====================================================================================================
+// launchers
+static inline unsigned grid_n(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+#define HPGMX_KB_DISPATCH(kb, CALL)                  \
+    do {                                             \
+        if ((kb) <= 4) { constexpr int KB = 4; CALL; }        \
+        else if ((kb) <= 8) { constexpr int KB = 8; CALL; }   \
+        else if ((kb) <= 16) { constexpr int KB = 16; CALL; } \
+        else if ((kb) <= 32) { constexpr int KB = 32; CALL; } \
+        else { constexpr int KB = 64; CALL; }                 \
+    } while (0)
+
+template <typename V>
+static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, const void *Q,
+                       int kb, void *w, double *partials, Ctrl *ctrl, hipStream_t s)
+{
+    using T = typename VecOf2<V>::T;
+    const dim3 gr(red_blocks(A.g.N)), bl(kBlock);
+    HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, v, A.col, d,
+                                             (const T *)z, (const T *)Q, kb, (T *)w, partials, ctrl));
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, int kb, void *w,
+                     double *partials, Ctrl *ctrl, hipStream_t s)
+{
+    switch (p) {
+    case P64: spmv_dot_t(A, A.v64, A.d64, z, Q, kb, w, partials, ctrl, s); break;
+    case P32: spmv_dot_t(A, A.v32, A.d32, z, Q, kb, w, partials, ctrl, s); break;
+    case P16: spmv_dot_t(A, A.v16, A.d16, z, Q, kb, w, partials, ctrl, s); break;
+    case PB16: spmv_dot_t(A, A.vb16, A.db16, z, Q, kb, w, partials, ctrl, s); break;
+    }
+}
+
+void launch_cgs_dot(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
+                    hipStream_t s)
+{
+    const dim3 gr(red_blocks(N)), bl(kBlock);
+    if (p == P64)
+        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_dot<double, KB>), gr, bl, 0, s, N,
+                                                 (const double *)Q, kb, (double *)w, partials, ctrl));
+    else
+        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_dot<float, KB>), gr, bl, 0, s, N,
+                                                 (const float *)Q, kb, (float *)w, partials, ctrl));
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_cgs_norm(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
+                     int k, int m, hipStream_t s)
+{
+    const dim3 gr(red_blocks(N)), bl(kBlock);
+    if (p == P64)
+        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_norm<double, KB>), gr, bl, 0, s, N,
+                                                 (const double *)Q, kb, (double *)w, partials, ctrl,
+                                                 k, m));
+    else
+        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_norm<float, KB>), gr, bl, 0, s, N,
+                                                 (const float *)Q, kb, (float *)w, partials, ctrl,
+                                                 k, m));
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s)
+{
+    if (p == P64) hipLaunchKernelGGL(k_normalize<double>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (double *)w, ctrl);
+    else hipLaunchKernelGGL(k_normalize<float>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (float *)w, ctrl);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
+                    double *partials, Ctrl *ctrl, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_resid64, dim3(red_blocks(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.v64, A.col,
+                       A.d64, x, b, r, partials, ctrl, m);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_norm64, dim3(red_blocks(N)), dim3(kBlock), 0, s, N, v, partials, ctrl);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_cast(i64 N, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s)
+{
+    if (p == P64) hipLaunchKernelGGL(k_cast<double>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, r, ctrl, (double *)q);
+    else hipLaunchKernelGGL(k_cast<float>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, r, ctrl, (float *)q);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_trsm, dim3(1), dim3(64), 0, s, ctrl, kk, m);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_gemv(i64 N, Prec p, const void *Q, int kk, const Ctrl *ctrl, void *u, hipStream_t s)
+{
+    const dim3 gr(grid_n(N)), bl(kBlock);
+    if (p == P64)
+        HPGMX_KB_DISPATCH(kk, hipLaunchKernelGGL((k_gemv<double, KB>), gr, bl, 0, s, N,
+                                                 (const double *)Q, kk, ctrl, (double *)u));
+    else
+        HPGMX_KB_DISPATCH(kk, hipLaunchKernelGGL((k_gemv<float, KB>), gr, bl, 0, s, N,
+                                                 (const float *)Q, kk, ctrl, (float *)u));
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_update(i64 N, Prec p, const void *z, double *x, hipStream_t s)
+{
+    if (p == P64) hipLaunchKernelGGL(k_update<double>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (const double *)z, x);
+    else hipLaunchKernelGGL(k_update<float>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (const float *)z, x);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s)
+{
+    const i64 n16 = (i64)(bytes / 16);
+    const i64 b = (n16 + kBlock - 1) / kBlock;
+    const unsigned blocks = (unsigned)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+    hipLaunchKernelGGL(k_copy, dim3(blocks), dim3(kBlock), 0, s, n16, (const u32x4 *)src, (u32x4 *)dst);
+    HPGMX_LAUNCH_CHECK();
+}
+
+}  // namespace hpgmx

@@ -1,0 +1,324 @@
+// Stencil-side kernels: matrix generation, ordering permutations, ELL SpMV,
+// one colour of a multicolour Gauss-Seidel sweep, fused residual-restriction
+// and prolongation-correction.  All are HBM-bandwidth bound (no dense
+// contraction anywhere), so they are written for coalesced streaming: one
+// row per lane, slot-major ELL arrays read with non-temporal loads (each
+// matrix entry is used once per launch) and vector entries gathered through
+// the caches (each is reused by up to 26 rows).
+#include "hpgmx_internal.hpp"
+
+#include <stdexcept>
+
+namespace hpgmx {
+
+// ---- element access ---------------------------------------------------------
+template <typename V> struct VecOf { using T = float; };
+template <> struct VecOf<double> { using T = double; };
+
+template <typename V> __device__ __forceinline__ V ldm(const V *p) { return __builtin_nontemporal_load(p); }
+template <> __device__ __forceinline__ __half ldm<__half>(const __half *p)
+{
+    return __ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
+}
+template <> __device__ __forceinline__ bf16 ldm<bf16>(const bf16 *p)
+{
+    return __ushort_as_bfloat16(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
+}
+
+template <typename T, typename V> __device__ __forceinline__ T val(V v) { return (T)v; }
+template <> __device__ __forceinline__ float val<float, __half>(__half v) { return __half2float(v); }
+template <> __device__ __forceinline__ float val<float, bf16>(bf16 v) { return __bfloat162float(v); }
+
+__device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
+
+static inline unsigned grid_for(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+#define HPGMX_LAUNCH_CHECK()                                                    \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));  \
+    } while (0)
+
+// ---- geometry -----------------------------------------------------------------
+Geom make_geom(int nx, int ny, int nz)
+{
+    Geom g{};
+    g.nx = nx; g.ny = ny; g.nz = nz;
+    i64 o = 0;
+    for (int c = 0; c < 8; ++c) {
+        const int pi = c & 1, pj = (c >> 1) & 1, pk = ((c >> 2) & 1) ^ 1;
+        g.bx[c] = (nx - pi + 1) / 2;
+        g.by[c] = (ny - pj + 1) / 2;
+        g.bz[c] = (nz - pk + 1) / 2;
+        g.off[c] = o;
+        o += (i64)g.bx[c] * g.by[c] * g.bz[c];
+    }
+    g.off[8] = o;
+    g.N = o;
+    return g;
+}
+
+unsigned earlier_colour_mask(int c, bool forward)
+{
+    unsigned m = 0;
+    for (int s = 0; s < kSlots; ++s) {
+        int di, dj, dk;
+        slot_offset(s, di, dj, dk);
+        const int flip = (di & 1) | ((dj & 1) << 1) | ((dk & 1) << 2);
+        const int cn = c ^ flip;
+        if (forward ? cn < c : cn > c) m |= 1u << s;
+    }
+    return m;
+}
+
+// ---- generation -----------------------------------------------------------------
+// Entry of the 27-point operator for offset (di,dj,dk) (Sec. 2, Sec. 3):
+// 26 on the diagonal, -1 off it, with the x-neighbour entries shifted to
+// -1-beta (i-1) and -1+beta (i+1).
+__device__ inline double stencil_entry(double beta, int di, int dj, int dk)
+{
+    if (di == 0 && dj == 0 && dk == 0) return 26.0;
+    if (di < 0) return -1.0 - beta;
+    if (di > 0) return -1.0 + beta;
+    return -1.0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_generate(Geom g, double beta, int *col, double *v64,
+                                                     double *d64, float *v32, float *d32,
+                                                     __half *v16, __half *d16, bf16 *vb16,
+                                                     bf16 *db16)
+{
+    const i64 p = gtid();
+    if (p >= g.N) return;
+    int i, j, k;
+    from_internal(g, p, i, j, k);
+    const i64 N = g.N;
+    for (int s = 0; s < kSlots; ++s) {
+        int di, dj, dk;
+        slot_offset(s, di, dj, dk);
+        const int ii = i + di, jj = j + dj, kk = k + dk;
+        const bool in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
+        const double a = in ? stencil_entry(beta, di, dj, dk) : 0.0;
+        const i64 e = (i64)s * N + p;
+        if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)p;
+        if (v64) v64[e] = a;
+        if (v32) v32[e] = (float)a;
+        if (v16) v16[e] = __float2half((float)a);
+        if (vb16) vb16[e] = __float2bfloat16((float)a);
+    }
+    const double dg = stencil_entry(beta, 0, 0, 0);
+    if (d64) d64[p] = dg;
+    if (d32) d32[p] = (float)dg;
+    if (d16) d16[p] = __float2half((float)dg);
+    if (db16) db16[p] = __float2bfloat16((float)dg);
+}
+
+void launch_generate(const Matrix &A, double beta, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, beta, A.col,
+                       A.v64, A.d64, A.v32, A.d32, A.v16, A.d16, A.vb16, A.db16);
+    HPGMX_LAUNCH_CHECK();
+}
+
+// ---- natural <-> colour-blocked order ---------------------------------------------
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_nat2int(Geom g, const Ti *__restrict__ nat, To *__restrict__ in)
+{
+    const i64 I = gtid();
+    if (I >= g.N) return;
+    const int i = (int)(I % g.nx), j = (int)((I / g.nx) % g.ny), k = (int)(I / ((i64)g.nx * g.ny));
+    in[to_internal(g, i, j, k)] = (To)nat[I];
+}
+
+template <typename Ti, typename To>
+__global__ __launch_bounds__(kBlock) void k_int2nat(Geom g, const Ti *__restrict__ in, To *__restrict__ nat)
+{
+    const i64 I = gtid();
+    if (I >= g.N) return;
+    const int i = (int)(I % g.nx), j = (int)((I / g.nx) % g.ny), k = (int)(I / ((i64)g.nx * g.ny));
+    nat[I] = (To)in[to_internal(g, i, j, k)];
+}
+
+void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s)
+{
+    const dim3 gr(grid_for(g.N)), bl(kBlock);
+    const bool s64 = src == P64, d64 = dst == P64;
+    if (s64 && d64) hipLaunchKernelGGL((k_nat2int<double, double>), gr, bl, 0, s, g, (const double *)nat, (double *)in);
+    else if (s64) hipLaunchKernelGGL((k_nat2int<double, float>), gr, bl, 0, s, g, (const double *)nat, (float *)in);
+    else if (d64) hipLaunchKernelGGL((k_nat2int<float, double>), gr, bl, 0, s, g, (const float *)nat, (double *)in);
+    else hipLaunchKernelGGL((k_nat2int<float, float>), gr, bl, 0, s, g, (const float *)nat, (float *)in);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s)
+{
+    const dim3 gr(grid_for(g.N)), bl(kBlock);
+    const bool s64 = src == P64, d64 = dst == P64;
+    if (s64 && d64) hipLaunchKernelGGL((k_int2nat<double, double>), gr, bl, 0, s, g, (const double *)in, (double *)nat);
+    else if (s64) hipLaunchKernelGGL((k_int2nat<double, float>), gr, bl, 0, s, g, (const double *)in, (float *)nat);
+    else if (d64) hipLaunchKernelGGL((k_int2nat<float, double>), gr, bl, 0, s, g, (const float *)in, (double *)nat);
+    else hipLaunchKernelGGL((k_int2nat<float, float>), gr, bl, 0, s, g, (const float *)in, (float *)nat);
+    HPGMX_LAUNCH_CHECK();
+}
+
+// ---- SpMV -------------------------------------------------------------------------------
+// y = A x over all N rows (Sec. 3.2 ELL SpMV).
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_spmv(i64 N, const V *__restrict__ offv,
+                                                 const int *__restrict__ offc,
+                                                 const V *__restrict__ diag,
+                                                 const typename VecOf<V>::T *__restrict__ x,
+                                                 typename VecOf<V>::T *__restrict__ y)
+{
+    using T = typename VecOf<V>::T;
+    const i64 p = gtid();
+    if (p >= N) return;
+    T acc = val<T>(ldm(diag + p)) * x[p];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        const i64 e = (i64)s * N + p;
+        acc += val<T>(ldm(offv + e)) * x[ldm(offc + e)];
+    }
+    y[p] = acc;
+}
+
+template <typename V>
+static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void *y, hipStream_t s)
+{
+    using T = typename VecOf<V>::T;
+    hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, v, A.col, d,
+                       (const T *)x, (T *)y);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s)
+{
+    switch (p) {
+    case P64: spmv_t(A, A.v64, A.d64, x, y, s); break;
+    case P32: spmv_t(A, A.v32, A.d32, x, y, s); break;
+    case P16: spmv_t(A, A.v16, A.d16, x, y, s); break;
+    case PB16: spmv_t(A, A.vb16, A.db16, x, y, s); break;
+    }
+}
+
+// ---- Gauss-Seidel, one colour ---------------------------------------------------------------
+// Rows p in [row0, row0 + cnt) of one colour:
+//   z_p <- (r_p - sum_{s in mask} a_{p,s} z_{col(p,s)}) / a_pp
+// (relaxation form of eq. (1)).  Rows of one colour never couple, so the
+// in-place update is race free.  Slots outside `mask` are skipped: on a sweep
+// from a zero guess they point at colours that still hold zero.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, unsigned mask,
+                                               const V *__restrict__ offv,
+                                               const int *__restrict__ offc,
+                                               const V *__restrict__ diag,
+                                               const typename VecOf<V>::T *__restrict__ r,
+                                               typename VecOf<V>::T *z)
+{
+    using T = typename VecOf<V>::T;
+    const i64 t = gtid();
+    if (t >= cnt) return;
+    const i64 p = row0 + t;
+    T acc = r[p];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (mask & (1u << s)) {
+            const i64 e = (i64)s * N + p;
+            acc -= val<T>(ldm(offv + e)) * z[ldm(offc + e)];
+        }
+    }
+    z[p] = acc / val<T>(ldm(diag + p));
+}
+
+template <typename V>
+static void gs_t(const Matrix &A, const V *v, const V *d, int c, unsigned mask, const void *r,
+                 void *z, hipStream_t s)
+{
+    using T = typename VecOf<V>::T;
+    const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
+    if (cnt == 0) return;
+    hipLaunchKernelGGL(k_gs<V>, dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N, mask, v,
+                       A.col, d, (const T *)r, (T *)z);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_gs_colour(const Matrix &A, Prec p, int c, unsigned mask, const void *r, void *z,
+                      hipStream_t s)
+{
+    switch (p) {
+    case P64: gs_t(A, A.v64, A.d64, c, mask, r, z, s); break;
+    case P32: gs_t(A, A.v32, A.d32, c, mask, r, z, s); break;
+    case P16: gs_t(A, A.v16, A.d16, c, mask, r, z, s); break;
+    case PB16: gs_t(A, A.vb16, A.db16, c, mask, r, z, s); break;
+    }
+}
+
+// ---- fused residual-restriction (eq. (6)) ------------------------------------------------------
+// The colour-4 block of the fine level holds the injection points in the
+// coarse level's natural order: row q of that block is coarse point
+// (q % cx, (q / cx) % cy, q / (cx cy)).  Only those rows are evaluated.
+template <typename V>
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const V *__restrict__ offv,
+                                                     const int *__restrict__ offc,
+                                                     const V *__restrict__ diag,
+                                                     const typename VecOf<V>::T *__restrict__ r,
+                                                     const typename VecOf<V>::T *__restrict__ z,
+                                                     typename VecOf<V>::T *__restrict__ rc)
+{
+    using T = typename VecOf<V>::T;
+    const i64 q = gtid();
+    if (q >= gc.N) return;
+    const i64 N = gf.N, p = gf.off[4] + q;
+    T acc = val<T>(ldm(diag + p)) * z[p];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        const i64 e = (i64)s * N + p;
+        acc += val<T>(ldm(offv + e)) * z[ldm(offc + e)];
+    }
+    const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
+    rc[to_internal(gc, I, J, K)] = r[p] - acc;
+}
+
+template <typename V>
+static void restrict_t(const Matrix &A, const Geom &gc, const V *v, const V *d, const void *r,
+                       const void *z, void *rc, hipStream_t s)
+{
+    using T = typename VecOf<V>::T;
+    hipLaunchKernelGGL(k_restrict<V>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc, v, A.col,
+                       d, (const T *)r, (const T *)z, (T *)rc);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
+                     void *rc, hipStream_t s)
+{
+    switch (p) {
+    case P64: restrict_t(Af, gc, Af.v64, Af.d64, r, z, rc, s); break;
+    case P32: restrict_t(Af, gc, Af.v32, Af.d32, r, z, rc, s); break;
+    case P16: restrict_t(Af, gc, Af.v16, Af.d16, r, z, rc, s); break;
+    case PB16: restrict_t(Af, gc, Af.vb16, Af.db16, r, z, rc, s); break;
+    }
+}
+
+// ---- prolongation-correction: z += P zc, P = R^T -------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T *__restrict__ zc, T *__restrict__ z)
+{
+    const i64 q = gtid();
+    if (q >= gc.N) return;
+    const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
+    z[gf.off[4] + q] += zc[to_internal(gc, I, J, K)];
+}
+
+void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void *z, hipStream_t s)
+{
+    if (p == P64)
+        hipLaunchKernelGGL(k_prolong<double>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, gf, gc,
+                           (const double *)zc, (double *)z);
+    else
+        hipLaunchKernelGGL(k_prolong<float>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, gf, gc,
+                           (const float *)zc, (float *)z);
+    HPGMX_LAUNCH_CHECK();
+}
+
+}  // namespace hpgmx

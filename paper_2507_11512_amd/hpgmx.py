@@ -1,0 +1,276 @@
+"""Thin ctypes binding of libhpgmx.so (argument marshalling only).
+
+Every function has the name of the C entry point it wraps (without the
+``hpgmx_`` prefix) and takes torch tensors on the GPU; the data pointers and
+the current HIP stream are handed to the library as plain pointers.  All
+arithmetic runs in the library's HIP kernels.  If the library has not been
+built this module raises ImportError: there is no fallback path.
+"""
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhpgmx.so")
+
+F64, F32, F16, BF16 = 0, 1, 2, 3
+GS_FORWARD, GS_BACKWARD, GS_SYMMETRIC = 0, 1, 2
+SOLVE_PROFILE = 1
+
+K_GS, K_GS_ZERO, K_RESTRICT, K_PROLONG, K_SPMV_DOT, K_CGS_DOT, K_CGS_NORM, K_NORMALIZE, \
+    K_RESID64, K_CAST, K_TRSM, K_GEMV, K_UPDATE, K_PERMUTE = range(14)
+K_COUNT = 14
+KERNEL_NAMES = ["gs", "gs_zero", "restrict", "prolong", "spmv_dot", "cgs_dot", "cgs_norm",
+                "normalize", "resid64", "cast", "trsm", "gemv", "update", "permute"]
+
+STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
+
+EXPORTS = ["hpgmx_setup_problem", "hpgmx_workspace_bytes", "hpgmx_bind_workspace",
+           "hpgmx_mg_setup", "hpgmx_gmres_ir_solve", "hpgmx_spmv", "hpgmx_smooth",
+           "hpgmx_vcycle", "hpgmx_restrict_residual", "hpgmx_prolong_add",
+           "hpgmx_rhs_from_x", "hpgmx_profile_get", "hpgmx_stream_copy", "hpgmx_destroy",
+           "hpgmx_last_error"]
+
+
+class ProblemDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("beta", C.c_double)]
+
+
+class MgDesc(C.Structure):
+    _fields_ = [("levels", C.c_int), ("pre_sweeps", C.c_int), ("post_sweeps", C.c_int),
+                ("coarsest_sweeps", C.c_int), ("sweep", C.c_int)]
+
+
+class SolveDesc(C.Structure):
+    _fields_ = [("restart", C.c_int), ("max_iters", C.c_int), ("tol", C.c_double),
+                ("inner_dtype", C.c_int), ("res_hist_host", C.POINTER(C.c_double)),
+                ("res_hist_len", C.c_int), ("flags", C.c_int)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("restarts", C.c_int), ("converged", C.c_int),
+                ("breakdown", C.c_int), ("rho0", C.c_double), ("final_rel_res", C.c_double),
+                ("est_rel_res", C.c_double), ("solve_ms", C.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                          "(or python paper_2507_11512_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    H = C.c_void_p
+    sig = {
+        "hpgmx_setup_problem": [C.POINTER(ProblemDesc), vp, C.POINTER(H)],
+        "hpgmx_workspace_bytes": [H, C.POINTER(MgDesc), i, C.c_uint, C.POINTER(C.c_size_t)],
+        "hpgmx_bind_workspace": [H, vp, C.c_size_t],
+        "hpgmx_mg_setup": [H, C.POINTER(MgDesc)],
+        "hpgmx_gmres_ir_solve": [H, vp, vp, C.POINTER(SolveDesc), C.POINTER(SolveStats)],
+        "hpgmx_spmv": [H, i, i, vp, vp],
+        "hpgmx_smooth": [H, i, i, i, vp, vp, i],
+        "hpgmx_vcycle": [H, i, vp, vp],
+        "hpgmx_restrict_residual": [H, i, i, vp, vp, vp],
+        "hpgmx_prolong_add": [H, i, i, vp, vp],
+        "hpgmx_rhs_from_x": [H, vp, vp],
+        "hpgmx_profile_get": [H, i, i, C.POINTER(d), C.POINTER(C.c_longlong)],
+        "hpgmx_stream_copy": [H, vp, vp, C.c_size_t, i, C.POINTER(d)],
+        "hpgmx_destroy": [H],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.hpgmx_last_error.argtypes = [H]
+    lib.hpgmx_last_error.restype = C.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+class HpgmxError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(h, st):
+    if st != 0:
+        msg = lib.hpgmx_last_error(h) if h else b""
+        raise HpgmxError(st, (msg or b"").decode())
+
+
+def _ptr(t):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous GPU tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _vec_dtype(dtype):
+    import torch
+    return torch.float64 if dtype == F64 else torch.float32
+
+
+@dataclass
+class Stats:
+    iters: int
+    restarts: int
+    converged: bool
+    breakdown: bool
+    rho0: float
+    final_rel_res: float
+    est_rel_res: float
+    solve_ms: float
+
+
+# ---- one function per C entry point ------------------------------------------------------
+def setup_problem(nx, ny, nz, beta=0.5, stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    h = C.c_void_p()
+    desc = ProblemDesc(int(nx), int(ny), int(nz), float(beta))
+    _check(None, lib.hpgmx_setup_problem(C.byref(desc), C.c_void_p(stream.cuda_stream), C.byref(h)))
+    return h
+
+
+def workspace_bytes(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD, restart=30,
+                    dtype_mask=(1 << F64) | (1 << F32)):
+    mg = MgDesc(levels, pre, post, coarsest, sweep)
+    out = C.c_size_t()
+    _check(h, lib.hpgmx_workspace_bytes(h, C.byref(mg), int(restart), int(dtype_mask), C.byref(out)))
+    return out.value
+
+
+def bind_workspace(h, tensor):
+    _check(h, lib.hpgmx_bind_workspace(h, _ptr(tensor), tensor.numel() * tensor.element_size()))
+
+
+def mg_setup(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD):
+    mg = MgDesc(int(levels), int(pre), int(post), int(coarsest), int(sweep))
+    _check(h, lib.hpgmx_mg_setup(h, C.byref(mg)))
+
+
+def gmres_ir_solve(h, b, x, restart=30, max_iters=10000, tol=1e-9, inner_dtype=F32,
+                   hist_len=0, profile=False):
+    """Solves in place: x holds x0 on entry and the solution on exit."""
+    import numpy as np
+    hist = np.zeros(max(hist_len, 1))
+    desc = SolveDesc(int(restart), int(max_iters), float(tol), int(inner_dtype),
+                     hist.ctypes.data_as(C.POINTER(C.c_double)) if hist_len > 0 else None,
+                     int(hist_len), SOLVE_PROFILE if profile else 0)
+    st = SolveStats()
+    _check(h, lib.hpgmx_gmres_ir_solve(h, _ptr(b), _ptr(x), C.byref(desc), C.byref(st)))
+    s = Stats(st.iters, st.restarts, bool(st.converged), bool(st.breakdown), st.rho0,
+              st.final_rel_res, st.est_rel_res, st.solve_ms)
+    if hist_len > 0:
+        return s, hist[:min(st.iters, hist_len)].copy()
+    return s
+
+
+def spmv(h, level, dtype, x, y):
+    _check(h, lib.hpgmx_spmv(h, int(level), int(dtype), _ptr(x), _ptr(y)))
+
+
+def smooth(h, level, dtype, sweep, r, z, zero_guess=False):
+    _check(h, lib.hpgmx_smooth(h, int(level), int(dtype), int(sweep), _ptr(r), _ptr(z),
+                               int(bool(zero_guess))))
+
+
+def vcycle(h, dtype, r, z):
+    _check(h, lib.hpgmx_vcycle(h, int(dtype), _ptr(r), _ptr(z)))
+
+
+def restrict_residual(h, level, dtype, r, z, r_coarse):
+    _check(h, lib.hpgmx_restrict_residual(h, int(level), int(dtype), _ptr(r), _ptr(z),
+                                          _ptr(r_coarse)))
+
+
+def prolong_add(h, level, dtype, z_coarse, z):
+    _check(h, lib.hpgmx_prolong_add(h, int(level), int(dtype), _ptr(z_coarse), _ptr(z)))
+
+
+def rhs_from_x(h, x, b):
+    _check(h, lib.hpgmx_rhs_from_x(h, _ptr(x), _ptr(b)))
+
+
+def profile_get(h, kernel, level=0):
+    ms, n = C.c_double(), C.c_longlong()
+    _check(h, lib.hpgmx_profile_get(h, int(kernel), int(level), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def stream_copy(h, src, dst, nbytes, reps=20):
+    ms = C.c_double()
+    _check(h, lib.hpgmx_stream_copy(h, _ptr(src), _ptr(dst), int(nbytes), int(reps), C.byref(ms)))
+    return ms.value
+
+
+def destroy(h):
+    if h:
+        _check(None, lib.hpgmx_destroy(h))
+
+
+def last_error(h):
+    return (lib.hpgmx_last_error(h) or b"").decode()
+
+
+# ---- convenience object -------------------------------------------------------------------
+class Problem:
+    """One stencil problem with its multigrid hierarchy on the current GPU.
+
+    >>> P = Problem(128, beta=0.5, levels=4, sweep='forward')
+    >>> x, stats = P.solve(b, tol=1e-9, restart=30, precision='mxp')
+    """
+
+    _SWEEPS = {"forward": GS_FORWARD, "backward": GS_BACKWARD, "symmetric": GS_SYMMETRIC}
+    _PREC = {"fp64": F64, "mxp": F32, "fp32": F32, "fp16": F16, "bf16": BF16}
+
+    def __init__(self, n, beta=0.5, levels=4, sweep="forward", pre=1, post=1, coarsest=1,
+                 stream=None, workspace=None):
+        import torch
+        self.dims = (n, n, n) if isinstance(n, int) else tuple(n)
+        self.N = self.dims[0] * self.dims[1] * self.dims[2]
+        self.levels = levels
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.h = setup_problem(*self.dims, beta=beta, stream=self.stream)
+        sw = self._SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
+        try:
+            if workspace is not None:
+                bind_workspace(self.h, workspace)
+                self.workspace = workspace
+            mg_setup(self.h, levels, pre, post, coarsest, sw)
+        except Exception:
+            destroy(self.h)
+            self.h = None
+            raise
+
+    def level_dims(self, level):
+        return tuple(d >> level for d in self.dims)
+
+    def rhs_from_x(self, x):
+        import torch
+        b = torch.empty_like(x, dtype=torch.float64)
+        rhs_from_x(self.h, x, b)
+        return b
+
+    def solve(self, b, x0=None, tol=1e-9, restart=30, max_iters=10000, precision="mxp",
+              hist_len=0, profile=False):
+        import torch
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        prec = self._PREC[precision] if isinstance(precision, str) else int(precision)
+        with torch.cuda.stream(self.stream):
+            out = gmres_ir_solve(self.h, b, x, restart, max_iters, tol, prec, hist_len, profile)
+        return (x, *out) if isinstance(out, tuple) else (x, out)
+
+    def close(self):
+        if self.h:
+            destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

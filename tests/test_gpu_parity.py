@@ -1,0 +1,279 @@
+"""GPU parity of every C-ABI entry point against the CPU oracle.
+
+Tolerances are derived from the arithmetic (u = unit roundoff of the dtype,
+gamma_n = n u / (1 - n u), Higham's dot-product bound):
+  * SpMV, residual-restriction: |y - y_ref|_i <= 2 gamma_28 (|r| + |A||x|)_i,
+    the oracle evaluated in FP64 on the same (FP32-rounded) inputs;
+  * one Gauss-Seidel colour pass adds at most gamma_28 S (S the row scale
+    (|r_i| + sum |a_ij||z_j|) / a_ii) to the largest error so far, because
+    the matrix is weakly diagonally dominant, so after P passes
+    ||z - z_ref||_inf <= 2 P gamma_28 max S;
+  * prolongation is one addition per entry: 2u |z + zc|;
+  * FP64 V-cycle: normwise 1e-12; FP32 V-cycle: normwise 1e-4 (about 60
+    relaxation/restriction stages of relative error <= gamma_28 each);
+  * solves: the bar of the target -- final FP64 relative residual <= 1e-9
+    and ||x - x_oracle|| / ||x_oracle|| <= 1e-8.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_11512_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U = {0: 2.0 ** -53, 1: 2.0 ** -24, 2: 2.0 ** -24, 3: 2.0 ** -24}
+
+
+def gamma(n, u):
+    return n * u / (1.0 - n * u)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def hp(torch_cuda):
+    from paper_2507_11512_amd import hpgmx
+    return hpgmx
+
+
+_problems = {}
+
+
+def problem(hp, dims, levels, sweep="forward"):
+    key = (tuple(dims), levels, sweep)
+    if key not in _problems:
+        print(f"[setup] dims={dims} levels={levels} sweep={sweep}", flush=True)
+        _problems[key] = hp.Problem(dims, beta=0.5, levels=levels, sweep=sweep)
+    return _problems[key]
+
+
+def dev(a, dtype):
+    import torch
+    t = torch.float64 if dtype == 0 else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", t)
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def rnd(a, dtype):
+    return a if dtype == 0 else a.astype(np.float32).astype(np.float64)
+
+
+def ldims(dims, level):
+    return tuple(int(d) >> level for d in dims)
+
+
+GRIDS = [((16, 16, 16), 3), ((24, 20, 16), 3), ((64, 64, 64), 4), ((12, 12, 12), 2)]
+
+
+@pytest.mark.parametrize("dims,levels", GRIDS)
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3])
+def test_spmv_every_level(hp, dims, levels, dtype):
+    P = problem(hp, dims, levels)
+    for lvl in range(levels):
+        d = ldims(dims, lvl)
+        x = rnd(inputs.uniform(d, 100 + lvl), dtype)
+        y = dev(np.zeros(x.size), dtype)
+        hp.spmv(P.h, lvl, dtype, dev(x, dtype), y)
+        got = host(y)
+        ref = oracle.spmv(d, x)
+        tol = 2 * gamma(28, U[dtype]) * oracle.absrow(d, x) + 1e-300
+        assert np.all(np.abs(got - ref) <= tol), (lvl, np.max(np.abs(got - ref) / tol))
+
+
+def _gs_tol(d, r, z_in, z_ref, dtype, passes):
+    zmax = np.maximum(np.abs(z_in), np.abs(z_ref))
+    S = (np.abs(r) + oracle.absrow(d, zmax) - 26.0 * zmax) / 26.0
+    return 2 * passes * gamma(28, U[dtype]) * S.max()
+
+
+@pytest.mark.parametrize("dims,levels", GRIDS[:3])
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("sweep", [0, 1, 2])
+@pytest.mark.parametrize("zero", [False, True])
+def test_smooth_every_level(hp, dims, levels, dtype, sweep, zero):
+    P = problem(hp, dims, levels)
+    for lvl in range(levels):
+        d = ldims(dims, lvl)
+        r = rnd(inputs.uniform(d, 200 + lvl), dtype)
+        z0 = np.zeros(r.size) if zero else rnd(inputs.uniform(d, 300 + lvl), dtype)
+        zt = dev(z0 if not zero else inputs.uniform(d, 7), dtype)  # contents ignored when zero
+        hp.smooth(P.h, lvl, dtype, sweep, dev(r, dtype), zt, zero_guess=zero)
+        got = host(zt)
+        ref = oracle.gs(d, r, z0, sweep)
+        tol = _gs_tol(d, r, z0, ref, dtype, 16 if sweep == 2 else 8)
+        assert np.max(np.abs(got - ref)) <= tol, (lvl, np.max(np.abs(got - ref)), tol)
+
+
+@pytest.mark.parametrize("dims,levels", GRIDS)
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3])
+def test_restrict_and_prolong_every_level(hp, dims, levels, dtype):
+    P = problem(hp, dims, levels)
+    vt = 0 if dtype == 0 else 1
+    for lvl in range(levels - 1):
+        d, dc = ldims(dims, lvl), ldims(dims, lvl + 1)
+        r = rnd(inputs.uniform(d, 400 + lvl), dtype)
+        z = rnd(inputs.uniform(d, 500 + lvl), dtype)
+        rc = dev(np.zeros(int(np.prod(dc))), dtype)
+        hp.restrict_residual(P.h, lvl, dtype, dev(r, dtype), dev(z, dtype), rc)
+        ref = oracle.restrict_fused(d, r, z)
+        scale = oracle.inject(d, np.abs(r) + oracle.absrow(d, z))
+        assert np.all(np.abs(host(rc) - ref) <= 2 * gamma(28, U[dtype]) * scale + 1e-300)
+        zc = rnd(inputs.uniform(dc, 600 + lvl), vt)
+        zt = dev(z, dtype)
+        hp.prolong_add(P.h, lvl, dtype, dev(zc, dtype), zt)
+        ref = oracle.prolong_add(d, zc, z)
+        assert np.all(np.abs(host(zt) - ref) <= 2 * U[dtype] * np.abs(ref))
+
+
+@pytest.mark.parametrize("dims,levels,sweep", [((16, 16, 16), 3, "symmetric"),
+                                               ((16, 16, 16), 3, "forward"),
+                                               ((24, 20, 16), 3, "forward"),
+                                               ((64, 64, 64), 4, "forward"),
+                                               ((8, 8, 8), 1, "forward")])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_vcycle(hp, dims, levels, sweep, dtype):
+    P = problem(hp, dims, levels, sweep)
+    r = rnd(inputs.uniform(dims, 700), dtype)
+    z = dev(np.zeros(r.size), dtype)
+    hp.vcycle(P.h, dtype, dev(r, dtype), z)
+    ref = oracle.vcycle(dims, r, levels, 1, 1, 1, {"forward": 0, "symmetric": 2}[sweep])
+    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    assert err <= (1e-12 if dtype == 0 else 1e-4), err
+
+
+def test_rhs_from_x(hp):
+    dims = (24, 20, 16)
+    P = problem(hp, dims, 3)
+    x = inputs.uniform(dims, 800)
+    b = P.rhs_from_x(dev(x, 0))
+    ref = oracle.spmv(dims, x)
+    assert np.all(np.abs(host(b) - ref) <= 2 * gamma(28, U[0]) * oracle.absrow(dims, x))
+
+
+def _solve_pair(hp, dims, levels, sweep, precision, restart=30, x0=None, tol=1e-9):
+    P = problem(hp, dims, levels, sweep)
+    b = oracle.spmv(dims, inputs.ones(dims))
+    xg, st = P.solve(dev(b, 0), None if x0 is None else dev(x0, 0), tol=tol, restart=restart,
+                     precision=precision)
+    x = host(xg)
+    sw = {"forward": 0, "symmetric": 2}[sweep]
+    xo, sto = oracle.gmres_ir(dims, b, x0=x0, levels=levels, sweep=sw, restart=restart, tol=tol,
+                              f32=(precision != "fp64"))
+    res = np.linalg.norm(b - oracle.spmv(dims, x)) / np.linalg.norm(b)
+    print(f"[solve] dims={dims} L={levels} {sweep} {precision} m={restart}: gpu iters={st.iters} "
+          f"restarts={st.restarts} res={res:.3e} | oracle iters={sto.iters}", flush=True)
+    return x, st, xo, sto, res
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mxp"])
+def test_solve_tiny_config(hp, precision):
+    dims = (16, 16, 16)
+    x, st, xo, sto, res = _solve_pair(hp, dims, 3, "symmetric", precision)
+    assert st.converged and st.final_rel_res <= 1e-9 and res <= 1e-9
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    if precision == "fp64":
+        assert abs(st.iters - sto.iters) <= 2
+    else:
+        assert abs(st.iters - sto.iters) <= 2 + sto.iters // 10
+
+
+@pytest.mark.parametrize("dims,levels", [((32, 32, 32), 4), ((24, 20, 16), 3)])
+@pytest.mark.parametrize("precision", ["fp64", "mxp"])
+def test_solve_forward(hp, dims, levels, precision):
+    x, st, xo, sto, res = _solve_pair(hp, dims, levels, "forward", precision)
+    assert st.converged and res <= 1e-9
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    if precision == "fp64":
+        assert abs(st.iters - sto.iters) <= 2
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mxp"])
+def test_solve_forced_restarts_and_random_start(hp, precision):
+    dims = (16, 16, 16)
+    x, st, xo, sto, res = _solve_pair(hp, dims, 3, "forward", precision, restart=5,
+                                      x0=inputs.random_x0(dims))
+    assert st.converged and st.restarts >= 3 and res <= 1e-9
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+    if precision == "fp64":
+        assert abs(st.iters - sto.iters) <= 2
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_solve_16bit_matrix(hp, precision):
+    dims = (32, 32, 32)
+    x, st, xo, sto, res = _solve_pair(hp, dims, 4, "forward", precision)
+    assert st.converged and res <= 1e-9
+    assert np.linalg.norm(x - xo) / np.linalg.norm(xo) <= 1e-8
+
+
+def test_solve_edge_cases(hp):
+    import torch
+    dims = (16, 16, 16)
+    P = problem(hp, dims, 3)
+    n = P.N
+    x, st = P.solve(torch.zeros(n, dtype=torch.float64, device="cuda"))
+    assert st.converged and st.iters == 0 and torch.all(x == 0)
+    b = dev(oracle.spmv(dims, inputs.ones(dims)), 0)
+    x, st = P.solve(b, max_iters=3)
+    assert not st.converged and st.iters == 3
+    x, st = P.solve(b, max_iters=0)
+    assert not st.converged and st.iters == 0 and torch.all(x == 0)
+    bad = b.clone()
+    bad[17] = float("nan")
+    with pytest.raises(hp.HpgmxError) as e:
+        P.solve(bad)
+    assert e.value.status == -5
+    with pytest.raises(hp.HpgmxError) as e:
+        P.solve(b, restart=64)
+    assert e.value.status == -1
+    # the handle stays usable after EINVAL / ENONFINITE
+    x, st = P.solve(b, precision="fp64")
+    assert st.converged
+
+
+def test_setup_errors(hp):
+    with pytest.raises(hp.HpgmxError):
+        hp.Problem((20, 16, 16), levels=4)        # 20 not divisible by 8
+    with pytest.raises(hp.HpgmxError):
+        hp.Problem((8, 8, 8), levels=4)           # coarsest level 1^3
+    with pytest.raises(hp.HpgmxError):
+        hp.Problem((8, 8, 8), levels=9)
+    P = problem(hp, (16, 16, 16), 3)
+    import torch
+    v = torch.zeros(P.N, dtype=torch.float32, device="cuda")
+    with pytest.raises(hp.HpgmxError):
+        hp.spmv(P.h, 3, 1, v, v.clone())          # level out of range
+    with pytest.raises(hp.HpgmxError):
+        hp.restrict_residual(P.h, 2, 1, v, v, v)  # no coarser level
+    with pytest.raises(hp.HpgmxError):
+        hp.spmv(P.h, 0, 7, v, v.clone())          # bad dtype
+
+
+def test_bound_workspace_matches_owned_memory(hp):
+    import torch
+    dims = (32, 32, 32)
+    h = hp.setup_problem(*dims, beta=0.5)
+    nbytes = hp.workspace_bytes(h, levels=4, restart=30, dtype_mask=(1 << 0) | (1 << 1))
+    ws = torch.empty(nbytes // 8 + 64, dtype=torch.float64, device="cuda")
+    off = (-ws.data_ptr()) % 256
+    ws_view = ws.view(torch.uint8)[off:off + nbytes]
+    hp.bind_workspace(h, ws_view)
+    hp.mg_setup(h, 4)
+    b = dev(oracle.spmv(dims, inputs.ones(dims)), 0)
+    x = torch.zeros_like(b)
+    st = hp.gmres_ir_solve(h, b, x, inner_dtype=1)
+    ref = problem(hp, dims, 4)
+    x2, st2 = ref.solve(b, precision="mxp")
+    hp.destroy(h)
+    assert st.converged and st.iters == st2.iters
+    assert torch.equal(x, x2)
