@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <stdexcept>
@@ -38,7 +39,8 @@ struct Level {
 
 struct Krylov {
     int m = 0;
-    void *Q = nullptr;  // (m + 1) columns of N
+    i64 ldq = 0;        // leading dimension of Q (N rounded up, plus a skew)
+    void *Q = nullptr;  // (m + 1) columns of ldq
     void *z = nullptr;
     void *u = nullptr;
 };
@@ -145,21 +147,47 @@ struct ProfScope {
 };
 
 // ---- allocation plan ---------------------------------------------------------------------
+// Leading dimension of the Krylov basis: N rounded up to 64 elements plus a
+// skew (HPGMX_LDQ_PAD overrides the default for layout studies).
+i64 krylov_ldq(i64 N)
+{
+    i64 pad = kDefaultLdqPad;
+    const char *e = std::getenv("HPGMX_LDQ_PAD");
+    if (e && *e) {
+        const long v = std::atol(e);
+        if (v >= 0 && v <= (1 << 20)) pad = v;
+    }
+    return (N + 63) / 64 * 64 + pad;
+}
+
+// ELL chunk size (log2 rows per chunk, 0 = slot-major over the whole
+// matrix).  HPGMX_ELL_CHUNK_LOG2 overrides the default for layout studies.
+int ell_chunk_log2()
+{
+    const char *e = std::getenv("HPGMX_ELL_CHUNK_LOG2");
+    if (e && *e) {
+        const int v = std::atoi(e);
+        if (v >= 0 && v <= 16) return v;
+    }
+    return kDefaultEllChunkLog2;
+}
+
+
 void alloc_matrix_prec(hpgmx_ctx *c, Matrix &A, Prec p)
 {
-    const size_t N = (size_t)A.g.N;
+    const size_t N = (size_t)A.g.N, E = (size_t)ell_entries(A.g.N, A.clog2);
     switch (p) {
     case P64:
-        if (!A.v64) { A.v64 = (double *)c->dalloc(kSlots * N * 8); A.d64 = (double *)c->dalloc(N * 8); }
+        if (!A.v64) { A.v64 = (double *)c->dalloc(E * 8); A.d64 = (double *)c->dalloc(N * 8); }
         break;
     case P32:
-        if (!A.v32) { A.v32 = (float *)c->dalloc(kSlots * N * 4); A.d32 = (float *)c->dalloc(N * 4); }
+        if (!A.v32) { A.v32 = (float *)c->dalloc(E * 4); A.d32 = (float *)c->dalloc(N * 4); }
         break;
     case P16:
-        if (!A.v16) { A.v16 = (__half *)c->dalloc(kSlots * N * 2); A.d16 = (__half *)c->dalloc(N * 2); }
+        if (!A.v16) { A.v16 = (__half *)c->dalloc(E * 2); A.d16 = (__half *)c->dalloc(N * 2); }
         break;
     case PB16:
-        if (!A.vb16) { A.vb16 = (bf16 *)c->dalloc(kSlots * N * 2); A.db16 = (bf16 *)c->dalloc(N * 2); }
+        if (!A.vb16) { A.vb16 = (bf16 *)c->dalloc(E * 2); A.db16 = (bf16 *)c->dalloc(N * 2); }
         break;
     }
 }
@@ -236,7 +264,8 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
             for (auto it = c->owned.begin(); it != c->owned.end(); ++it)
                 if (*it == K.Q) { (void)hipFree(K.Q); c->owned.erase(it); break; }
         }
-        K.Q = c->dalloc(N0 * (m + 1) * vec_bytes(p));
+        K.ldq = krylov_ldq((i64)N0);
+        K.Q = c->dalloc((size_t)K.ldq * (m + 1) * vec_bytes(p));
         K.m = m;
     }
     if (!K.z) {
@@ -256,12 +285,13 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
     const size_t N0 = (size_t)nx * ny * nz;
     for (int l = 0; l < mg.levels; ++l) {
         const size_t N = (size_t)nx * ny * nz;
-        add(kSlots * N * 4);                              // columns
+        const size_t E = (size_t)ell_entries((i64)N, ell_chunk_log2());
+        add(E * 4);                                       // columns
         for (int p = 0; p < 4; ++p) {
             const bool want = (mask >> p) & 1u || p == P64;  // FP64 always (outer residual)
             if (!want) continue;
             const size_t vb = p == P64 ? 8 : p == P32 ? 4 : 2;
-            add(kSlots * N * vb);
+            add(E * vb);
             add(N * vb);
         }
         if (l >= 1) {
@@ -278,7 +308,7 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
     for (int p = 0; p < 4; ++p) {
         if (!((mask >> p) & 1u)) continue;
         const size_t vb = p == P64 ? 8 : 4;
-        add(N0 * (m + 1) * vb);
+        add((size_t)krylov_ldq((i64)N0) * (m + 1) * vb);
         add(N0 * vb); add(N0 * vb);
     }
     for (int vt = 0; vt < 2; ++vt) {                       // ABI staging buffers
@@ -296,9 +326,9 @@ void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool for
     for (int n = 0; n < 8; ++n) {
         const int col = forward ? n : 7 - n;
         if (n == 0 && skip_first_colour) continue;
-        const unsigned mask = zero ? earlier_colour_mask(col, forward) : (1u << kSlots) - 1u;
+        const int mode = !zero ? kGsFull : forward ? kGsZeroForward : kGsZeroBackward;
         ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
-        launch_gs_colour(A, p, col, mask, r, z, c->stream);
+        launch_gs_colour(A, p, col, mode, r, z, c->stream);
     }
 }
 
@@ -379,7 +409,8 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
     const i64 N = g0.N;
     const size_t vb = vec_bytes(p);
     char *Q = (char *)K.Q;
-    auto col = [&](int j) { return (void *)(Q + (size_t)j * N * vb); };
+    const i64 ldq = K.ldq;
+    auto col = [&](int j) { return (void *)(Q + (size_t)j * ldq * vb); };
 
     c->prof = (d->flags & HPGMX_SOLVE_PROFILE) != 0;
     if (c->prof) {
@@ -436,15 +467,15 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                 vcycle(c, 0, p, col(k), K.z);
                 {
                     ProfScope ps(c, HPGMX_K_SPMV_DOT, 0);
-                    launch_spmv_dot(A0, p, K.z, K.Q, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                    launch_spmv_dot(A0, p, K.z, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                 }
                 {
                     ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
-                    launch_cgs_dot(N, p, K.Q, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                    launch_cgs_dot(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                 }
                 {
                     ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
-                    launch_cgs_norm(N, p, K.Q, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
+                    launch_cgs_norm(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
                 }
                 {
                     ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
@@ -467,7 +498,7 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             }
             {
                 ProfScope ps(c, HPGMX_K_GEMV, 0);
-                launch_gemv(N, p, K.Q, kk, c->ctrl, K.u, c->stream);
+                launch_gemv(N, p, K.Q, ldq, kk, c->ctrl, K.u, c->stream);
             }
             vcycle(c, 0, p, K.u, K.z);
             {
@@ -616,7 +647,8 @@ hpgmx_status hpgmx_mg_setup(hpgmx_handle h, const hpgmx_mg_desc *mg)
         for (int l = 0; l < mg->levels; ++l) {
             Matrix &A = h->lv[l].A;
             A.g = make_geom(nx, ny, nz);
-            A.col = (int *)h->dalloc((size_t)kSlots * A.g.N * 4);
+            A.clog2 = ell_chunk_log2();
+            A.col = (int *)h->dalloc((size_t)ell_entries(A.g.N, A.clog2) * 4);
             alloc_matrix_prec(h, A, P64);
             alloc_matrix_prec(h, A, P32);
             launch_generate(A, pd.beta, h->stream);

@@ -37,6 +37,10 @@ constexpr int kMaxRestart = 63;   // m; the basis holds m + 1 vectors
 constexpr int kMaxBasis = 64;     // kMaxRestart + 1
 constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
 constexpr int kMaxRedBlocks = 2048;  // workgroups of the grid-stride reductions
+constexpr int kDefaultEllChunkLog2 = 8;  // ELL chunking default (see ell_row)
+// Extra elements between Krylov basis columns, so that columns do not start
+// on the same large power-of-two boundary (DRAM channel/bank aliasing).
+constexpr int kDefaultLdqPad = 1088;
 
 using bf16 = __hip_bfloat16;
 
@@ -86,11 +90,48 @@ __host__ __device__ inline void slot_offset(int s, int &di, int &dj, int &dk)
 }
 
 // Bit s set when slot s of a colour-c row couples to a colour relaxed before c
-// in the given direction (forward: lower colour index).
-unsigned earlier_colour_mask(int c, bool forward);
+// in the given direction (forward: lower colour index first).
+__host__ __device__ constexpr unsigned zero_guess_mask(int c, bool forward)
+{
+    unsigned m = 0;
+    for (int s = 0; s < kSlots; ++s) {
+        const int t = s < 13 ? s : s + 1;
+        const int di = t % 3 - 1, dj = (t / 3) % 3 - 1, dk = t / 9 - 1;
+        const int flip = (di & 1) | ((dj & 1) << 1) | ((dk & 1) << 2);
+        const int cn = c ^ flip;
+        if (forward ? cn < c : cn > c) m |= 1u << s;
+    }
+    return m;
+}
+
+// Gauss-Seidel colour-pass modes.
+constexpr int kGsFull = 0;          // every slot
+constexpr int kGsZeroForward = 1;   // forward sweep from z = 0
+constexpr int kGsZeroBackward = 2;  // backward sweep from z = 0
+
+// Position of slot s of row p in the ELL arrays.  clog2 = 0: slot-major over
+// the whole matrix ([s*N + p]).  clog2 > 0: rows are grouped in chunks of
+// C = 2^clog2 and each chunk is slot-major on its own (SELL-C with sigma = 1):
+// a wavefront's 26 slots then lie in one contiguous 26*C-entry region.
+struct EllRow {
+    i64 base, stride;
+};
+__host__ __device__ inline EllRow ell_row(i64 p, i64 N, int clog2)
+{
+    if (clog2 == 0) return {p, N};
+    return {(p >> clog2) * ((i64)kSlots << clog2) + (p & ((1ll << clog2) - 1)), 1ll << clog2};
+}
+// Entries each off-diagonal ELL array holds (the last chunk is padded).
+__host__ __device__ inline i64 ell_entries(i64 N, int clog2)
+{
+    if (clog2 == 0) return (i64)kSlots * N;
+    const i64 C = 1ll << clog2;
+    return (i64)kSlots * ((N + C - 1) / C) * C;
+}
 
 struct Matrix {
     Geom g;
+    int clog2 = 0;       // ELL chunking (see ell_row)
     int *col = nullptr;  // [26][N]
     double *v64 = nullptr, *d64 = nullptr;
     float *v32 = nullptr, *d32 = nullptr;
@@ -122,29 +163,30 @@ void launch_generate(const Matrix &A, double beta, hipStream_t s);
 void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s);
 void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s);
 void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s);
-// One colour of a Gauss-Seidel sweep: rows of colour c, neighbours in `mask`.
-void launch_gs_colour(const Matrix &A, Prec p, int c, unsigned mask, const void *r, void *z,
+// One colour of a Gauss-Seidel sweep: rows of colour c, slots per `mode`.
+void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
                       hipStream_t s);
 void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
                      void *rc, hipStream_t s);
 void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void *z,
                     hipStream_t s);
 
-// Krylov kernels.  Q is column-major with leading dimension ldq = N.
+// Krylov kernels.  Q is column-major with leading dimension ldq >= N.
 int red_blocks(i64 N);
-void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, int kb, void *w,
-                     double *partials, Ctrl *ctrl, hipStream_t s);
-void launch_cgs_dot(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
-                    hipStream_t s);
-void launch_cgs_norm(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
-                     int k, int m, hipStream_t s);
+void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 ldq, int kb,
+                     void *w, double *partials, Ctrl *ctrl, hipStream_t s);
+void launch_cgs_dot(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+                    Ctrl *ctrl, hipStream_t s);
+void launch_cgs_norm(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+                     Ctrl *ctrl, int k, int m, hipStream_t s);
 void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s);
 void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
                     double *partials, Ctrl *ctrl, int m, hipStream_t s);
 void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStream_t s);
 void launch_cast(i64 N, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s);
 void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s);
-void launch_gemv(i64 N, Prec p, const void *Q, int kk, const Ctrl *ctrl, void *u, hipStream_t s);
+void launch_gemv(i64 N, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u,
+                 hipStream_t s);
 void launch_update(i64 N, Prec p, const void *z, double *x, hipStream_t s);
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 

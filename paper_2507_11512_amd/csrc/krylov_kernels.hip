@@ -118,14 +118,21 @@ __device__ __forceinline__ void finish_sums(const double *partials, int kb, doub
         __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Column j of the basis for a kernel compiled for KB columns: loads are
+// issued for all KB columns unconditionally (so they can all be in flight at
+// once); columns at or beyond kb re-read column kb-1 from cache and carry a
+// zero coefficient.
+__device__ __forceinline__ i64 col_off(int j, int kb, i64 ldq) { return (i64)(j < kb ? j : kb - 1) * ldq; }
+
 // ---- w = A z fused with h1 = Q_{1:kb}^T w (Alg. 3: SpMV, then the first GEMVT) ----
 template <typename V, int KB>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, const V *__restrict__ offv,
                                                      const int *__restrict__ offc,
                                                      const V *__restrict__ diag,
                                                      const typename VecOf2<V>::T *__restrict__ z,
                                                      const typename VecOf2<V>::T *__restrict__ Q,
-                                                     int kb, typename VecOf2<V>::T *__restrict__ w,
+                                                     i64 ldq, int kb,
+                                                     typename VecOf2<V>::T *__restrict__ w,
                                                      double *partials, Ctrl *ctrl)
 {
     using T = typename VecOf2<V>::T;
@@ -134,17 +141,20 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, const V *__restrict_
     for (int j = 0; j < KB; ++j) acc[j] = 0.0;
     const i64 stride = (i64)gridDim.x * kBlock;
     for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        T q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
+        const EllRow er = ell_row(p, N, clog2);
         T v = cv<T>(ldnt(diag + p)) * z[p];
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            const i64 e = (i64)s * N + p;
+            const i64 e = er.base + (i64)s * er.stride;
             v += cv<T>(ldnt(offv + e)) * z[ldnt(offc + e)];
         }
         w[p] = v;
         const double vd = (double)v;
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < kb) acc[j] += (double)Q[(i64)j * N + p] * vd;
+        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
     }
     store_partials<KB>(acc, kb, partials);
     if (arrive_last(&ctrl->counter[0])) finish_sums(partials, kb, ctrl->h1, &ctrl->counter[0]);
@@ -152,32 +162,29 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, const V *__restrict_
 
 // ---- w -= Q h1 fused with h2 = Q^T w (the reorthogonalisation GEMV and GEMVT) ----
 template <typename T, int KB>
-__global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 N, const T *__restrict__ Q, int kb,
+__global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 N, const T *__restrict__ Q, i64 ldq, int kb,
                                                     T *__restrict__ w, double *partials,
                                                     Ctrl *ctrl)
 {
-    double acc[KB], c[KB];
+    __shared__ double c[KB];
+    if ((int)threadIdx.x < KB) c[threadIdx.x] = (int)threadIdx.x < kb ? ctrl->h1[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[KB];
 #pragma unroll
-    for (int j = 0; j < KB; ++j) {
-        acc[j] = 0.0;
-        c[j] = j < kb ? ctrl->h1[j] : 0.0;
-    }
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
     const i64 stride = (i64)gridDim.x * kBlock;
     for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
         T q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
         double v = (double)w[p];
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < kb) {
-                q[j] = Q[(i64)j * N + p];
-                v -= c[j] * (double)q[j];
-            }
+        for (int j = 0; j < KB; ++j) v -= c[j] * (double)q[j];
         const T vt = (T)v;
         w[p] = vt;
         const double vd = (double)vt;
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < kb) acc[j] += (double)q[j] * vd;
+        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
     }
     store_partials<KB>(acc, kb, partials);
     if (arrive_last(&ctrl->counter[1])) finish_sums(partials, kb, ctrl->h2, &ctrl->counter[1]);
@@ -223,19 +230,22 @@ __device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
 
 // ---- w -= Q h2 fused with ||w||^2, then the Givens step -------------------------------------
 template <typename T, int KB>
-__global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 N, const T *__restrict__ Q, int kb,
+__global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 N, const T *__restrict__ Q, i64 ldq, int kb,
                                                      T *__restrict__ w, double *partials,
                                                      Ctrl *ctrl, int k, int m)
 {
-    double acc[1] = {0.0}, c[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) c[j] = j < kb ? ctrl->h2[j] : 0.0;
+    __shared__ double c[KB];
+    if ((int)threadIdx.x < KB) c[threadIdx.x] = (int)threadIdx.x < kb ? ctrl->h2[threadIdx.x] : 0.0;
+    __syncthreads();
+    double acc[1] = {0.0};
     const i64 stride = (i64)gridDim.x * kBlock;
     for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        T q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
         double v = (double)w[p];
 #pragma unroll
-        for (int j = 0; j < KB; ++j)
-            if (j < kb) v -= c[j] * (double)Q[(i64)j * N + p];
+        for (int j = 0; j < KB; ++j) v -= c[j] * (double)q[j];
         const T vt = (T)v;
         w[p] = vt;
         acc[0] += (double)vt * (double)vt;
@@ -257,7 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_normalize(i64 N, T *__restrict__ w, 
 }
 
 // ---- FP64 outer residual r = b - A x with ||r||^2 (Alg. 3, residual step) ----
-__global__ __launch_bounds__(kBlock) void k_resid64(i64 N, const double *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, const double *__restrict__ offv,
                                                     const int *__restrict__ offc,
                                                     const double *__restrict__ diag,
                                                     const double *__restrict__ x,
@@ -268,10 +278,11 @@ __global__ __launch_bounds__(kBlock) void k_resid64(i64 N, const double *__restr
     double acc[1] = {0.0};
     const i64 stride = (i64)gridDim.x * kBlock;
     for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        const EllRow er = ell_row(p, N, clog2);
         double v = ldnt(diag + p) * x[p];
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
-            const i64 e = (i64)s * N + p;
+            const i64 e = er.base + (i64)s * er.stride;
             v += ldnt(offv + e) * x[ldnt(offc + e)];
         }
         const double rv = b[p] - v;
@@ -336,18 +347,20 @@ __global__ void k_trsm(Ctrl *c, int kk, int m)
 
 // ---- u = Q(:,0:kk) y ------------------------------------------------------------------------------
 template <typename T, int KB>
-__global__ __launch_bounds__(kBlock) void k_gemv(i64 N, const T *__restrict__ Q, int kk,
+__global__ __launch_bounds__(kBlock) void k_gemv(i64 N, const T *__restrict__ Q, i64 ldq, int kk,
                                                  const Ctrl *ctrl, T *__restrict__ u)
 {
-    double c[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) c[j] = j < kk ? ctrl->y[j] : 0.0;
+    __shared__ double c[KB];
+    if ((int)threadIdx.x < KB) c[threadIdx.x] = (int)threadIdx.x < kk ? ctrl->y[threadIdx.x] : 0.0;
+    __syncthreads();
     const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
     if (p >= N) return;
+    T q[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kk, ldq) + p];
     double v = 0.0;
 #pragma unroll
-    for (int j = 0; j < KB; ++j)
-        if (j < kk) v += c[j] * (double)Q[(i64)j * N + p];
+    for (int j = 0; j < KB; ++j) v += c[j] * (double)q[j];
     u[p] = (T)v;
 }
 
@@ -372,62 +385,79 @@ __global__ __launch_bounds__(kBlock) void k_copy(i64 n16, const u32x4 *__restric
 // launchers
 static inline unsigned grid_n(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-#define HPGMX_KB_DISPATCH(kb, CALL)                  \
-    do {                                             \
-        if ((kb) <= 4) { constexpr int KB = 4; CALL; }        \
-        else if ((kb) <= 8) { constexpr int KB = 8; CALL; }   \
-        else if ((kb) <= 16) { constexpr int KB = 16; CALL; } \
-        else if ((kb) <= 32) { constexpr int KB = 32; CALL; } \
-        else { constexpr int KB = 64; CALL; }                 \
-    } while (0)
+// Basis-count buckets: kernels are compiled for KB = 4, 8, ..., 64 columns.
+#define HPGMX_KB_CASE(N_)                   \
+    case N_: {                              \
+        constexpr int KB = 4 * N_;          \
+        HPGMX_KB_BODY;                      \
+    } break;
+#define HPGMX_KB_SWITCH(kb)                                                                  \
+    switch (((kb) + 3) / 4) {                                                                \
+        HPGMX_KB_CASE(1) HPGMX_KB_CASE(2) HPGMX_KB_CASE(3) HPGMX_KB_CASE(4) HPGMX_KB_CASE(5) \
+        HPGMX_KB_CASE(6) HPGMX_KB_CASE(7) HPGMX_KB_CASE(8) HPGMX_KB_CASE(9) HPGMX_KB_CASE(10) \
+        HPGMX_KB_CASE(11) HPGMX_KB_CASE(12) HPGMX_KB_CASE(13) HPGMX_KB_CASE(14)              \
+        HPGMX_KB_CASE(15) HPGMX_KB_CASE(16)                                                  \
+    default: throw std::runtime_error("basis size out of range");                            \
+    }
 
 template <typename V>
 static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, const void *Q,
-                       int kb, void *w, double *partials, Ctrl *ctrl, hipStream_t s)
+                       i64 ldq, int kb, void *w, double *partials, Ctrl *ctrl, hipStream_t s)
 {
     using T = typename VecOf2<V>::T;
     const dim3 gr(red_blocks(A.g.N)), bl(kBlock);
-    HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, v, A.col, d,
-                                             (const T *)z, (const T *)Q, kb, (T *)w, partials, ctrl));
+#define HPGMX_KB_BODY                                                                          \
+    hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, A.clog2, v, A.col, d, (const T *)z, \
+                       (const T *)Q, ldq, kb, (T *)w, partials, ctrl)
+    HPGMX_KB_SWITCH(kb)
+#undef HPGMX_KB_BODY
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, int kb, void *w,
-                     double *partials, Ctrl *ctrl, hipStream_t s)
+void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 ldq, int kb,
+                     void *w, double *partials, Ctrl *ctrl, hipStream_t s)
 {
     switch (p) {
-    case P64: spmv_dot_t(A, A.v64, A.d64, z, Q, kb, w, partials, ctrl, s); break;
-    case P32: spmv_dot_t(A, A.v32, A.d32, z, Q, kb, w, partials, ctrl, s); break;
-    case P16: spmv_dot_t(A, A.v16, A.d16, z, Q, kb, w, partials, ctrl, s); break;
-    case PB16: spmv_dot_t(A, A.vb16, A.db16, z, Q, kb, w, partials, ctrl, s); break;
+    case P64: spmv_dot_t(A, A.v64, A.d64, z, Q, ldq, kb, w, partials, ctrl, s); break;
+    case P32: spmv_dot_t(A, A.v32, A.d32, z, Q, ldq, kb, w, partials, ctrl, s); break;
+    case P16: spmv_dot_t(A, A.v16, A.d16, z, Q, ldq, kb, w, partials, ctrl, s); break;
+    case PB16: spmv_dot_t(A, A.vb16, A.db16, z, Q, ldq, kb, w, partials, ctrl, s); break;
     }
 }
 
-void launch_cgs_dot(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
-                    hipStream_t s)
+void launch_cgs_dot(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+                    Ctrl *ctrl, hipStream_t s)
 {
     const dim3 gr(red_blocks(N)), bl(kBlock);
-    if (p == P64)
-        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_dot<double, KB>), gr, bl, 0, s, N,
-                                                 (const double *)Q, kb, (double *)w, partials, ctrl));
-    else
-        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_dot<float, KB>), gr, bl, 0, s, N,
-                                                 (const float *)Q, kb, (float *)w, partials, ctrl));
+    if (p == P64) {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_cgs_dot<double, KB>), gr, bl, 0, s, N, (const double *)Q, ldq, kb, (double *)w, partials, ctrl)
+        HPGMX_KB_SWITCH(kb)
+#undef HPGMX_KB_BODY
+    } else {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_cgs_dot<float, KB>), gr, bl, 0, s, N, (const float *)Q, ldq, kb, (float *)w, partials, ctrl)
+        HPGMX_KB_SWITCH(kb)
+#undef HPGMX_KB_BODY
+    }
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_cgs_norm(i64 N, Prec p, const void *Q, int kb, void *w, double *partials, Ctrl *ctrl,
-                     int k, int m, hipStream_t s)
+void launch_cgs_norm(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+                     Ctrl *ctrl, int k, int m, hipStream_t s)
 {
     const dim3 gr(red_blocks(N)), bl(kBlock);
-    if (p == P64)
-        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_norm<double, KB>), gr, bl, 0, s, N,
-                                                 (const double *)Q, kb, (double *)w, partials, ctrl,
-                                                 k, m));
-    else
-        HPGMX_KB_DISPATCH(kb, hipLaunchKernelGGL((k_cgs_norm<float, KB>), gr, bl, 0, s, N,
-                                                 (const float *)Q, kb, (float *)w, partials, ctrl,
-                                                 k, m));
+    if (p == P64) {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_cgs_norm<double, KB>), gr, bl, 0, s, N, (const double *)Q, ldq, kb, (double *)w, partials, ctrl, k, m)
+        HPGMX_KB_SWITCH(kb)
+#undef HPGMX_KB_BODY
+    } else {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_cgs_norm<float, KB>), gr, bl, 0, s, N, (const float *)Q, ldq, kb, (float *)w, partials, ctrl, k, m)
+        HPGMX_KB_SWITCH(kb)
+#undef HPGMX_KB_BODY
+    }
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -441,7 +471,7 @@ void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s)
 void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
                     double *partials, Ctrl *ctrl, int m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resid64, dim3(red_blocks(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.v64, A.col,
+    hipLaunchKernelGGL(k_resid64, dim3(red_blocks(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2, A.v64, A.col,
                        A.d64, x, b, r, partials, ctrl, m);
     HPGMX_LAUNCH_CHECK();
 }
@@ -465,15 +495,20 @@ void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s)
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_gemv(i64 N, Prec p, const void *Q, int kk, const Ctrl *ctrl, void *u, hipStream_t s)
+void launch_gemv(i64 N, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u, hipStream_t s)
 {
     const dim3 gr(grid_n(N)), bl(kBlock);
-    if (p == P64)
-        HPGMX_KB_DISPATCH(kk, hipLaunchKernelGGL((k_gemv<double, KB>), gr, bl, 0, s, N,
-                                                 (const double *)Q, kk, ctrl, (double *)u));
-    else
-        HPGMX_KB_DISPATCH(kk, hipLaunchKernelGGL((k_gemv<float, KB>), gr, bl, 0, s, N,
-                                                 (const float *)Q, kk, ctrl, (float *)u));
+    if (p == P64) {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_gemv<double, KB>), gr, bl, 0, s, N, (const double *)Q, ldq, kk, ctrl, (double *)u)
+        HPGMX_KB_SWITCH(kk)
+#undef HPGMX_KB_BODY
+    } else {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_gemv<float, KB>), gr, bl, 0, s, N, (const float *)Q, ldq, kk, ctrl, (float *)u)
+        HPGMX_KB_SWITCH(kk)
+#undef HPGMX_KB_BODY
+    }
     HPGMX_LAUNCH_CHECK();
 }
 

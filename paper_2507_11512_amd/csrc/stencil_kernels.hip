@@ -58,19 +58,6 @@ Geom make_geom(int nx, int ny, int nz)
     return g;
 }
 
-unsigned earlier_colour_mask(int c, bool forward)
-{
-    unsigned m = 0;
-    for (int s = 0; s < kSlots; ++s) {
-        int di, dj, dk;
-        slot_offset(s, di, dj, dk);
-        const int flip = (di & 1) | ((dj & 1) << 1) | ((dk & 1) << 2);
-        const int cn = c ^ flip;
-        if (forward ? cn < c : cn > c) m |= 1u << s;
-    }
-    return m;
-}
-
 // ---- generation -----------------------------------------------------------------
 // Entry of the 27-point operator for offset (di,dj,dk) (Sec. 2, Sec. 3):
 // 26 on the diagonal, -1 off it, with the x-neighbour entries shifted to
@@ -83,7 +70,7 @@ __device__ inline double stencil_entry(double beta, int di, int dj, int dk)
     return -1.0;
 }
 
-__global__ __launch_bounds__(kBlock) void k_generate(Geom g, double beta, int *col, double *v64,
+__global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, double beta, int *col, double *v64,
                                                      double *d64, float *v32, float *d32,
                                                      __half *v16, __half *d16, bf16 *vb16,
                                                      bf16 *db16)
@@ -92,14 +79,14 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, double beta, int *c
     if (p >= g.N) return;
     int i, j, k;
     from_internal(g, p, i, j, k);
-    const i64 N = g.N;
+    const EllRow er = ell_row(p, g.N, clog2);
     for (int s = 0; s < kSlots; ++s) {
         int di, dj, dk;
         slot_offset(s, di, dj, dk);
         const int ii = i + di, jj = j + dj, kk = k + dk;
         const bool in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
         const double a = in ? stencil_entry(beta, di, dj, dk) : 0.0;
-        const i64 e = (i64)s * N + p;
+        const i64 e = er.base + (i64)s * er.stride;
         if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)p;
         if (v64) v64[e] = a;
         if (v32) v32[e] = (float)a;
@@ -115,7 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, double beta, int *c
 
 void launch_generate(const Matrix &A, double beta, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, beta, A.col,
+    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, A.clog2, beta, A.col,
                        A.v64, A.d64, A.v32, A.d32, A.v16, A.d16, A.vb16, A.db16);
     HPGMX_LAUNCH_CHECK();
 }
@@ -164,7 +151,7 @@ void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat
 // ---- SpMV -------------------------------------------------------------------------------
 // y = A x over all N rows (Sec. 3.2 ELL SpMV).
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_spmv(i64 N, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, const V *__restrict__ offv,
                                                  const int *__restrict__ offc,
                                                  const V *__restrict__ diag,
                                                  const typename VecOf<V>::T *__restrict__ x,
@@ -173,10 +160,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv(i64 N, const V *__restrict__ of
     using T = typename VecOf<V>::T;
     const i64 p = gtid();
     if (p >= N) return;
+    const EllRow er = ell_row(p, N, clog2);
     T acc = val<T>(ldm(diag + p)) * x[p];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-        const i64 e = (i64)s * N + p;
+        const i64 e = er.base + (i64)s * er.stride;
         acc += val<T>(ldm(offv + e)) * x[ldm(offc + e)];
     }
     y[p] = acc;
@@ -186,7 +174,7 @@ template <typename V>
 static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void *y, hipStream_t s)
 {
     using T = typename VecOf<V>::T;
-    hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, v, A.col, d,
+    hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2, v, A.col, d,
                        (const T *)x, (T *)y);
     HPGMX_LAUNCH_CHECK();
 }
@@ -203,12 +191,15 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s)
 
 // ---- Gauss-Seidel, one colour ---------------------------------------------------------------
 // Rows p in [row0, row0 + cnt) of one colour:
-//   z_p <- (r_p - sum_{s in mask} a_{p,s} z_{col(p,s)}) / a_pp
+//   z_p <- (r_p - sum_{s in MASK} a_{p,s} z_{col(p,s)}) / a_pp
 // (relaxation form of eq. (1)).  Rows of one colour never couple, so the
-// in-place update is race free.  Slots outside `mask` are skipped: on a sweep
-// from a zero guess they point at colours that still hold zero.
-template <typename V>
-__global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, unsigned mask,
+// in-place update is race free.  MASK is a compile-time slot set, so the
+// unrolled loop issues every load of the row before the first use: the full
+// mask for ordinary sweeps, and for a sweep from a zero guess only the slots
+// that couple to colours relaxed earlier in the sweep (the others still hold
+// zero, and skipping them gives the same result bit for bit).
+template <typename V, unsigned MASK>
+__global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2,
                                                const V *__restrict__ offv,
                                                const int *__restrict__ offc,
                                                const V *__restrict__ diag,
@@ -219,37 +210,62 @@ __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, unsigne
     const i64 t = gtid();
     if (t >= cnt) return;
     const i64 p = row0 + t;
+    const EllRow er = ell_row(p, N, clog2);
     T acc = r[p];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-        if (mask & (1u << s)) {
-            const i64 e = (i64)s * N + p;
+        if (MASK & (1u << s)) {
+            const i64 e = er.base + (i64)s * er.stride;
             acc -= val<T>(ldm(offv + e)) * z[ldm(offc + e)];
         }
     }
     z[p] = acc / val<T>(ldm(diag + p));
 }
 
-template <typename V>
-static void gs_t(const Matrix &A, const V *v, const V *d, int c, unsigned mask, const void *r,
-                 void *z, hipStream_t s)
+constexpr unsigned kFullMask = (1u << kSlots) - 1u;
+
+template <typename V, unsigned MASK>
+static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z,
+                      hipStream_t s)
 {
     using T = typename VecOf<V>::T;
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
-    hipLaunchKernelGGL(k_gs<V>, dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N, mask, v,
-                       A.col, d, (const T *)r, (T *)z);
+    hipLaunchKernelGGL((k_gs<V, MASK>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N,
+                       A.clog2, v, A.col, d, (const T *)r, (T *)z);
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_gs_colour(const Matrix &A, Prec p, int c, unsigned mask, const void *r, void *z,
+#define HPGMX_GS_CASE(C, FWD) \
+    case C: gs_launch<V, zero_guess_mask(C, FWD)>(A, v, d, c, r, z, s); break;
+
+template <typename V>
+static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const void *r, void *z,
+                 hipStream_t s)
+{
+    if (mode == kGsFull) {
+        gs_launch<V, kFullMask>(A, v, d, c, r, z, s);
+    } else if (mode == kGsZeroForward) {
+        switch (c) {
+            HPGMX_GS_CASE(0, true) HPGMX_GS_CASE(1, true) HPGMX_GS_CASE(2, true) HPGMX_GS_CASE(3, true)
+            HPGMX_GS_CASE(4, true) HPGMX_GS_CASE(5, true) HPGMX_GS_CASE(6, true) HPGMX_GS_CASE(7, true)
+        }
+    } else {
+        switch (c) {
+            HPGMX_GS_CASE(0, false) HPGMX_GS_CASE(1, false) HPGMX_GS_CASE(2, false) HPGMX_GS_CASE(3, false)
+            HPGMX_GS_CASE(4, false) HPGMX_GS_CASE(5, false) HPGMX_GS_CASE(6, false) HPGMX_GS_CASE(7, false)
+        }
+    }
+}
+
+void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
                       hipStream_t s)
 {
     switch (p) {
-    case P64: gs_t(A, A.v64, A.d64, c, mask, r, z, s); break;
-    case P32: gs_t(A, A.v32, A.d32, c, mask, r, z, s); break;
-    case P16: gs_t(A, A.v16, A.d16, c, mask, r, z, s); break;
-    case PB16: gs_t(A, A.vb16, A.db16, c, mask, r, z, s); break;
+    case P64: gs_t(A, A.v64, A.d64, c, mode, r, z, s); break;
+    case P32: gs_t(A, A.v32, A.d32, c, mode, r, z, s); break;
+    case P16: gs_t(A, A.v16, A.d16, c, mode, r, z, s); break;
+    case PB16: gs_t(A, A.vb16, A.db16, c, mode, r, z, s); break;
     }
 }
 
@@ -258,7 +274,7 @@ void launch_gs_colour(const Matrix &A, Prec p, int c, unsigned mask, const void 
 // coarse level's natural order: row q of that block is coarse point
 // (q % cx, (q / cx) % cy, q / (cx cy)).  Only those rows are evaluated.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2, const V *__restrict__ offv,
                                                      const int *__restrict__ offc,
                                                      const V *__restrict__ diag,
                                                      const typename VecOf<V>::T *__restrict__ r,
@@ -269,10 +285,11 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, const V *
     const i64 q = gtid();
     if (q >= gc.N) return;
     const i64 N = gf.N, p = gf.off[4] + q;
+    const EllRow er = ell_row(p, N, clog2);
     T acc = val<T>(ldm(diag + p)) * z[p];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
-        const i64 e = (i64)s * N + p;
+        const i64 e = er.base + (i64)s * er.stride;
         acc += val<T>(ldm(offv + e)) * z[ldm(offc + e)];
     }
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
@@ -284,7 +301,7 @@ static void restrict_t(const Matrix &A, const Geom &gc, const V *v, const V *d, 
                        const void *z, void *rc, hipStream_t s)
 {
     using T = typename VecOf<V>::T;
-    hipLaunchKernelGGL(k_restrict<V>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc, v, A.col,
+    hipLaunchKernelGGL(k_restrict<V>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc, A.clog2, v, A.col,
                        d, (const T *)r, (const T *)z, (T *)rc);
     HPGMX_LAUNCH_CHECK();
 }

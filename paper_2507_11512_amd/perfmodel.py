@@ -173,3 +173,12 @@ def zero_guess_active_slots(colour, forward=True):
         if (cn < colour) if forward else (cn > colour):
             n += 1
     return n
+
+
+def penalty(n_d, n_ir):
+    """Iteration-count penalty of the mixed-precision rate (Sec. 3): the rate
+    is multiplied by n_d / n_ir when that ratio is below one, and left as is
+    otherwise."""
+    if not n_d or not n_ir:
+        return 1.0
+    return min(1.0, n_d / n_ir)

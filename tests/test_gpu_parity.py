@@ -277,3 +277,26 @@ def test_bound_workspace_matches_owned_memory(hp):
     hp.destroy(h)
     assert st.converged and st.iters == st2.iters
     assert torch.equal(x, x2)
+
+
+@pytest.mark.parametrize("clog2", ["0", "6", "8"])
+def test_ell_chunk_layouts(hp, clog2, monkeypatch):
+    """The SpMV, smoother, restriction and solve agree with the oracle for
+    every ELL chunking (ragged grids leave a partial last chunk)."""
+    monkeypatch.setenv("HPGMX_ELL_CHUNK_LOG2", clog2)
+    dims = (24, 20, 14)
+    P = hp.Problem(dims, beta=0.5, levels=2, sweep="forward")
+    x = rnd(inputs.uniform(dims, 900), 1)
+    y = dev(np.zeros(x.size), 1)
+    hp.spmv(P.h, 0, 1, dev(x, 1), y)
+    assert np.all(np.abs(host(y) - oracle.spmv(dims, x)) <= 2 * gamma(28, U[1]) * oracle.absrow(dims, x))
+    r = rnd(inputs.uniform(dims, 901), 0)
+    z = dev(np.zeros(r.size), 0)
+    hp.smooth(P.h, 0, 0, 0, dev(r, 0), z, zero_guess=True)
+    ref = oracle.gs(dims, r, np.zeros(r.size), 0)
+    assert np.max(np.abs(host(z) - ref)) <= _gs_tol(dims, r, np.zeros(r.size), ref, 0, 8)
+    b = oracle.spmv(dims, inputs.ones(dims))
+    xg, st = P.solve(dev(b, 0), tol=1e-9, precision="mxp")
+    res = np.linalg.norm(b - oracle.spmv(dims, host(xg))) / np.linalg.norm(b)
+    P.close()
+    assert st.converged and res <= 1e-9
