@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--cpu-iters", type=int, default=2, help="inner steps of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-validation", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the timed FP64 phase")
+    ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel profile")
     return ap.parse_args()
 
 
@@ -155,13 +157,13 @@ def main():
             log(f"validation {prec}: iters={st.iters} res={st.final_rel_res:.3e} "
                 f"|x-1|/|1|={err:.3e} time={st.solve_ms / 1e3:.3f}s")
         n_d, n_ir = val["fp64"]["iters"], val["mxp"]["iters"]
-    penalty = min(1.0, n_d / n_ir) if n_d and n_ir else 1.0
+    penalty = pm.penalty(n_d, n_ir)
 
     # ---- 2./3. timed phases ------------------------------------------------------------------
     cycles = pm.fixed_iteration_cycles(args.iters, m)
     flops = pm.solve_flops(cfg, cycles)
     res = {}
-    for prec in ("mxp", "fp64"):
+    for prec in (("mxp",) if args.no_fp64 else ("mxp", "fp64")):
         for _ in range(args.warmup):
             P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec)
         torch.cuda.synchronize()
@@ -175,12 +177,13 @@ def main():
         log(f"timed {prec}: {dt * 1e3:.1f} ms/solve ({args.iters} iters) -> "
             f"{flops / dt / 1e9:.1f} GFLOP/s raw")
     value = res["mxp"]["gflops_raw"] * penalty
-    fp64_gflops = res["fp64"]["gflops_raw"]
+    fp64_gflops = res["fp64"]["gflops_raw"] if "fp64" in res else None
 
     # ---- 4a. per-kernel profile (HIP events around each launch) ---------------------------
     kernels = {}
     dominant = None
-    for prec, dt_code in (("mxp", hp.F32), ("fp64", hp.F64)):
+    prof_precs = () if args.no_profile else (("mxp", hp.F32),) if args.no_fp64 else (("mxp", hp.F32), ("fp64", hp.F64))
+    for prec, dt_code in prof_precs:
         _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec, profile=True)
         B = kernel_bytes_table(cfg, cycles, dt_code, hp, pm)
         for (kid, lvl), nbytes in sorted(B.items()):
@@ -194,9 +197,9 @@ def main():
                              "frac_peak": round(gbps / PEAK_HBM_GBPS, 4)}
         log(f"profiled {prec} solve: {st.solve_ms:.1f} ms with events")
     mxp_k = {k: v for k, v in kernels.items() if k.endswith("_mxp")}
-    dom_name = max(mxp_k, key=lambda k: mxp_k[k]["total_ms"])
-    dominant = mxp_k[dom_name]
-    for k, v in sorted(mxp_k.items(), key=lambda kv: -kv[1]["total_ms"])[:8]:
+    dom_name = max(mxp_k, key=lambda k: mxp_k[k]["total_ms"]) if mxp_k else None
+    dominant = mxp_k[dom_name] if mxp_k else None
+    for k, v in sorted(mxp_k.items(), key=lambda kv: -kv[1]["total_ms"])[:10]:
         log(f"  {k:24s} {v['total_ms']:9.2f} ms  {v['launches']:6d} launches  {v['GBps']:7.1f} GB/s")
 
     # ---- 4b. streaming copy reference ---------------------------------------------------------
@@ -224,8 +227,7 @@ def main():
                          f"V-cycle), {dt:.1f} s wall"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
 
-    dom_kid = dom_name.rsplit("_", 2)[0]
-    traffic = load_traffic(dom_name, dominant["bytes_per_launch"])
+    traffic = load_traffic(dom_name, dominant["bytes_per_launch"]) if dominant else None
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -243,23 +245,23 @@ def main():
                                f"V-cycle fwd multicolour GS 1/1/1, {args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L,
                    "iters_per_solve": args.iters},
-        "fp64_gflops": round(fp64_gflops, 2),
-        "speedup_vs_fp64": round(value / fp64_gflops, 4),
-        "raw_speedup_vs_fp64": round(res["mxp"]["gflops_raw"] / fp64_gflops, 4),
+        "fp64_gflops": round(fp64_gflops, 2) if fp64_gflops else None,
+        "speedup_vs_fp64": round(value / fp64_gflops, 4) if fp64_gflops else None,
+        "raw_speedup_vs_fp64": round(res["mxp"]["gflops_raw"] / fp64_gflops, 4) if fp64_gflops else None,
         "penalty": round(penalty, 4),
         "n_d": n_d, "n_ir": n_ir,
         "validation": val,
-        "fp64_ms_per_step": round(res["fp64"]["s_per_solve"] * 1e3, 3),
+        "fp64_ms_per_step": round(res["fp64"]["s_per_solve"] * 1e3, 3) if "fp64" in res else None,
         "flops_per_solve": flops,
         "roofline": {"bound": "hbm", "kernel": dom_name,
-                     "achieved": dominant["GBps"], "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                     "frac": dominant["frac_peak"],
-                     "bytes_per_launch": dominant["bytes_per_launch"], "avg_us": dominant["avg_us"],
+                     "achieved": dominant["GBps"] if dominant else None, "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": dominant["frac_peak"] if dominant else None,
+                     "bytes_per_launch": dominant["bytes_per_launch"] if dominant else None,
+                     "avg_us": dominant["avg_us"] if dominant else None,
                      "traffic": traffic, "copy_GBps": round(copy_gbps, 1)},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
-    del dom_kid
     P.close()
     print(json.dumps(out), flush=True)
 

@@ -219,14 +219,31 @@ void ensure_prec(hpgmx_ctx *c, Prec p)
     }
 }
 
+// A vector the kernels gather from: N + 1 entries, entry N zero (the
+// column of padded ELL slots).
+void *gathered_vector(hpgmx_ctx *c, i64 N, Prec p)
+{
+    char *v = (char *)c->dalloc((size_t)(N + 1) * vec_bytes(p));
+    hip_check(hipMemsetAsync(v + (size_t)N * vec_bytes(p), 0, vec_bytes(p), c->stream),
+              "hipMemsetAsync");
+    return v;
+}
+
+// The staging buffers serve every level: re-zero entry N of the level used.
+void zero_entry(hpgmx_ctx *c, void *v, i64 N, Prec p)
+{
+    hip_check(hipMemsetAsync((char *)v + (size_t)N * vec_bytes(p), 0, vec_bytes(p), c->stream),
+              "hipMemsetAsync");
+}
+
 void ensure_level_vectors(hpgmx_ctx *c, Prec p)
 {
     const int vt = vt_of(p);
     for (size_t l = 1; l < c->lv.size(); ++l) {
         Level &L = c->lv[l];
         if (!L.r[vt]) {
-            L.r[vt] = c->dalloc((size_t)L.A.g.N * vec_bytes(p));
-            L.z[vt] = c->dalloc((size_t)L.A.g.N * vec_bytes(p));
+            L.r[vt] = gathered_vector(c, L.A.g.N, p);
+            L.z[vt] = gathered_vector(c, L.A.g.N, p);
         }
     }
 }
@@ -236,7 +253,7 @@ void ensure_tmp(hpgmx_ctx *c, Prec p)
     const int vt = vt_of(p);
     const size_t N0 = (size_t)c->lv[0].A.g.N;
     for (int i = 0; i < 3; ++i)
-        if (!c->tmp[vt][i]) c->tmp[vt][i] = c->dalloc(N0 * vec_bytes(p));
+        if (!c->tmp[vt][i]) c->tmp[vt][i] = gathered_vector(c, (i64)N0, p);
 }
 
 void ensure_common(hpgmx_ctx *c)
@@ -254,7 +271,7 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
     const size_t N0 = (size_t)c->lv[0].A.g.N;
     if (!c->b_int) {
         c->b_int = (double *)c->dalloc(N0 * 8);
-        c->x_int = (double *)c->dalloc(N0 * 8);
+        c->x_int = (double *)gathered_vector(c, (i64)N0, P64);
         c->r64 = (double *)c->dalloc(N0 * 8);
     }
     Krylov &K = c->kry[p];
@@ -269,7 +286,7 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
         K.m = m;
     }
     if (!K.z) {
-        K.z = c->dalloc(N0 * vec_bytes(p));
+        K.z = gathered_vector(c, (i64)N0, p);
         K.u = c->dalloc(N0 * vec_bytes(p));
     }
     ensure_level_vectors(c, p);
@@ -297,23 +314,23 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
         if (l >= 1) {
             for (int vt = 0; vt < 2; ++vt) {
                 const bool want = vt == 0 ? (mask & 1u) : (mask & 0xEu);
-                if (want) { add(N * (vt == 0 ? 8 : 4)); add(N * (vt == 0 ? 8 : 4)); }
+                if (want) { add((N + 1) * (vt == 0 ? 8 : 4)); add((N + 1) * (vt == 0 ? 8 : 4)); }
             }
         }
         nx /= 2; ny /= 2; nz /= 2;
     }
     add(sizeof(Ctrl));
     add((size_t)kMaxRedBlocks * kMaxBasis * 8);
-    add(N0 * 8); add(N0 * 8); add(N0 * 8);                // b, x, r in FP64
+    add(N0 * 8); add((N0 + 1) * 8); add(N0 * 8);          // b, x, r in FP64
     for (int p = 0; p < 4; ++p) {
         if (!((mask >> p) & 1u)) continue;
         const size_t vb = p == P64 ? 8 : 4;
         add((size_t)krylov_ldq((i64)N0) * (m + 1) * vb);
-        add(N0 * vb); add(N0 * vb);
+        add((N0 + 1) * vb); add(N0 * vb);
     }
     for (int vt = 0; vt < 2; ++vt) {                       // ABI staging buffers
         const bool want = vt == 0 ? true : (mask & 0xEu) != 0;
-        if (want) for (int i = 0; i < 3; ++i) add(N0 * (vt == 0 ? 8 : 4));
+        if (want) for (int i = 0; i < 3; ++i) add((N0 + 1) * (vt == 0 ? 8 : 4));
     }
     return tot;
 }
@@ -692,6 +709,7 @@ hpgmx_status hpgmx_spmv(hpgmx_handle h, int level, int dtype, const void *x, voi
         const int vt = vt_of(p);
         const Matrix &A = h->lv[level].A;
         const Prec pv = p == P64 ? P64 : P32;
+        zero_entry(h, h->tmp[vt][0], A.g.N, pv);
         launch_nat2int(A.g, pv, x, pv, h->tmp[vt][0], h->stream);
         launch_spmv(A, p, h->tmp[vt][0], h->tmp[vt][1], h->stream);
         launch_int2nat(A.g, pv, h->tmp[vt][1], pv, y, h->stream);
@@ -714,6 +732,7 @@ hpgmx_status hpgmx_smooth(hpgmx_handle h, int level, int dtype, int sweep, const
         const int vt = vt_of(p);
         const Matrix &A = h->lv[level].A;
         const Prec pv = p == P64 ? P64 : P32;
+        zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         if (!zero_guess) launch_nat2int(A.g, pv, z, pv, h->tmp[vt][1], h->stream);
         smooth_level(h, level, p, sweep, h->tmp[vt][0], h->tmp[vt][1], zero_guess != 0, 1);
@@ -735,6 +754,7 @@ hpgmx_status hpgmx_vcycle(hpgmx_handle h, int dtype, const void *r, void *z)
         const int vt = vt_of(p);
         const Matrix &A = h->lv[0].A;
         const Prec pv = p == P64 ? P64 : P32;
+        zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         vcycle(h, 0, p, h->tmp[vt][0], h->tmp[vt][1]);
         launch_int2nat(A.g, pv, h->tmp[vt][1], pv, z, h->stream);
@@ -758,6 +778,7 @@ hpgmx_status hpgmx_restrict_residual(hpgmx_handle h, int level, int dtype, const
         const Matrix &A = h->lv[level].A;
         const Geom &gc = h->lv[level + 1].A.g;
         const Prec pv = p == P64 ? P64 : P32;
+        zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         launch_nat2int(A.g, pv, z, pv, h->tmp[vt][1], h->stream);
         launch_restrict(A, gc, p, h->tmp[vt][0], h->tmp[vt][1], h->tmp[vt][2], h->stream);
@@ -795,6 +816,7 @@ hpgmx_status hpgmx_rhs_from_x(hpgmx_handle h, const double *x, double *b)
         check_ptr(b, "b");
         ensure_tmp(h, P64);
         const Matrix &A = h->lv[0].A;
+        zero_entry(h, h->tmp[0][0], A.g.N, P64);
         launch_nat2int(A.g, P64, x, P64, h->tmp[0][0], h->stream);
         launch_spmv(A, P64, h->tmp[0][0], h->tmp[0][1], h->stream);
         launch_int2nat(A.g, P64, h->tmp[0][1], P64, b, h->stream);

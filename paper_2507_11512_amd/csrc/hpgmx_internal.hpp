@@ -12,10 +12,12 @@
 //    wavefront), and the colour-4 block of a fine level is exactly the coarse
 //    level in its natural order.
 //  * The matrix is ELLPACK (Sec. 3.2) with the diagonal split off: 26
-//    off-diagonal slots, slot-major (value and int32 column of slot s for row
-//    p at [s*N + p]), plus a diagonal array.  Rows with fewer neighbours pad
-//    with value 0 and column = the row itself.  Column indices are shared by
-//    all value precisions (FP64, FP32, FP16, BF16).
+//    off-diagonal slots (layout: see ell_row) plus a diagonal array.  Rows
+//    with fewer neighbours pad with value 0 and column N: every vector the
+//    kernels gather from holds N + 1 entries and keeps entry N at zero, so a
+//    padded slot contributes 0 * 0 whatever the rest of the vector holds.
+//    Column indices are shared by all value precisions (FP64, FP32, FP16,
+//    BF16).
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -36,7 +38,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxRestart = 63;   // m; the basis holds m + 1 vectors
 constexpr int kMaxBasis = 64;     // kMaxRestart + 1
 constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
-constexpr int kMaxRedBlocks = 2048;  // workgroups of the grid-stride reductions
+constexpr int kMaxRedBlocks = 1024;  // workgroups of the grid-stride reductions
 constexpr int kDefaultEllChunkLog2 = 8;  // ELL chunking default (see ell_row)
 // Extra elements between Krylov basis columns, so that columns do not start
 // on the same large power-of-two boundary (DRAM channel/bank aliasing).
@@ -146,7 +148,7 @@ inline size_t vec_bytes(Prec p) { return p == P64 ? 8 : 4; }
 
 // Device-side control block of one Krylov cycle (FP64): Hessenberg matrix
 // (rotated) and its unrotated copy, Givens rotations, right-hand side t,
-// projected solution y, CGS2 coefficients, scalars and reduction counters.
+// projected solution y, CGS2 coefficients and scalars.
 struct Ctrl {
     double H[kMaxBasis * kMaxRestart];
     double Hbar[kMaxBasis * kMaxRestart];
@@ -155,8 +157,14 @@ struct Ctrl {
     // scalars read back by the host after every inner step (keep together)
     double rho, inv_rho, beta, inv_beta, nrm2, rho0;
     int breakdown, nonfinite;
-    unsigned counter[4];
 };
+
+// What the finish kernel of a reduction does with the summed partials.
+constexpr int kFinishH1 = 0;          // h1 = Q^T w
+constexpr int kFinishH2 = 1;          // h2 = Q^T w (reorthogonalisation)
+constexpr int kFinishNormGivens = 2;  // ||w||^2, then the Givens step of column k
+constexpr int kFinishResid = 3;       // rho = ||b - A x||, start of a cycle
+constexpr int kFinishRho0 = 4;        // rho0 = ||b||
 
 // ---- launchers (stream-ordered) -------------------------------------------
 void launch_generate(const Matrix &A, double beta, hipStream_t s);

@@ -4,13 +4,14 @@
 // and the mixed-precision solution update.
 //
 // Reductions (inner products and norms) are deterministic: every workgroup
-// of a fixed-size grid-stride launch writes its partial sums, and the last
-// workgroup to finish (found with a device-scope counter) adds them in block
-// order and writes the result -- no second launch and no floating-point
-// atomics.  The Givens update of the Hessenberg column (Alg. 3, "Update QR
-// with Given's rotations") runs in FP64 in that last workgroup of the norm
-// pass, so the whole inner step needs no host round trip except the 8-byte
-// residual-estimate read.
+// of a fixed-size grid-stride launch writes its partial sums, and a
+// one-workgroup finish kernel adds them in workgroup order.  The kernel
+// boundary makes the partial sums visible, so the streaming kernels need no
+// device-scope fences (on gfx950 a device-scope release writes back the
+// XCD's L2, which costs far more than the extra launch).  The Givens update
+// of the Hessenberg column (Alg. 3, "Update QR with Given's rotations") runs
+// in FP64 in the finish kernel of the norm pass, so the whole inner step
+// needs no host round trip except the small residual-estimate read.
 #include "hpgmx_internal.hpp"
 
 #include <stdexcept>
@@ -53,7 +54,8 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Writes this workgroup's sums of acc[0..kb) to partials[blockIdx.x * kMaxBasis + j].
+// Writes this workgroup's sums of acc[0..kb) to partials[j * kMaxRedBlocks + blockIdx.x]
+// (column j of the partial sums is contiguous for the finish kernel).
 template <int KB>
 __device__ __forceinline__ void store_partials(const double (&acc)[KB], int kb, double *partials)
 {
@@ -71,51 +73,8 @@ __device__ __forceinline__ void store_partials(const double (&acc)[KB], int kb, 
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-        __hip_atomic_store(partials + (i64)blockIdx.x * kMaxBasis + threadIdx.x, s, __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
+        partials[(i64)threadIdx.x * kMaxRedBlocks + blockIdx.x] = s;
     }
-}
-
-// True in exactly one workgroup: the last one to arrive.  Partial sums
-// written before the call are visible to it after the call.
-__device__ __forceinline__ bool arrive_last(unsigned *counter)
-{
-    __shared__ int last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = prev == gridDim.x - 1;
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
-// In the last workgroup: out[j] = sum over workgroups b (in order) of
-// partials[b][j], j < kb.  Lane l of wave w adds workgroups b = w, w+4, ...
-__device__ __forceinline__ void finish_sums(const double *partials, int kb, double *out,
-                                            unsigned *counter)
-{
-    __shared__ double fin[kBlock / 64][kMaxBasis];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int nb = gridDim.x;
-    if (lane < kb) {
-        double s = 0.0;
-        for (int b = wave; b < nb; b += kBlock / 64)
-            s += __hip_atomic_load(partials + (i64)b * kMaxBasis + lane, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-        fin[wave][lane] = s;
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < kb) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += fin[w][threadIdx.x];
-        out[threadIdx.x] = s;
-    }
-    if (threadIdx.x == 0)
-        __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Column j of the basis for a kernel compiled for KB columns: loads are
@@ -157,7 +116,6 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, const V *
         for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
     }
     store_partials<KB>(acc, kb, partials);
-    if (arrive_last(&ctrl->counter[0])) finish_sums(partials, kb, ctrl->h1, &ctrl->counter[0]);
 }
 
 // ---- w -= Q h1 fused with h2 = Q^T w (the reorthogonalisation GEMV and GEMVT) ----
@@ -187,45 +145,69 @@ __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 N, const T *__restrict__
         for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
     }
     store_partials<KB>(acc, kb, partials);
-    if (arrive_last(&ctrl->counter[1])) finish_sums(partials, kb, ctrl->h2, &ctrl->counter[1]);
 }
 
-// Givens update of Hessenberg column k (0-based) in FP64, done by one thread:
+// Givens update of Hessenberg column k (0-based) in FP64, by one workgroup:
 // H(0:k,k) = h1 + h2, H(k+1,k) = beta; rotate by the earlier rotations (each
 // rotation reads both entries before writing either); form the rotation that
 // annihilates H(k+1,k); update t and the residual estimate rho = |t(k+1)|.
+// The inputs are staged in LDS by all threads, the rotation chain runs in one
+// thread out of LDS and registers, and the results are written back in
+// parallel (a single thread reading global memory would wait on every load).
 __device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
 {
-    double *Hk = c->H + (i64)k * (m + 1);
-    double *Hb = c->Hbar + (i64)k * (m + 1);
-    for (int j = 0; j <= k; ++j) Hk[j] = c->h1[j] + c->h2[j];
+    __shared__ double hk[kMaxBasis + 1], cs[kMaxBasis], sn[kMaxBasis], tk[2];
+    const int t = threadIdx.x;
     const double beta = sqrt(nrm2);
-    Hk[k + 1] = beta;
-    for (int j = 0; j <= k + 1; ++j) Hb[j] = Hk[j];
-    for (int j = 0; j < k; ++j) {
-        const double a = Hk[j], b = Hk[j + 1];
-        Hk[j] = c->cs[j] * a + c->sn[j] * b;
-        Hk[j + 1] = -c->sn[j] * a + c->cs[j] * b;
+    if (t <= k) hk[t] = c->h1[t] + c->h2[t];
+    if (t < k) {
+        cs[t] = c->cs[t];
+        sn[t] = c->sn[t];
     }
-    const double mu = sqrt(Hk[k] * Hk[k] + Hk[k + 1] * Hk[k + 1]);
-    double ck = 1.0, sk = 0.0;
-    if (mu > 0.0) {
-        ck = Hk[k] / mu;
-        sk = Hk[k + 1] / mu;
+    if (t == 0) {
+        hk[k + 1] = beta;
+        tk[0] = c->t[k];
     }
-    c->cs[k] = ck;
-    c->sn[k] = sk;
-    Hk[k] = mu;
-    Hk[k + 1] = 0.0;
-    const double tk = c->t[k];
-    c->t[k + 1] = -sk * tk;
-    c->t[k] = ck * tk;
-    c->rho = fabs(c->t[k + 1]);
-    c->beta = beta;
-    c->nrm2 = nrm2;
-    c->breakdown = !(beta > 1e-300);
-    c->inv_beta = c->breakdown ? 0.0 : 1.0 / beta;
-    c->nonfinite = !isfinite(nrm2);
+    __syncthreads();
+    double *Hb = c->Hbar + (i64)k * (m + 1);
+    if (t <= k + 1) Hb[t] = hk[t];  // unrotated column
+    if (t == 0) {
+        double a = hk[0];
+        for (int j = 0; j < k; ++j) {
+            const double b = hk[j + 1];
+            hk[j] = cs[j] * a + sn[j] * b;
+            a = -sn[j] * a + cs[j] * b;
+        }
+        const double bk = hk[k + 1];
+        const double mu = sqrt(a * a + bk * bk);
+        double ck = 1.0, sk = 0.0;
+        if (mu > 0.0) {
+            ck = a / mu;
+            sk = bk / mu;
+        }
+        cs[k] = ck;
+        sn[k] = sk;
+        hk[k] = mu;
+        hk[k + 1] = 0.0;
+        const double t0 = tk[0];
+        tk[0] = ck * t0;
+        tk[1] = -sk * t0;
+        c->rho = fabs(tk[1]);
+        c->beta = beta;
+        c->nrm2 = nrm2;
+        c->breakdown = !(beta > 1e-300);
+        c->inv_beta = c->breakdown ? 0.0 : 1.0 / beta;
+        c->nonfinite = !isfinite(nrm2);
+    }
+    __syncthreads();
+    double *Hk = c->H + (i64)k * (m + 1);
+    if (t <= k + 1) Hk[t] = hk[t];
+    if (t == 0) {
+        c->cs[k] = cs[k];
+        c->sn[k] = sn[k];
+        c->t[k] = tk[0];
+        c->t[k + 1] = tk[1];
+    }
 }
 
 // ---- w -= Q h2 fused with ||w||^2, then the Givens step -------------------------------------
@@ -251,10 +233,6 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 N, const T *__restrict_
         acc[0] += (double)vt * (double)vt;
     }
     store_partials<1>(acc, 1, partials);
-    if (arrive_last(&ctrl->counter[2])) {
-        finish_sums(partials, 1, &ctrl->nrm2, &ctrl->counter[2]);
-        if (threadIdx.x == 0) givens_column(ctrl, k, m, ctrl->nrm2);
-    }
 }
 
 // ---- q_{k+1} = w / beta -------------------------------------------------------------------------
@@ -290,21 +268,6 @@ __global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, const doub
         acc[0] += rv * rv;
     }
     store_partials<1>(acc, 1, partials);
-    if (arrive_last(&ctrl->counter[3])) {
-        finish_sums(partials, 1, &ctrl->nrm2, &ctrl->counter[3]);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            const double rho = sqrt(ctrl->nrm2);
-            ctrl->rho = rho;
-            ctrl->inv_rho = rho > 0.0 ? 1.0 / rho : 0.0;
-            ctrl->nonfinite = !isfinite(rho);
-            ctrl->breakdown = 0;
-        }
-        // new cycle: t = (rho, 0, ..., 0)
-        for (int j = threadIdx.x; j < kMaxBasis; j += kBlock) ctrl->t[j] = 0.0;
-        __syncthreads();
-        if (threadIdx.x == 0) ctrl->t[0] = ctrl->rho;
-    }
 }
 
 // ---- rho0 = ||b|| (Alg. 3, first step) -----------------------------------------------------------
@@ -315,13 +278,71 @@ __global__ __launch_bounds__(kBlock) void k_norm64(i64 N, const double *__restri
     const i64 stride = (i64)gridDim.x * kBlock;
     for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) acc[0] += v[p] * v[p];
     store_partials<1>(acc, 1, partials);
-    if (arrive_last(&ctrl->counter[3])) {
-        finish_sums(partials, 1, &ctrl->nrm2, &ctrl->counter[3]);
-        if (threadIdx.x == 0) {
-            ctrl->rho0 = sqrt(ctrl->nrm2);
-            ctrl->nonfinite = !isfinite(ctrl->rho0);
+}
+
+// ---- finish kernel: add the partial sums of nb workgroups in order -------------------------
+constexpr int kFinishThreads = 1024;
+
+// Wave w sums columns j = w, w + 16, ...; lane l adds workgroups l, l + 64, ...
+// with four independent accumulators, then the wave adds its lanes.
+__global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restrict__ partials,
+                                                           int nb, int kb, int mode, Ctrl *c,
+                                                           int k, int m)
+{
+    __shared__ double tot[kMaxBasis];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < kb; j += kFinishThreads / 64) {
+        const double *col = partials + (i64)j * kMaxRedBlocks;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int b = lane;
+        for (; b + 192 < nb; b += 256) {
+            s0 += col[b];
+            s1 += col[b + 64];
+            s2 += col[b + 128];
+            s3 += col[b + 192];
         }
+        for (; b < nb; b += 64) s0 += col[b];
+        const double s = wave_sum((s0 + s1) + (s2 + s3));
+        if (lane == 0) tot[j] = s;
     }
+    __syncthreads();
+    switch (mode) {
+    case kFinishH1:
+        if ((int)threadIdx.x < kb) c->h1[threadIdx.x] = tot[threadIdx.x];
+        break;
+    case kFinishH2:
+        if ((int)threadIdx.x < kb) c->h2[threadIdx.x] = tot[threadIdx.x];
+        break;
+    case kFinishNormGivens:
+        givens_column(c, k, m, tot[0]);
+        break;
+    case kFinishResid:
+        // start of a cycle: rho = ||r||, t = (rho, 0, ..., 0)
+        if ((int)threadIdx.x < kMaxBasis) c->t[threadIdx.x] = threadIdx.x == 0 ? sqrt(tot[0]) : 0.0;
+        if (threadIdx.x == 0) {
+            const double rho = sqrt(tot[0]);
+            c->nrm2 = tot[0];
+            c->rho = rho;
+            c->inv_rho = rho > 0.0 ? 1.0 / rho : 0.0;
+            c->nonfinite = !isfinite(rho);
+            c->breakdown = 0;
+        }
+        break;
+    case kFinishRho0:
+        if (threadIdx.x == 0) {
+            c->nrm2 = tot[0];
+            c->rho0 = sqrt(tot[0]);
+            c->nonfinite = !isfinite(c->rho0);
+        }
+        break;
+    }
+}
+
+static void finish(const double *partials, int nb, int kb, int mode, Ctrl *ctrl, int k, int m,
+                   hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, nb, kb, mode, ctrl,
+                       k, m);
 }
 
 // ---- q_1 = r / rho in the inner dtype --------------------------------------------------------------
@@ -334,15 +355,24 @@ __global__ __launch_bounds__(kBlock) void k_cast(i64 N, const double *__restrict
     if (p < N) q[p] = (T)(r[p] * s);
 }
 
-// ---- y = H(0:kk,0:kk)^{-1} t(0:kk) by back substitution (FP64, one thread) ----
-__global__ void k_trsm(Ctrl *c, int kk, int m)
+// ---- y = H(0:kk,0:kk)^{-1} t(0:kk) by back substitution (FP64, one workgroup) ----
+// Column-oriented: y_i = t_i / H_ii, then every row above subtracts H_ji y_i
+// in parallel; the triangle and t live in LDS.
+__global__ __launch_bounds__(kMaxBasis) void k_trsm(Ctrl *c, int kk, int m)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ double Hs[kMaxBasis][kMaxBasis + 1], ts[kMaxBasis], ys[kMaxBasis];
+    const int t = threadIdx.x;
+    for (int j = 0; j < kk; ++j)
+        if (t <= j) Hs[t][j] = c->H[(i64)j * (m + 1) + t];
+    if (t < kk) ts[t] = c->t[t];
+    __syncthreads();
     for (int i = kk - 1; i >= 0; --i) {
-        double acc = c->t[i];
-        for (int j = i + 1; j < kk; ++j) acc -= c->H[(i64)j * (m + 1) + i] * c->y[j];
-        c->y[i] = acc / c->H[(i64)i * (m + 1) + i];
+        const double yi = ts[i] / Hs[i][i];  // ts[i] is not written in this step
+        if (t < i) ts[t] -= Hs[t][i] * yi;
+        if (t == 0) ys[i] = yi;
+        __syncthreads();
     }
+    if (t < kk) c->y[t] = ys[t];
 }
 
 // ---- u = Q(:,0:kk) y ------------------------------------------------------------------------------
@@ -411,6 +441,7 @@ static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, c
                        (const T *)Q, ldq, kb, (T *)w, partials, ctrl)
     HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
+    finish(partials, (int)gr.x, kb, kFinishH1, ctrl, 0, 0, s);
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -440,6 +471,7 @@ void launch_cgs_dot(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, doub
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     }
+    finish(partials, (int)gr.x, kb, kFinishH2, ctrl, 0, 0, s);
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -458,6 +490,7 @@ void launch_cgs_norm(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, dou
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     }
+    finish(partials, (int)gr.x, 1, kFinishNormGivens, ctrl, k, m, s);
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -471,14 +504,18 @@ void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s)
 void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
                     double *partials, Ctrl *ctrl, int m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_resid64, dim3(red_blocks(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2, A.v64, A.col,
+    const unsigned nb = (unsigned)red_blocks(A.g.N);
+    hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, A.v64, A.col,
                        A.d64, x, b, r, partials, ctrl, m);
+    finish(partials, (int)nb, 1, kFinishResid, ctrl, 0, m, s);
     HPGMX_LAUNCH_CHECK();
 }
 
 void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_norm64, dim3(red_blocks(N)), dim3(kBlock), 0, s, N, v, partials, ctrl);
+    const unsigned nb = (unsigned)red_blocks(N);
+    hipLaunchKernelGGL(k_norm64, dim3(nb), dim3(kBlock), 0, s, N, v, partials, ctrl);
+    finish(partials, (int)nb, 1, kFinishRho0, ctrl, 0, 0, s);
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -491,7 +528,7 @@ void launch_cast(i64 N, Prec p, const double *r, const Ctrl *ctrl, void *q, hipS
 
 void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_trsm, dim3(1), dim3(64), 0, s, ctrl, kk, m);
+    hipLaunchKernelGGL(k_trsm, dim3(1), dim3(kMaxBasis), 0, s, ctrl, kk, m);
     HPGMX_LAUNCH_CHECK();
 }
 

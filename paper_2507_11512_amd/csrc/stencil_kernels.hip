@@ -79,7 +79,8 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, double b
     if (p >= g.N) return;
     int i, j, k;
     from_internal(g, p, i, j, k);
-    const EllRow er = ell_row(p, g.N, clog2);
+    const i64 N = g.N;
+    const EllRow er = ell_row(p, N, clog2);
     for (int s = 0; s < kSlots; ++s) {
         int di, dj, dk;
         slot_offset(s, di, dj, dk);
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, double b
         const bool in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
         const double a = in ? stencil_entry(beta, di, dj, dk) : 0.0;
         const i64 e = er.base + (i64)s * er.stride;
-        if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)p;
+        if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)N;
         if (v64) v64[e] = a;
         if (v32) v32[e] = (float)a;
         if (v16) v16[e] = __float2half((float)a);

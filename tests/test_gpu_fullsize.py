@@ -1,0 +1,176 @@
+"""GPU parity at the benchmark's full sizes (128^3 and 320^3).
+
+At these sizes the oracle cannot run the whole method in seconds, so the
+checks are (a) sampled outputs that the oracle computes row by row, (b)
+properties that hold at any size -- the relaxation identity of every
+Gauss-Seidel row given the GPU's own neighbour values, the exact solution
+x* = 1 of b = A 1 -- and (c) the oracle's own 128^3 solves stored by
+tests/golden/make_oracle_golden.py.  Problems are set up exactly as
+bench.py sets them up (same levels, sweeps, restart and layout).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_11512_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+U32, U64 = 2.0 ** -24, 2.0 ** -53
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "oracle_solves.json")
+
+
+def gamma(n, u):
+    return n * u / (1.0 - n * u)
+
+
+@pytest.fixture(scope="module")
+def hp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2507_11512_amd import hpgmx
+    return hpgmx
+
+
+def dev(a, dt):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", torch.float64 if dt == 0 else torch.float32)
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def colours(d):
+    nx, ny, nz = d
+    ci = (np.arange(nx) % 2).astype(np.int8)
+    cj = (np.arange(ny) % 2).astype(np.int8)
+    ck = ((np.arange(nz) + 1) % 2).astype(np.int8)
+    return (ci[None, None, :] + 2 * cj[None, :, None] + 4 * ck[:, None, None]).astype(np.int8).ravel()
+
+
+def abs_offdiag_rows(d, w, rows):
+    """sum_{j != i} |a_ij| |w_j| at the given rows.  For beta = 0.5 every
+    off-diagonal entry is negative, so it equals 26 |w_i| - (A |w|)_i."""
+    aw = np.abs(w)
+    return 26.0 * aw[rows] - oracle.spmv_rows(d, aw, rows)
+
+
+def sample_rows(d, n, seed):
+    nx, ny, nz = d
+    N = nx * ny * nz
+    rng = np.random.default_rng(seed)
+    rows = set(rng.integers(0, N, n).tolist())
+    # corners, edges and faces
+    for k in (0, nz - 1):
+        for j in (0, 1, ny - 1):
+            for i in (0, 1, nx - 2, nx - 1):
+                rows.add(i + nx * (j + ny * k))
+    return np.array(sorted(rows), dtype=np.int64)
+
+
+@pytest.fixture(scope="module")
+def p320(hp):
+    print("[setup] 320^3, 4 levels, forward GS (the bench configuration)", flush=True)
+    P = hp.Problem(320, beta=0.5, levels=4, sweep="forward")
+    yield P
+    P.close()
+
+
+@pytest.mark.parametrize("dt", [1, 0])
+def test_spmv_320_sampled(hp, p320, dt):
+    d = (320, 320, 320)
+    x = inputs.uniform(d, 31)
+    if dt == 1:
+        x = x.astype(np.float32).astype(np.float64)
+    y = dev(np.zeros(x.size), dt)
+    hp.spmv(p320.h, 0, dt, dev(x, dt), y)
+    rows = sample_rows(d, 20000, 1)
+    got = host(y)[rows]
+    ref = oracle.spmv_rows(d, x, rows)
+    scale = 26.0 * np.abs(x[rows]) + abs_offdiag_rows(d, x, rows)
+    u = U32 if dt == 1 else U64
+    assert np.all(np.abs(got - ref) <= 2 * gamma(28, u) * scale)
+
+
+def test_gs_320_relaxation_identity(hp, p320):
+    """After one forward sweep, every row of colour c satisfies
+    26 z_new = r - sum(earlier colours) a z_new - sum(later colours) a z_old
+    up to one relaxation's rounding."""
+    d = (320, 320, 320)
+    r = inputs.uniform(d, 32).astype(np.float32).astype(np.float64)
+    z0 = inputs.uniform(d, 33).astype(np.float32).astype(np.float64)
+    zt = dev(z0, 1)
+    hp.smooth(p320.h, 0, 1, 0, dev(r, 1), zt, zero_guess=False)
+    z1 = host(zt)
+    col = colours(d)
+    rows = sample_rows(d, 16000, 2)
+    for c in range(8):
+        rc = rows[col[rows] == c]
+        w = np.where(col < c, z1, z0)
+        off = oracle.spmv_rows(d, w, rc) - 26.0 * w[rc]
+        expect = (r[rc] - off) / 26.0
+        S = (np.abs(r[rc]) + abs_offdiag_rows(d, w, rc)) / 26.0
+        assert np.all(np.abs(z1[rc] - expect) <= 2 * gamma(28, U32) * S + 1e-300), c
+
+
+def test_restrict_320_sampled(hp, p320):
+    d, dc = (320, 320, 320), (160, 160, 160)
+    r = inputs.uniform(d, 34).astype(np.float32).astype(np.float64)
+    z = inputs.uniform(d, 35).astype(np.float32).astype(np.float64)
+    rc = dev(np.zeros(160 ** 3), 1)
+    hp.restrict_residual(p320.h, 0, 1, dev(r, 1), dev(z, 1), rc)
+    got = host(rc)
+    cs = sample_rows(dc, 8000, 3)
+    I, J, K = cs % 160, (cs // 160) % 160, cs // (160 * 160)
+    fine = 2 * I + 320 * (2 * J + 320 * 2 * K)
+    ref = r[fine] - oracle.spmv_rows(d, z, fine)
+    scale = np.abs(r[fine]) + 26.0 * np.abs(z[fine]) + abs_offdiag_rows(d, z, fine)
+    assert np.all(np.abs(got[cs] - ref) <= 2 * gamma(28, U32) * scale)
+
+
+@pytest.mark.parametrize("precision", ["mxp", "fp64"])
+def test_solve_320(hp, p320, precision):
+    import torch
+    d = (320, 320, 320)
+    b = p320.rhs_from_x(torch.ones(320 ** 3, dtype=torch.float64, device="cuda"))
+    x, st = p320.solve(b, tol=1e-9, restart=30, precision=precision)
+    xh = host(x)
+    bh = oracle.spmv(d, np.ones(xh.size))
+    res = np.linalg.norm(bh - oracle.spmv(d, xh)) / np.linalg.norm(bh)
+    err = np.linalg.norm(xh - 1.0) / np.sqrt(xh.size)
+    print(f"[320^3 {precision}] iters={st.iters} res={res:.3e} |x-1|/|1|={err:.3e} "
+          f"time={st.solve_ms / 1e3:.2f}s", flush=True)
+    assert st.converged and res <= 1e-9
+    assert err <= 1e-8
+
+
+@pytest.mark.parametrize("x0", ["zero", "random"])
+@pytest.mark.parametrize("precision", ["fp64", "mxp"])
+def test_mid_128_config(hp, x0, precision):
+    d = (128, 128, 128)
+    g = json.load(open(GOLDEN))["cases"]["mid_128" if x0 == "zero" else "mid_128_random_x0"]
+    P = hp.Problem(128, beta=0.5, levels=4, sweep="forward")
+    b = oracle.spmv(d, inputs.ones(d))
+    xs = None if x0 == "zero" else dev(inputs.random_x0(d), 0)
+    x, st = P.solve(dev(b, 0), xs, tol=1e-9, restart=30, precision=precision)
+    P.close()
+    xh = host(x)
+    res = np.linalg.norm(b - oracle.spmv(d, xh)) / np.linalg.norm(b)
+    err = np.linalg.norm(xh - 1.0) / np.sqrt(xh.size)
+    ref = g["f64"] if precision == "fp64" else g["f32"]
+    print(f"[128^3 {x0} {precision}] gpu iters={st.iters} oracle iters={ref['iters']} "
+          f"res={res:.3e} |x-1|/|1|={err:.3e}", flush=True)
+    assert st.converged and res <= 1e-9
+    # x against the oracle's FP64 solution on its stored sample of entries
+    rows = np.array(g["f64"]["sample_rows"])
+    xo = np.array(g["f64"]["sample_x"])
+    dx = np.linalg.norm(xh[rows] - xo) / np.linalg.norm(xo)
+    print(f"[128^3 {x0} {precision}] sampled |x - x_or| / |x_or| = {dx:.3e}", flush=True)
+    assert dx <= 1e-8
+    if precision == "fp64":
+        assert abs(st.iters - ref["iters"]) <= 2

@@ -300,3 +300,26 @@ def test_ell_chunk_layouts(hp, clog2, monkeypatch):
     res = np.linalg.norm(b - oracle.spmv(dims, host(xg))) / np.linalg.norm(b)
     P.close()
     assert st.converged and res <= 1e-9
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_zero_guess_ignores_stale_contents(hp, dtype):
+    """A sweep from a zero guess must not depend on what the work buffers held
+    before (boundary rows have padded ELL slots; they must never pick up a
+    stale value, NaN included)."""
+    import torch
+    dims = (16, 16, 16)
+    P = problem(hp, dims, 3)
+    r = rnd(inputs.uniform(dims, 950), dtype)
+    nan = torch.full((r.size,), float("nan"), device="cuda",
+                     dtype=torch.float64 if dtype == 0 else torch.float32)
+    hp.smooth(P.h, 0, dtype, 0, dev(r, dtype), nan.clone(), zero_guess=False)  # leaves NaN behind
+    z = nan.clone()
+    hp.smooth(P.h, 0, dtype, 0, dev(r, dtype), z, zero_guess=True)
+    ref = oracle.gs(dims, r, np.zeros(r.size), 0)
+    got = host(z)
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - ref)) <= _gs_tol(dims, r, np.zeros(r.size), ref, dtype, 8)
+    zc = nan.clone()
+    hp.vcycle(P.h, dtype, dev(r, dtype), zc)
+    assert bool(torch.isfinite(zc).all())
