@@ -72,6 +72,18 @@ typedef struct {
     double beta;
 } hpgmx_problem_desc;
 
+/* A general 27-point stencil: coef[t] multiplies the neighbour at offset
+ * (di,dj,dk) with t = 9(dk+1) + 3(dj+1) + (di+1) (t = 13 is the diagonal,
+ * which must be nonzero); entries outside the grid are dropped as for the
+ * beta family.  The beta family is coef = 26 on the diagonal, -1-beta at
+ * di = -1, -1+beta at di = +1, -1 elsewhere.  The stencil of A^T is coef
+ * reversed (coef[26 - t]).  Used for the adjoint (gradients with respect to
+ * the 27 entries). */
+typedef struct {
+    int nx, ny, nz;
+    double coef[27];
+} hpgmx_stencil_desc;
+
 /* The V-cycle (Sec. 2 Fig. 1 applied recursively; Sec. 3): `levels` grids,
  * each coarser one half the size in every dimension (coarse point (I,J,K) is
  * fine point (2I,2J,2K)); pre/post smoothing sweeps on every level but the
@@ -120,6 +132,12 @@ typedef struct {
  * work there.  No device memory is touched until hpgmx_mg_setup. */
 hpgmx_status hpgmx_setup_problem(const hpgmx_problem_desc *desc, void *hip_stream,
                                  hpgmx_handle *out);
+
+/* As hpgmx_setup_problem for a general 27-point stencil (every multigrid
+ * level uses the same stencil).  EINVAL for non-finite entries or a zero
+ * diagonal. */
+hpgmx_status hpgmx_setup_problem_stencil(const hpgmx_stencil_desc *desc, void *hip_stream,
+                                         hpgmx_handle *out);
 
 /* Device bytes the hierarchy of `mg` plus the Krylov workspace for a
  * restart length `restart` need, for every inner dtype whose bit
@@ -171,6 +189,13 @@ hpgmx_status hpgmx_prolong_add(hpgmx_handle h, int level, int dtype, const void 
 
 /* b = A x on level 0 in FP64 (device, natural order). */
 hpgmx_status hpgmx_rhs_from_x(hpgmx_handle h, const double *x, double *b);
+
+/* Adjoint gradient of the stencil entries: out27[t] = sum over grid points i
+ * whose neighbour i + d_t lies in the grid of lam_i * x_{i + d_t}, in FP64.
+ * If x = A^{-1} b and A^T lam = dL/dx, then dL/dcoef[t] = -out27[t] and
+ * dL/db = lam.  lam, x: FP64 device vectors (natural order, level 0); out27:
+ * 27 doubles of device memory.  Stream-ordered. */
+hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double *x, double *out27);
 
 /* Per-kernel timing of the last solve run with HPGMX_SOLVE_PROFILE.
  * Kernel ids are HPGMX_K_*; `level` selects the grid for the per-level

@@ -51,6 +51,24 @@ double or_coef(double beta, int faces_only, int di, int dj, int dk)
     return -1.0;
 }
 
+/* The stencil as a table of 27 entries in slot order
+ * s = 9(dk+1) + 3(dj+1) + (di+1); s = 13 is the diagonal.  Every routine
+ * below works from such a table; the beta family above fills it, and the
+ * *_c entry points accept any table (used by the adjoint tests, where each
+ * entry is a parameter). */
+void or_stencil_from_beta(double beta, int faces_only, double *c27)
+{
+    for (int dk = -1; dk <= 1; ++dk)
+        for (int dj = -1; dj <= 1; ++dj)
+            for (int di = -1; di <= 1; ++di)
+                c27[9 * (dk + 1) + 3 * (dj + 1) + (di + 1)] = or_coef(beta, faces_only, di, dj, dk);
+}
+
+static inline double cf(const double *c27, int di, int dj, int dk)
+{
+    return c27[9 * (dk + 1) + 3 * (dj + 1) + (di + 1)];
+}
+
 static inline idx_t lex(int nx, int ny, int i, int j, int k)
 {
     return (idx_t)i + (idx_t)nx * ((idx_t)j + (idx_t)ny * (idx_t)k);
@@ -59,7 +77,7 @@ static inline idx_t lex(int nx, int ny, int i, int j, int k)
 /* One row of y = A x: sum over the 27 offsets in slot order
  * s = 9(dk+1) + 3(dj+1) + (di+1), dropping offsets outside the grid
  * (Dirichlet truncation of the stencil at the domain boundary).             */
-static double row_apply(int nx, int ny, int nz, double beta, int fo,
+static double row_apply(int nx, int ny, int nz, const double *c27,
                         const double *x, int i, int j, int k)
 {
     double acc = 0.0;
@@ -68,14 +86,14 @@ static double row_apply(int nx, int ny, int nz, double beta, int fo,
             for (int di = -1; di <= 1; ++di) {
                 int ii = i + di, jj = j + dj, kk = k + dk;
                 if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
-                acc += or_coef(beta, fo, di, dj, dk) * x[lex(nx, ny, ii, jj, kk)];
+                acc += cf(c27, di, dj, dk) * x[lex(nx, ny, ii, jj, kk)];
             }
     return acc;
 }
 
 /* Sum of the off-diagonal terms of one row against z (slot order, diagonal
  * skipped).  Used by the Gauss-Seidel relaxation form.                      */
-static double row_offdiag(int nx, int ny, int nz, double beta, int fo,
+static double row_offdiag(int nx, int ny, int nz, const double *c27,
                           const double *z, int i, int j, int k)
 {
     double acc = 0.0;
@@ -85,19 +103,26 @@ static double row_offdiag(int nx, int ny, int nz, double beta, int fo,
                 if (di == 0 && dj == 0 && dk == 0) continue;
                 int ii = i + di, jj = j + dj, kk = k + dk;
                 if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
-                acc += or_coef(beta, fo, di, dj, dk) * z[lex(nx, ny, ii, jj, kk)];
+                acc += cf(c27, di, dj, dk) * z[lex(nx, ny, ii, jj, kk)];
             }
     return acc;
 }
 
 /* y = A x (the SpMV of Alg. 3 and the FP64 outer residual's product). */
-void or_spmv(int nx, int ny, int nz, double beta, int fo, const double *x, double *y)
+void or_spmv_c(int nx, int ny, int nz, const double *c27, const double *x, double *y)
 {
 #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
             for (int i = 0; i < nx; ++i)
-                y[lex(nx, ny, i, j, k)] = row_apply(nx, ny, nz, beta, fo, x, i, j, k);
+                y[lex(nx, ny, i, j, k)] = row_apply(nx, ny, nz, c27, x, i, j, k);
+}
+
+void or_spmv(int nx, int ny, int nz, double beta, int fo, const double *x, double *y)
+{
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
+    or_spmv_c(nx, ny, nz, c27, x, y);
 }
 
 /* Selected rows of y = A x, for sampled checks at sizes where a full product
@@ -105,11 +130,13 @@ void or_spmv(int nx, int ny, int nz, double beta, int fo, const double *x, doubl
 void or_spmv_rows(int nx, int ny, int nz, double beta, int fo, const double *x,
                   const idx_t *rows, idx_t nrows, double *y)
 {
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
 #pragma omp parallel for schedule(static)
     for (idx_t t = 0; t < nrows; ++t) {
         idx_t I = rows[t];
         int i = (int)(I % nx), j = (int)((I / nx) % ny), k = (int)(I / ((idx_t)nx * ny));
-        y[t] = row_apply(nx, ny, nz, beta, fo, x, i, j, k);
+        y[t] = row_apply(nx, ny, nz, c27, x, i, j, k);
     }
 }
 
@@ -117,6 +144,8 @@ void or_spmv_rows(int nx, int ny, int nz, double beta, int fo, const double *x,
  * the parity tolerances (row sums of |a_ij| |x_j|).                         */
 void or_absrow(int nx, int ny, int nz, double beta, int fo, const double *x, double *y)
 {
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
 #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < nz; ++k)
         for (int j = 0; j < ny; ++j)
@@ -127,7 +156,7 @@ void or_absrow(int nx, int ny, int nz, double beta, int fo, const double *x, dou
                         for (int di = -1; di <= 1; ++di) {
                             int ii = i + di, jj = j + dj, kk = k + dk;
                             if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
-                            acc += fabs(or_coef(beta, fo, di, dj, dk)) * fabs(x[lex(nx, ny, ii, jj, kk)]);
+                            acc += fabs(cf(c27, di, dj, dk)) * fabs(x[lex(nx, ny, ii, jj, kk)]);
                         }
                 y[lex(nx, ny, i, j, k)] = acc;
             }
@@ -154,17 +183,17 @@ int or_color(int i, int j, int k)
  * z_I <- (r_I - sum_{J != I} a_IJ z_J) / a_II   (relaxation form of the
  * forward Gauss-Seidel step, eq. (1) and Sec. 3.2).  Rows of one colour do
  * not couple, so their order does not matter; natural order is used.       */
-static void relax_color(int nx, int ny, int nz, double beta, int fo,
+static void relax_color(int nx, int ny, int nz, const double *c27,
                         const double *r, double *z, int c)
 {
     int pi = c & 1, pj = (c >> 1) & 1, pk = ((c >> 2) & 1) ^ 1;
-    double diag = or_coef(beta, fo, 0, 0, 0);
+    double diag = cf(c27, 0, 0, 0);
 #pragma omp parallel for schedule(static)
     for (int k = pk; k < nz; k += 2)
         for (int j = pj; j < ny; j += 2)
             for (int i = pi; i < nx; i += 2) {
                 idx_t I = lex(nx, ny, i, j, k);
-                z[I] = (r[I] - row_offdiag(nx, ny, nz, beta, fo, z, i, j, k)) / diag;
+                z[I] = (r[I] - row_offdiag(nx, ny, nz, c27, z, i, j, k)) / diag;
             }
 }
 
@@ -175,13 +204,20 @@ static void relax_color(int nx, int ny, int nz, double beta, int fo,
  * The backward half starts by relaxing colour 7 again with unchanged
  * neighbours; this reproduces the value the forward half gave it, exactly
  * as the two triangular solves of eqs. (1)-(2) do.                          */
+void or_gs_c(int nx, int ny, int nz, const double *c27, int sweep, const double *r, double *z)
+{
+    if (sweep == 0 || sweep == 2)
+        for (int c = 0; c < 8; ++c) relax_color(nx, ny, nz, c27, r, z, c);
+    if (sweep == 1 || sweep == 2)
+        for (int c = 7; c >= 0; --c) relax_color(nx, ny, nz, c27, r, z, c);
+}
+
 void or_gs(int nx, int ny, int nz, double beta, int fo, int sweep,
            const double *r, double *z)
 {
-    if (sweep == 0 || sweep == 2)
-        for (int c = 0; c < 8; ++c) relax_color(nx, ny, nz, beta, fo, r, z, c);
-    if (sweep == 1 || sweep == 2)
-        for (int c = 7; c >= 0; --c) relax_color(nx, ny, nz, beta, fo, r, z, c);
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
+    or_gs_c(nx, ny, nz, c27, sweep, r, z);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -218,8 +254,8 @@ void or_prolong_add(int nx, int ny, int nz, const double *zc, double *z)
  * rc_i = r_{f(i)} - sum_j A_{f(i) j} z_j, evaluated only at coarse points.
  * The sum uses the same slot order as or_spmv, so the result equals
  * R (r - A z) computed with or_spmv and or_inject bit for bit.              */
-void or_restrict_fused(int nx, int ny, int nz, double beta, int fo,
-                       const double *r, const double *z, double *rc)
+static void restrict_fused_c(int nx, int ny, int nz, const double *c27,
+                             const double *r, const double *z, double *rc)
 {
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
 #pragma omp parallel for schedule(static)
@@ -227,9 +263,17 @@ void or_restrict_fused(int nx, int ny, int nz, double beta, int fo,
         for (int J = 0; J < cy; ++J)
             for (int I = 0; I < cx; ++I) {
                 idx_t f = lex(nx, ny, 2 * I, 2 * J, 2 * K);
-                double Az = row_apply(nx, ny, nz, beta, fo, z, 2 * I, 2 * J, 2 * K);
+                double Az = row_apply(nx, ny, nz, c27, z, 2 * I, 2 * J, 2 * K);
                 rc[lex(cx, cy, I, J, K)] = r[f] - Az;
             }
+}
+
+void or_restrict_fused(int nx, int ny, int nz, double beta, int fo,
+                       const double *r, const double *z, double *rc)
+{
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
+    restrict_fused_c(nx, ny, nz, c27, r, z, rc);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -255,8 +299,8 @@ static void round_vec(double *v, idx_t n, int f32)
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int levels, pre, post, coarsest, sweep;
-    double beta;
-    int fo, f32;
+    const double *c27;
+    int f32;
 } mgparam;
 
 /* z <- M^{-1} r on level l with dimensions (nx,ny,nz).  The V-cycle starts
@@ -270,26 +314,26 @@ static void mg_apply(const mgparam *p, int l, int nx, int ny, int nz,
     memset(z, 0, (size_t)n * sizeof(double));
     if (l == p->levels - 1) {
         for (int s = 0; s < p->coarsest; ++s) {
-            or_gs(nx, ny, nz, p->beta, p->fo, p->sweep, r, z);
+            or_gs_c(nx, ny, nz, p->c27, p->sweep, r, z);
             round_vec(z, n, p->f32);
         }
         return;
     }
     for (int s = 0; s < p->pre; ++s) {
-        or_gs(nx, ny, nz, p->beta, p->fo, p->sweep, r, z);
+        or_gs_c(nx, ny, nz, p->c27, p->sweep, r, z);
         round_vec(z, n, p->f32);
     }
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     idx_t nc = (idx_t)cx * cy * cz;
     double *rc = (double *)malloc((size_t)nc * sizeof(double));
     double *zc = (double *)malloc((size_t)nc * sizeof(double));
-    or_restrict_fused(nx, ny, nz, p->beta, p->fo, r, z, rc);
+    restrict_fused_c(nx, ny, nz, p->c27, r, z, rc);
     round_vec(rc, nc, p->f32);
     mg_apply(p, l + 1, cx, cy, cz, rc, zc);
     or_prolong_add(nx, ny, nz, zc, z);
     round_vec(z, n, p->f32);
     for (int s = 0; s < p->post; ++s) {
-        or_gs(nx, ny, nz, p->beta, p->fo, p->sweep, r, z);
+        or_gs_c(nx, ny, nz, p->c27, p->sweep, r, z);
         round_vec(z, n, p->f32);
     }
     free(rc);
@@ -299,7 +343,9 @@ static void mg_apply(const mgparam *p, int l, int nx, int ny, int nz,
 void or_vcycle(int nx, int ny, int nz, double beta, int fo, int levels, int pre,
                int post, int coarsest, int sweep, int f32, const double *r, double *z)
 {
-    mgparam p = {levels, pre, post, coarsest, sweep, beta, fo, f32};
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
+    mgparam p = {levels, pre, post, coarsest, sweep, c27, f32};
     mg_apply(&p, 0, nx, ny, nz, r, z);
 }
 
@@ -337,15 +383,15 @@ typedef struct {
  * k1 = number of steps in that cycle.  hist (length hist_len) receives the
  * estimated relative residual after each inner step.
  */
-int or_gmres_ir(int nx, int ny, int nz, double beta, int fo, int levels, int pre,
-                int post, int coarsest, int sweep, int f32, int restart, int max_iters,
-                double tol, const double *b, double *x, or_stats *stats,
-                double *Q1, double *Hbar1, double *y1, int *k1,
-                double *hist, int hist_len)
+int or_gmres_ir_c(int nx, int ny, int nz, const double *c27, int levels, int pre,
+                  int post, int coarsest, int sweep, int f32, int restart, int max_iters,
+                  double tol, const double *b, double *x, or_stats *stats,
+                  double *Q1, double *Hbar1, double *y1, int *k1,
+                  double *hist, int hist_len)
 {
     idx_t n = (idx_t)nx * ny * nz;
     int m = restart;
-    mgparam mp = {levels, pre, post, coarsest, sweep, beta, fo, f32};
+    mgparam mp = {levels, pre, post, coarsest, sweep, c27, f32};
     memset(stats, 0, sizeof(*stats));
     if (m < 1) return -1;
 
@@ -372,7 +418,7 @@ int or_gmres_ir(int nx, int ny, int nz, double beta, int fo, int levels, int pre
     stats->final_rel_res = 1.0;
     for (;;) {
         /* FP64 outer residual (Alg. 3, residual step; required in double). */
-        or_spmv(nx, ny, nz, beta, fo, x, r);
+        or_spmv_c(nx, ny, nz, c27, x, r);
         for (idx_t i = 0; i < n; ++i) r[i] = b[i] - r[i];
         double rho = sqrt(dot(r, r, n));
         stats->final_rel_res = rho / rho0;
@@ -392,7 +438,7 @@ int or_gmres_ir(int nx, int ny, int nz, double beta, int fo, int levels, int pre
             if (levels >= 1) mg_apply(&mp, 0, nx, ny, nz, qk, z);
             else memcpy(z, qk, (size_t)n * sizeof(double));
             round_vec(z, n, f32);
-            or_spmv(nx, ny, nz, beta, fo, z, w);
+            or_spmv_c(nx, ny, nz, c27, z, w);
             round_vec(w, n, f32);
             /* CGS2: two classical Gram-Schmidt passes, H(1:k,k) = h1 + h2. */
             for (int j = 0; j <= k; ++j) H[(size_t)k * (m + 1) + j] = 0.0;
@@ -465,4 +511,39 @@ int or_gmres_ir(int nx, int ny, int nz, double beta, int fo, int levels, int pre
 done:
     free(Q); free(H); free(t); free(cs); free(sn); free(y); free(r); free(z); free(hc);
     return rc_status;
+}
+
+int or_gmres_ir(int nx, int ny, int nz, double beta, int fo, int levels, int pre,
+                int post, int coarsest, int sweep, int f32, int restart, int max_iters,
+                double tol, const double *b, double *x, or_stats *stats,
+                double *Q1, double *Hbar1, double *y1, int *k1,
+                double *hist, int hist_len)
+{
+    double c27[27];
+    or_stencil_from_beta(beta, fo, c27);
+    return or_gmres_ir_c(nx, ny, nz, c27, levels, pre, post, coarsest, sweep, f32, restart,
+                         max_iters, tol, b, x, stats, Q1, Hbar1, y1, k1, hist, hist_len);
+}
+
+/* Adjoint quantities for a stencil parameterised by its 27 entries (the
+ * gradient of a loss through x = A^{-1} b): for each offset s,
+ * out[s] = sum over rows i with neighbour i+d_s inside the grid of
+ * lam_i * x_{i+d_s}.  The gradient of L with respect to entry s is -out[s]
+ * when lam solves A^T lam = dL/dx. */
+void or_stencil_correlation(int nx, int ny, int nz, const double *lam, const double *x,
+                            double *out27)
+{
+    for (int s = 0; s < 27; ++s) {
+        int di = s % 3 - 1, dj = (s / 3) % 3 - 1, dk = s / 9 - 1;
+        double acc = 0.0;
+#pragma omp parallel for collapse(2) reduction(+ : acc) schedule(static)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i) {
+                    int ii = i + di, jj = j + dj, kk = k + dk;
+                    if (ii < 0 || ii >= nx || jj < 0 || jj >= ny || kk < 0 || kk >= nz) continue;
+                    acc += lam[lex(nx, ny, i, j, k)] * x[lex(nx, ny, ii, jj, kk)];
+                }
+        out27[s] = acc;
+    }
 }

@@ -68,6 +68,14 @@ def load():
                                 C.POINTER(_CStats), C.c_void_p, C.c_void_p, C.c_void_p,
                                 C.POINTER(C.c_int), C.c_void_p, i]
     lib.or_gmres_ir.restype = i
+    lib.or_stencil_from_beta.argtypes = [d, i, _dp]
+    lib.or_spmv_c.argtypes = [i, i, i, _dp, _dp, _dp]
+    lib.or_gs_c.argtypes = [i, i, i, _dp, i, _dp, _dp]
+    lib.or_gmres_ir_c.argtypes = [i, i, i, _dp, i, i, i, i, i, i, i, i, d, _dp, _dp,
+                                  C.POINTER(_CStats), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(C.c_int), C.c_void_p, i]
+    lib.or_gmres_ir_c.restype = i
+    lib.or_stencil_correlation.argtypes = [i, i, i, _dp, _dp, _dp]
     _lib = lib
     return lib
 
@@ -189,3 +197,52 @@ def gmres_ir(dims, b, x0=None, levels=4, pre=1, post=1, coarsest=1, sweep=0,
     if hist_len > 0:
         out.append(hist[:min(stats.iters, hist_len)].copy())
     return tuple(out)
+
+
+# ---- general 27-entry stencils (slot s = 9(dk+1) + 3(dj+1) + (di+1)) ----------------------
+def stencil_from_beta(beta=0.5, faces_only=False):
+    c = np.empty(27)
+    load().or_stencil_from_beta(float(beta), int(faces_only), c)
+    return c
+
+
+def spmv_c(dims, coef27, x):
+    nx, ny, nz = _dims(dims)
+    y = np.empty(nx * ny * nz)
+    load().or_spmv_c(nx, ny, nz, _f64(coef27), _f64(x), y)
+    return y
+
+
+def gs_c(dims, coef27, r, z, sweep=0):
+    nx, ny, nz = _dims(dims)
+    z = _f64(z).copy()
+    load().or_gs_c(nx, ny, nz, _f64(coef27), int(sweep), _f64(r), z)
+    return z
+
+
+def gmres_ir_c(dims, coef27, b, x0=None, levels=3, pre=1, post=1, coarsest=1, sweep=0,
+               restart=30, max_iters=10000, tol=1e-9, f32=False):
+    nx, ny, nz = _dims(dims)
+    x = np.zeros(nx * ny * nz) if x0 is None else _f64(x0).copy()
+    st = _CStats()
+    rc = load().or_gmres_ir_c(nx, ny, nz, _f64(coef27), int(levels), int(pre), int(post),
+                              int(coarsest), int(sweep), int(f32), int(restart), int(max_iters),
+                              float(tol), _f64(b), x, C.byref(st), None, None, None, None, None, 0)
+    if rc != 0:
+        raise RuntimeError(f"oracle gmres_ir_c failed with status {rc}")
+    return x, Stats(st.iters, st.restarts, bool(st.converged), bool(st.breakdown), st.rho0,
+                    st.final_rel_res, st.est_rel_res)
+
+
+def stencil_correlation(dims, lam, x):
+    """out[s] = sum_i lam_i x_{i+d_s} over in-grid pairs (the adjoint gradient of the
+    stencil entries is -out)."""
+    nx, ny, nz = _dims(dims)
+    out = np.empty(27)
+    load().or_stencil_correlation(nx, ny, nz, _f64(lam), _f64(x), out)
+    return out
+
+
+def transpose_stencil(coef27):
+    """The stencil of A^T: entry at offset d is the entry of A at offset -d."""
+    return np.ascontiguousarray(np.asarray(coef27, dtype=np.float64)[::-1])

@@ -1,0 +1,77 @@
+"""Differentiable solve of the stencil system through the adjoint.
+
+x = A(theta)^{-1} b with A the 27-point stencil operator whose 27 entries are
+theta.  The backward pass solves the adjoint system A^T lam = dL/dx with the
+same mixed-precision GMRES-IR / multigrid solver (A^T is the stencil with
+theta reversed) and returns
+
+    dL/db     = lam,
+    dL/dtheta = -sum_i lam_i x_{i + d_t}   (t = 0..26, in-grid pairs only).
+
+Both solves and the gradient reduction run in the HIP library; this module
+only wires them into torch.autograd.
+"""
+import torch
+
+from . import hpgmx
+
+
+def _key(theta):
+    return tuple(float(v) for v in theta.detach().cpu().tolist())
+
+
+class StencilSolver:
+    """Caches the forward and the adjoint problem for each stencil it sees."""
+
+    def __init__(self, dims, levels=3, sweep="forward", restart=30, tol=1e-10,
+                 precision="mxp", max_iters=10000):
+        self.dims = (dims, dims, dims) if isinstance(dims, int) else tuple(dims)
+        self.levels, self.sweep = levels, sweep
+        self.restart, self.tol, self.precision, self.max_iters = restart, tol, precision, max_iters
+        self._cache = {}
+        self.last_stats = None
+
+    def problems(self, theta):
+        k = _key(theta)
+        if k not in self._cache:
+            coef = list(k)
+            fwd = hpgmx.Problem(self.dims, levels=self.levels, sweep=self.sweep, coef=coef)
+            adj = hpgmx.Problem(self.dims, levels=self.levels, sweep=self.sweep, coef=coef[::-1])
+            self._cache[k] = (fwd, adj)
+        return self._cache[k]
+
+    def solve(self, problem, rhs):
+        x, st = problem.solve(rhs.contiguous(), tol=self.tol, restart=self.restart,
+                              max_iters=self.max_iters, precision=self.precision)
+        self.last_stats = st
+        if not st.converged:
+            raise RuntimeError(f"stencil solve did not converge (rel. residual {st.final_rel_res:.3e})")
+        return x
+
+    def __call__(self, b, theta):
+        return StencilSolve.apply(b, theta, self)
+
+    def close(self):
+        for fwd, adj in self._cache.values():
+            fwd.close()
+            adj.close()
+        self._cache.clear()
+
+
+class StencilSolve(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, b, theta, solver):
+        fwd, adj = solver.problems(theta)
+        x = solver.solve(fwd, b.to(torch.float64))
+        ctx.save_for_backward(x, theta)
+        ctx.solver = solver
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        x, theta = ctx.saved_tensors
+        solver = ctx.solver
+        fwd, adj = solver.problems(theta)
+        lam = solver.solve(adj, g.to(torch.float64).contiguous())
+        grad_theta = -fwd.stencil_grad(lam, x)
+        return lam, grad_theta.to(theta.dtype), None

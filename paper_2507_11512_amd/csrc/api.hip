@@ -50,7 +50,8 @@ inline int vt_of(Prec p) { return p == P64 ? 0 : 1; }
 }  // namespace
 
 struct hpgmx_ctx {
-    hpgmx_problem_desc prob{};
+    hpgmx_problem_desc prob{};  // grid size (beta is unused once `stencil` is set)
+    Stencil stencil{};
     hipStream_t stream = nullptr;
     int device = 0;
     bool mg_ready = false;
@@ -215,7 +216,7 @@ void ensure_prec(hpgmx_ctx *c, Prec p)
         if (p != P32) only.v32 = nullptr, only.d32 = nullptr;
         if (p != P16) only.v16 = nullptr, only.d16 = nullptr;
         if (p != PB16) only.vb16 = nullptr, only.db16 = nullptr;
-        launch_generate(only, c->prob.beta, c->stream);
+        launch_generate(only, c->stencil, c->stream);
     }
 }
 
@@ -588,6 +589,32 @@ hpgmx_status guarded(hpgmx_ctx *c, F &&f)
     }
 }
 
+hpgmx_status create(int nx, int ny, int nz, const Stencil &st, double beta, void *hip_stream,
+                           hpgmx_handle *out)
+{
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return HPGMX_EINVAL;
+    const double N = (double)nx * ny * nz;
+    if (N >= 2147483647.0) return HPGMX_EINVAL;  // int32 column indices (and entry N)
+    for (int t = 0; t < 27; ++t)
+        if (!std::isfinite(st.c[t])) return HPGMX_EINVAL;
+    if (st.c[13] == 0.0) return HPGMX_EINVAL;    // the smoother divides by the diagonal
+    hpgmx_ctx *c = new (std::nothrow) hpgmx_ctx();
+    if (!c) return HPGMX_ENOMEM;
+    c->prob.nx = nx;
+    c->prob.ny = ny;
+    c->prob.nz = nz;
+    c->prob.beta = beta;
+    c->stencil = st;
+    c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return HPGMX_EHIP;
+    }
+    *out = c;
+    return HPGMX_OK;
+}
+
 }  // namespace
 
 // =====================================================================================================
@@ -597,20 +624,18 @@ hpgmx_status hpgmx_setup_problem(const hpgmx_problem_desc *desc, void *hip_strea
 {
     if (!desc || !out) return HPGMX_EINVAL;
     *out = nullptr;
-    if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1) return HPGMX_EINVAL;
     if (!std::isfinite(desc->beta)) return HPGMX_EINVAL;
-    const double N = (double)desc->nx * desc->ny * desc->nz;
-    if (N >= 2147483647.0) return HPGMX_EINVAL;  // int32 column indices
-    hpgmx_ctx *c = new (std::nothrow) hpgmx_ctx();
-    if (!c) return HPGMX_ENOMEM;
-    c->prob = *desc;
-    c->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&c->device) != hipSuccess) {
-        delete c;
-        return HPGMX_EHIP;
-    }
-    *out = c;
-    return HPGMX_OK;
+    return create(desc->nx, desc->ny, desc->nz, stencil_from_beta(desc->beta), desc->beta,
+                  hip_stream, out);
+}
+
+hpgmx_status hpgmx_setup_problem_stencil(const hpgmx_stencil_desc *desc, void *hip_stream,
+                                         hpgmx_handle *out)
+{
+    if (!desc || !out) return HPGMX_EINVAL;
+    Stencil st{};
+    for (int t = 0; t < 27; ++t) st.c[t] = desc->coef[t];
+    return create(desc->nx, desc->ny, desc->nz, st, std::nan(""), hip_stream, out);
 }
 
 hpgmx_status hpgmx_workspace_bytes(hpgmx_handle h, const hpgmx_mg_desc *mg, int restart,
@@ -668,7 +693,7 @@ hpgmx_status hpgmx_mg_setup(hpgmx_handle h, const hpgmx_mg_desc *mg)
             A.col = (int *)h->dalloc((size_t)ell_entries(A.g.N, A.clog2) * 4);
             alloc_matrix_prec(h, A, P64);
             alloc_matrix_prec(h, A, P32);
-            launch_generate(A, pd.beta, h->stream);
+            launch_generate(A, h->stencil, h->stream);
             nx /= 2; ny /= 2; nz /= 2;
         }
         ensure_common(h);
@@ -820,6 +845,26 @@ hpgmx_status hpgmx_rhs_from_x(hpgmx_handle h, const double *x, double *b)
         launch_nat2int(A.g, P64, x, P64, h->tmp[0][0], h->stream);
         launch_spmv(A, P64, h->tmp[0][0], h->tmp[0][1], h->stream);
         launch_int2nat(A.g, P64, h->tmp[0][1], P64, b, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double *x, double *out27)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_ptr(lam, "lam");
+        check_ptr(x, "x");
+        check_ptr(out27, "out27");
+        ensure_tmp(h, P64);
+        const Matrix &A = h->lv[0].A;
+        zero_entry(h, h->tmp[0][1], A.g.N, P64);
+        launch_nat2int(A.g, P64, lam, P64, h->tmp[0][0], h->stream);
+        launch_nat2int(A.g, P64, x, P64, h->tmp[0][1], h->stream);
+        launch_stencil_correlation(A, (const double *)h->tmp[0][0], (const double *)h->tmp[0][1],
+                                   h->partials, h->ctrl, h->stream);
+        hip_check(hipMemcpyAsync(out27, h->ctrl->corr, 27 * sizeof(double), hipMemcpyDeviceToDevice,
+                                 h->stream), "hipMemcpyAsync");
         return HPGMX_OK;
     });
 }

@@ -157,6 +157,7 @@ struct Ctrl {
     // scalars read back by the host after every inner step (keep together)
     double rho, inv_rho, beta, inv_beta, nrm2, rho0;
     int breakdown, nonfinite;
+    double corr[27];  // stencil correlation of the adjoint gradient
 };
 
 // What the finish kernel of a reduction does with the summed partials.
@@ -165,9 +166,21 @@ constexpr int kFinishH2 = 1;          // h2 = Q^T w (reorthogonalisation)
 constexpr int kFinishNormGivens = 2;  // ||w||^2, then the Givens step of column k
 constexpr int kFinishResid = 3;       // rho = ||b - A x||, start of a cycle
 constexpr int kFinishRho0 = 4;        // rho0 = ||b||
+constexpr int kFinishCorr = 5;        // the 27 stencil correlations
 
 // ---- launchers (stream-ordered) -------------------------------------------
-void launch_generate(const Matrix &A, double beta, hipStream_t s);
+// The operator's 27 stencil entries in slot order t = 9(dk+1) + 3(dj+1) + (di+1)
+// (t = 13 is the diagonal), passed to kernels by value.
+struct Stencil {
+    double c[27];
+};
+Stencil stencil_from_beta(double beta);
+void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s);
+// out[t] = sum over rows of lam_p * x_{neighbour t of p} (x, lam in internal
+// order, x gathered with its zero entry at N); `partials` as for the
+// Krylov reductions.
+void launch_stencil_correlation(const Matrix &A, const double *lam, const double *x,
+                                double *partials, Ctrl *ctrl, hipStream_t s);
 void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s);
 void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s);
 void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s);

@@ -335,6 +335,9 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restr
             c->nonfinite = !isfinite(c->rho0);
         }
         break;
+    case kFinishCorr:
+        if ((int)threadIdx.x < kb) c->corr[threadIdx.x] = tot[threadIdx.x];
+        break;
     }
 }
 
@@ -343,6 +346,31 @@ static void finish(const double *partials, int nb, int kb, int mode, Ctrl *ctrl,
 {
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, nb, kb, mode, ctrl,
                        k, m);
+}
+
+// ---- stencil correlation for the adjoint gradient -------------------------------------------
+// acc[t] = sum_p lam_p x_{col(p,t)} for the 26 off-diagonal slots and
+// acc[13] = sum_p lam_p x_p; padded slots read the zero entry x_N.
+__global__ __launch_bounds__(kBlock) void k_stencil_corr(i64 N, int clog2, const int *__restrict__ offc,
+                                                         const double *__restrict__ lam,
+                                                         const double *__restrict__ x,
+                                                         double *partials)
+{
+    double acc[27];
+#pragma unroll
+    for (int t = 0; t < 27; ++t) acc[t] = 0.0;
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+        const EllRow er = ell_row(p, N, clog2);
+        const double l = lam[p];
+        acc[13] += l * x[p];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const int t = s < 13 ? s : s + 1;
+            acc[t] += l * x[ldnt(offc + er.base + (i64)s * er.stride)];
+        }
+    }
+    store_partials<27>(acc, 27, partials);
 }
 
 // ---- q_1 = r / rho in the inner dtype --------------------------------------------------------------
@@ -516,6 +544,16 @@ void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStre
     const unsigned nb = (unsigned)red_blocks(N);
     hipLaunchKernelGGL(k_norm64, dim3(nb), dim3(kBlock), 0, s, N, v, partials, ctrl);
     finish(partials, (int)nb, 1, kFinishRho0, ctrl, 0, 0, s);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_stencil_correlation(const Matrix &A, const double *lam, const double *x,
+                                double *partials, Ctrl *ctrl, hipStream_t s)
+{
+    const unsigned nb = (unsigned)red_blocks(A.g.N);
+    hipLaunchKernelGGL(k_stencil_corr, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, A.col, lam, x,
+                       partials);
+    finish(partials, (int)nb, 27, kFinishCorr, ctrl, 0, 0, s);
     HPGMX_LAUNCH_CHECK();
 }
 

@@ -59,18 +59,23 @@ Geom make_geom(int nx, int ny, int nz)
 }
 
 // ---- generation -----------------------------------------------------------------
-// Entry of the 27-point operator for offset (di,dj,dk) (Sec. 2, Sec. 3):
-// 26 on the diagonal, -1 off it, with the x-neighbour entries shifted to
-// -1-beta (i-1) and -1+beta (i+1).
-__device__ inline double stencil_entry(double beta, int di, int dj, int dk)
+// The 27-point operator of Sec. 2 / Sec. 3: 26 on the diagonal, -1 off it,
+// with the x-neighbour entries shifted to -1-beta (i-1) and -1+beta (i+1).
+Stencil stencil_from_beta(double beta)
 {
-    if (di == 0 && dj == 0 && dk == 0) return 26.0;
-    if (di < 0) return -1.0 - beta;
-    if (di > 0) return -1.0 + beta;
-    return -1.0;
+    Stencil st{};
+    for (int t = 0; t < 27; ++t) {
+        const int di = t % 3 - 1, dj = (t / 3) % 3 - 1, dk = t / 9 - 1;
+        double a = -1.0;
+        if (di == 0 && dj == 0 && dk == 0) a = 26.0;
+        else if (di < 0) a = -1.0 - beta;
+        else if (di > 0) a = -1.0 + beta;
+        st.c[t] = a;
+    }
+    return st;
 }
 
-__global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, double beta, int *col, double *v64,
+__global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil st, int *col, double *v64,
                                                      double *d64, float *v32, float *d32,
                                                      __half *v16, __half *d16, bf16 *vb16,
                                                      bf16 *db16)
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, double b
         slot_offset(s, di, dj, dk);
         const int ii = i + di, jj = j + dj, kk = k + dk;
         const bool in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
-        const double a = in ? stencil_entry(beta, di, dj, dk) : 0.0;
+        const double a = in ? st.c[9 * (dk + 1) + 3 * (dj + 1) + (di + 1)] : 0.0;
         const i64 e = er.base + (i64)s * er.stride;
         if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)N;
         if (v64) v64[e] = a;
@@ -94,16 +99,16 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, double b
         if (v16) v16[e] = __float2half((float)a);
         if (vb16) vb16[e] = __float2bfloat16((float)a);
     }
-    const double dg = stencil_entry(beta, 0, 0, 0);
+    const double dg = st.c[13];
     if (d64) d64[p] = dg;
     if (d32) d32[p] = (float)dg;
     if (d16) d16[p] = __float2half((float)dg);
     if (db16) db16[p] = __float2bfloat16((float)dg);
 }
 
-void launch_generate(const Matrix &A, double beta, hipStream_t s)
+void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, A.clog2, beta, A.col,
+    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, A.clog2, st, A.col,
                        A.v64, A.d64, A.v32, A.d32, A.v16, A.d16, A.vb16, A.db16);
     HPGMX_LAUNCH_CHECK();
 }

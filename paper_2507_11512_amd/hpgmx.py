@@ -25,7 +25,8 @@ KERNEL_NAMES = ["gs", "gs_zero", "restrict", "prolong", "spmv_dot", "cgs_dot", "
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
 
-EXPORTS = ["hpgmx_setup_problem", "hpgmx_workspace_bytes", "hpgmx_bind_workspace",
+EXPORTS = ["hpgmx_setup_problem", "hpgmx_setup_problem_stencil", "hpgmx_stencil_grad",
+           "hpgmx_workspace_bytes", "hpgmx_bind_workspace",
            "hpgmx_mg_setup", "hpgmx_gmres_ir_solve", "hpgmx_spmv", "hpgmx_smooth",
            "hpgmx_vcycle", "hpgmx_restrict_residual", "hpgmx_prolong_add",
            "hpgmx_rhs_from_x", "hpgmx_profile_get", "hpgmx_stream_copy", "hpgmx_destroy",
@@ -34,6 +35,10 @@ EXPORTS = ["hpgmx_setup_problem", "hpgmx_workspace_bytes", "hpgmx_bind_workspace
 
 class ProblemDesc(C.Structure):
     _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("beta", C.c_double)]
+
+
+class StencilDesc(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("coef", C.c_double * 27)]
 
 
 class MgDesc(C.Structure):
@@ -62,6 +67,8 @@ def _load():
     H = C.c_void_p
     sig = {
         "hpgmx_setup_problem": [C.POINTER(ProblemDesc), vp, C.POINTER(H)],
+        "hpgmx_setup_problem_stencil": [C.POINTER(StencilDesc), vp, C.POINTER(H)],
+        "hpgmx_stencil_grad": [H, vp, vp, vp],
         "hpgmx_workspace_bytes": [H, C.POINTER(MgDesc), i, C.c_uint, C.POINTER(C.c_size_t)],
         "hpgmx_bind_workspace": [H, vp, C.c_size_t],
         "hpgmx_mg_setup": [H, C.POINTER(MgDesc)],
@@ -133,6 +140,27 @@ def setup_problem(nx, ny, nz, beta=0.5, stream=None):
     desc = ProblemDesc(int(nx), int(ny), int(nz), float(beta))
     _check(None, lib.hpgmx_setup_problem(C.byref(desc), C.c_void_p(stream.cuda_stream), C.byref(h)))
     return h
+
+
+def setup_problem_stencil(nx, ny, nz, coef27, stream=None):
+    """A general 27-point stencil; coef27[t] multiplies the neighbour at offset
+    (di, dj, dk), t = 9(dk+1) + 3(dj+1) + (di+1)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    coef = [float(c) for c in coef27]
+    if len(coef) != 27:
+        raise ValueError("coef27 must have 27 entries")
+    h = C.c_void_p()
+    desc = StencilDesc(int(nx), int(ny), int(nz), (C.c_double * 27)(*coef))
+    _check(None, lib.hpgmx_setup_problem_stencil(C.byref(desc), C.c_void_p(stream.cuda_stream),
+                                                 C.byref(h)))
+    return h
+
+
+def stencil_grad(h, lam, x, out27):
+    """out27[t] = sum_i lam_i x_{i + d_t} (device FP64 tensors; out27 has 27 entries)."""
+    _check(h, lib.hpgmx_stencil_grad(h, _ptr(lam), _ptr(x), _ptr(out27)))
 
 
 def workspace_bytes(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD, restart=30,
@@ -228,13 +256,16 @@ class Problem:
     _PREC = {"fp64": F64, "mxp": F32, "fp32": F32, "fp16": F16, "bf16": BF16}
 
     def __init__(self, n, beta=0.5, levels=4, sweep="forward", pre=1, post=1, coarsest=1,
-                 stream=None, workspace=None):
+                 stream=None, workspace=None, coef=None):
         import torch
         self.dims = (n, n, n) if isinstance(n, int) else tuple(n)
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
         self.levels = levels
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        self.h = setup_problem(*self.dims, beta=beta, stream=self.stream)
+        if coef is None:
+            self.h = setup_problem(*self.dims, beta=beta, stream=self.stream)
+        else:
+            self.h = setup_problem_stencil(*self.dims, coef, stream=self.stream)
         sw = self._SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
         try:
             if workspace is not None:
@@ -263,6 +294,14 @@ class Problem:
         with torch.cuda.stream(self.stream):
             out = gmres_ir_solve(self.h, b, x, restart, max_iters, tol, prec, hist_len, profile)
         return (x, *out) if isinstance(out, tuple) else (x, out)
+
+    def stencil_grad(self, lam, x):
+        """27 FP64 values sum_i lam_i x_{i + d_t} (see hpgmx_stencil_grad)."""
+        import torch
+        out = torch.empty(27, dtype=torch.float64, device=lam.device)
+        with torch.cuda.stream(self.stream):
+            stencil_grad(self.h, lam, x, out)
+        return out
 
     def close(self):
         if self.h:

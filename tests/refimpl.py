@@ -97,3 +97,23 @@ def vcycle_ref(d, r, levels, pre=1, post=1, coarsest=1, sweep=0, beta=0.5, faces
     for _ in range(post):
         z = gs_triangular(A, perm, r, z, sweep)
     return z
+
+
+def shift_matrix(d, di, dj, dk):
+    """(S x)_i = x at the grid neighbour (i+di, j+dj, k+dk), 0 outside the grid."""
+    nx, ny, nz = dims3(d)
+
+    def s1(m, delta):
+        return sp.diags([np.ones(m - abs(delta))], [delta])
+
+    return sp.csr_matrix(sp.kron(s1(nz, dk), sp.kron(s1(ny, dj), s1(nx, di))))
+
+
+def stencil_matrix(d, coef27):
+    """sum over the 27 offsets of coef * shift (slot s = 9(dk+1) + 3(dj+1) + (di+1))."""
+    A = None
+    for s in range(27):
+        di, dj, dk = s % 3 - 1, (s // 3) % 3 - 1, s // 9 - 1
+        term = coef27[s] * shift_matrix(d, di, dj, dk)
+        A = term if A is None else A + term
+    return sp.csr_matrix(A)

@@ -285,3 +285,71 @@ def test_random_start_same_solution(oracle_mod):
     x, st = oracle_mod.gmres_ir(d, b, x0=inputs.random_x0(d), levels=3, tol=1e-11)
     assert st.converged
     assert np.linalg.norm(x - 1.0) / np.sqrt(x.size) < 1e-9
+
+
+# ------------------------------------------------ general stencils / adjoint --
+def random_stencil(seed, dominant=True):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-1.5, 0.2, 27)
+    c[13] = 0.0
+    c[13] = np.abs(c).sum() + (0.5 if dominant else 0.0)
+    return c
+
+
+def test_stencil_table_of_the_beta_family(oracle_mod):
+    c = oracle_mod.stencil_from_beta(0.5)
+    d = (5, 4, 6)
+    assert np.array_equal(refimpl.stencil_matrix(d, c).toarray(), refimpl.kron_matrix(d, 0.5).toarray())
+    assert np.array_equal(oracle_mod.transpose_stencil(c), oracle_mod.stencil_from_beta(-0.5))
+
+
+@pytest.mark.parametrize("d", [(5, 4, 6), (8, 8, 8)])
+def test_general_stencil_spmv(oracle_mod, d):
+    c = random_stencil(60)
+    x = inputs.uniform(d, 61)
+    S = refimpl.stencil_matrix(d, c)
+    y = oracle_mod.spmv_c(d, c, x)
+    assert np.allclose(y, S @ x, rtol=0, atol=1e-13 * (abs(S) @ np.abs(x)).max())
+    # the transposed table gives A^T
+    yt = oracle_mod.spmv_c(d, oracle_mod.transpose_stencil(c), x)
+    assert np.allclose(yt, S.T @ x, rtol=0, atol=1e-13 * (abs(S) @ np.abs(x)).max())
+
+
+def test_general_stencil_gs_and_solve(oracle_mod):
+    d = (8, 8, 8)
+    c = random_stencil(62)
+    A = refimpl.stencil_matrix(d, c)
+    r, z0 = inputs.uniform(d, 63), inputs.uniform(d, 64)
+    ref = refimpl.gs_triangular(A, refimpl.colour_perm(d), r, z0, 0)
+    assert np.allclose(oracle_mod.gs_c(d, c, r, z0, 0), ref, rtol=0, atol=1e-13)
+    b = inputs.uniform(d, 65)
+    x, st = oracle_mod.gmres_ir_c(d, c, b, levels=3, tol=1e-12)
+    assert st.converged
+    xs = np.linalg.solve(A.toarray(), b)
+    assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
+
+
+def test_stencil_correlation_and_adjoint_gradient(oracle_mod):
+    """dL/dtheta_s = -lam^T S_s x for L = g^T x, x = A^{-1} b, A^T lam = g;
+    checked against the dense products and against central differences of
+    dense solves."""
+    d = (6, 5, 4)
+    c = random_stencil(66)
+    b, g = inputs.uniform(d, 67), inputs.uniform(d, 68)
+    lam, x = inputs.uniform(d, 69), inputs.uniform(d, 70)
+    out = oracle_mod.stencil_correlation(d, lam, x)
+    for s in range(27):
+        di, dj, dk = s % 3 - 1, (s // 3) % 3 - 1, s // 9 - 1
+        assert np.isclose(out[s], lam @ (refimpl.shift_matrix(d, di, dj, dk) @ x), rtol=1e-13, atol=1e-13)
+    A = refimpl.stencil_matrix(d, c).toarray()
+    xs = np.linalg.solve(A, b)
+    ls = np.linalg.solve(A.T, g)
+    grad = -oracle_mod.stencil_correlation(d, ls, xs)
+    eps = 1e-6
+    for s in (0, 4, 12, 13, 14, 22, 26):
+        cp, cm = c.copy(), c.copy()
+        cp[s] += eps
+        cm[s] -= eps
+        fd = (g @ np.linalg.solve(refimpl.stencil_matrix(d, cp).toarray(), b)
+              - g @ np.linalg.solve(refimpl.stencil_matrix(d, cm).toarray(), b)) / (2 * eps)
+        assert np.isclose(grad[s], fd, rtol=1e-6, atol=1e-9), (s, grad[s], fd)
