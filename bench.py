@@ -45,11 +45,15 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--iters", type=int, default=300, help="inner steps per timed solve")
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--cpu-iters", type=int, default=2, help="inner steps of the CPU-oracle sample")
+    ap.add_argument("--cpu-iters", type=int, default=20, help="inner steps of the CPU-oracle sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-validation", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the timed FP64 phase")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel profile")
+    ap.add_argument("--inner", choices=["fp32", "fp16", "bf16"], default="fp32",
+                    help="inner precision of the mixed-precision solver (fp16/bf16: 16-bit matrices)")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch every kernel from the host instead of replaying captured inner steps")
     return ap.parse_args()
 
 
@@ -134,6 +138,8 @@ def main():
     from paper_2507_11512_amd import perfmodel as pm
 
     torch.cuda.set_device(0)
+    graph = not args.eager
+    PREC = {"fp64": "fp64", "mxp": args.inner}
     n, L, m = args.n, args.levels, args.restart
     cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=0, restart=m)
     N = n ** 3
@@ -148,14 +154,18 @@ def main():
     n_d = n_ir = None
     val = {}
     if not args.no_validation:
+        xs = {}
         for prec in ("fp64", "mxp"):
-            x, st = P.solve(b, tol=1e-9, restart=m, max_iters=10000, precision=prec)
+            x, st = P.solve(b, tol=1e-9, restart=m, max_iters=10000, precision=PREC[prec], graph=graph)
             err = (x - 1.0).norm().item() / (N ** 0.5)
+            xs[prec] = x
             val[prec] = {"iters": st.iters, "restarts": st.restarts, "converged": st.converged,
                          "final_rel_res": st.final_rel_res, "time_to_1e-9_s": st.solve_ms / 1e3,
                          "x_err_vs_ones": err}
             log(f"validation {prec}: iters={st.iters} res={st.final_rel_res:.3e} "
                 f"|x-1|/|1|={err:.3e} time={st.solve_ms / 1e3:.3f}s")
+        val["mxp"]["x_err_vs_fp64"] = ((xs["mxp"] - xs["fp64"]).norm() / xs["fp64"].norm()).item()
+        del xs
         n_d, n_ir = val["fp64"]["iters"], val["mxp"]["iters"]
     penalty = pm.penalty(n_d, n_ir)
 
@@ -165,11 +175,11 @@ def main():
     res = {}
     for prec in (("mxp",) if args.no_fp64 else ("mxp", "fp64")):
         for _ in range(args.warmup):
-            P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec)
+            P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], graph=graph)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for s in range(args.steps):
-            _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec)
+            _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], graph=graph)
             assert st.iters == args.iters
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
@@ -182,9 +192,10 @@ def main():
     # ---- 4a. per-kernel profile (HIP events around each launch) ---------------------------
     kernels = {}
     dominant = None
-    prof_precs = () if args.no_profile else (("mxp", hp.F32),) if args.no_fp64 else (("mxp", hp.F32), ("fp64", hp.F64))
+    inner_code = {"fp32": hp.F32, "fp16": hp.F16, "bf16": hp.BF16}[args.inner]
+    prof_precs = () if args.no_profile else (("mxp", inner_code),) if args.no_fp64 else (("mxp", inner_code), ("fp64", hp.F64))
     for prec, dt_code in prof_precs:
-        _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=prec, profile=True)
+        _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], profile=True)
         B = kernel_bytes_table(cfg, cycles, dt_code, hp, pm)
         for (kid, lvl), nbytes in sorted(B.items()):
             ms, cnt = hp.profile_get(P.h, kid, lvl)
@@ -239,12 +250,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-inner/f64-outer",
+        "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)"}[args.inner]
+                 + "-inner/f64-outer",
         "data": "synthetic: generated 27-point stencil, b = A*1, x0 = 0",
-        "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta=0.5, GMRES({m})-IR, {L}-level "
+        "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta=0.5, GMRES({m})-IR ({args.inner} inner), {L}-level "
                                f"V-cycle fwd multicolour GS 1/1/1, {args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L,
-                   "iters_per_solve": args.iters},
+                   "iters_per_solve": args.iters,
+                   "launch": "eager" if args.eager else "hipGraph per inner step"},
         "fp64_gflops": round(fp64_gflops, 2) if fp64_gflops else None,
         "speedup_vs_fp64": round(value / fp64_gflops, 4) if fp64_gflops else None,
         "raw_speedup_vs_fp64": round(res["mxp"]["gflops_raw"] / fp64_gflops, 4) if fp64_gflops else None,

@@ -97,6 +97,9 @@ typedef struct {
 
 /* Solve flags. */
 #define HPGMX_SOLVE_PROFILE 1  /* time every kernel launch with HIP events   */
+#define HPGMX_SOLVE_GRAPH 2    /* replay each inner step as a captured hipGraph
+                                  (on a private stream ordered after and before
+                                  the handle's stream; ignored with PROFILE) */
 
 /* Alg. 3 parameters.  restart = m (1..63), max_iters counts inner steps over
  * all restarts, tol is the relative residual ||b - A x|| / ||b|| to reach

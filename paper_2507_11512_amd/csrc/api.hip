@@ -4,6 +4,8 @@
 #include "hpgmx_internal.hpp"
 
 #include <cmath>
+#include <map>
+#include <tuple>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -70,6 +72,18 @@ struct hpgmx_ctx {
     Ctrl *ctrl = nullptr;
     double *host_scal = nullptr;   // pinned copy of the Ctrl scalar block
     void *tmp[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+
+    // hipGraph replay of inner steps: a private stream (default priority) that
+    // can be captured, and one instantiated graph per (dtype, k, m).
+    hipStream_t own = nullptr;
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+
+    void drop_graphs()
+    {
+        for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
+        graphs.clear();
+    }
 
     // profiling
     bool prof = false;
@@ -277,6 +291,7 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
     }
     Krylov &K = c->kry[p];
     if (K.m < m) {
+        c->drop_graphs();  // captured graphs hold the old basis pointers
         if (!c->ws_base && K.Q) {
             hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
             for (auto it = c->owned.begin(); it != c->owned.end(); ++it)
@@ -431,6 +446,35 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
     auto col = [&](int j) { return (void *)(Q + (size_t)j * ldq * vb); };
 
     c->prof = (d->flags & HPGMX_SOLVE_PROFILE) != 0;
+    // Graph replay needs a capturable stream and no memset nodes (a level with
+    // zero sweeps clears its vector with a memset); profiling times single
+    // launches, so it runs eagerly.
+    const hpgmx_mg_desc &mgd = c->mg;
+    const bool use_graph = (d->flags & HPGMX_SOLVE_GRAPH) && !c->prof && mgd.pre_sweeps > 0 &&
+                           mgd.post_sweeps > 0 && mgd.coarsest_sweeps > 0;
+    hipStream_t user_stream = c->stream;
+    if (use_graph) {
+        if (!c->own) {
+            hip_check(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+            hip_check(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
+            hip_check(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
+        }
+        hip_check(hipEventRecord(c->ev_in, user_stream), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(c->own, c->ev_in, 0), "hipStreamWaitEvent");
+        c->stream = c->own;
+    }
+    struct RestoreStream {
+        hpgmx_ctx *c;
+        hipStream_t user;
+        bool on;
+        ~RestoreStream()
+        {
+            if (!on) return;
+            (void)hipEventRecord(c->ev_out, c->stream);
+            (void)hipStreamWaitEvent(user, c->ev_out, 0);
+            c->stream = user;
+        }
+    } restore{c, user_stream, use_graph};
     if (c->prof) {
         std::memset(c->prof_ms, 0, sizeof(c->prof_ms));
         std::memset(c->prof_n, 0, sizeof(c->prof_n));
@@ -482,22 +526,43 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             int kk = 0;
             for (int k = 0; k < m; ++k) {
                 if (rho / rho0 < d->tol) break;
-                vcycle(c, 0, p, col(k), K.z);
-                {
-                    ProfScope ps(c, HPGMX_K_SPMV_DOT, 0);
-                    launch_spmv_dot(A0, p, K.z, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
-                }
-                {
-                    ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
-                    launch_cgs_dot(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
-                }
-                {
-                    ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
-                    launch_cgs_norm(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
-                }
-                {
-                    ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
-                    launch_normalize(N, p, col(k + 1), c->ctrl, c->stream);
+                // one inner step: z = M^{-1} q_k, w = A z, CGS2, Givens, q_{k+1}
+                auto step = [&]() {
+                    vcycle(c, 0, p, col(k), K.z);
+                    {
+                        ProfScope ps(c, HPGMX_K_SPMV_DOT, 0);
+                        launch_spmv_dot(A0, p, K.z, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
+                        launch_cgs_dot(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
+                        launch_cgs_norm(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
+                        launch_normalize(N, p, col(k + 1), c->ctrl, c->stream);
+                    }
+                };
+                if (use_graph) {
+                    const auto key = std::make_tuple((int)p, k, m);
+                    auto it = c->graphs.find(key);
+                    if (it == c->graphs.end()) {
+                        hipGraph_t g = nullptr;
+                        hipGraphExec_t ge = nullptr;
+                        hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal),
+                                  "hipStreamBeginCapture");
+                        step();
+                        hip_check(hipStreamEndCapture(c->stream, &g), "hipStreamEndCapture");
+                        hip_check(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+                        (void)hipGraphDestroy(g);
+                        it = c->graphs.emplace(key, ge).first;
+                    }
+                    hip_check(hipGraphLaunch(it->second, c->stream), "hipGraphLaunch");
+                } else {
+                    step();
                 }
                 sc = read_scal(c);
                 rho = sc.rho;
@@ -916,6 +981,13 @@ hpgmx_status hpgmx_destroy(hpgmx_handle h)
     for (auto &e : h->evpool) {
         (void)hipEventDestroy(e.a);
         (void)hipEventDestroy(e.b);
+    }
+    h->drop_graphs();
+    if (h->own) {
+        (void)hipStreamSynchronize(h->own);
+        (void)hipStreamDestroy(h->own);
+        (void)hipEventDestroy(h->ev_in);
+        (void)hipEventDestroy(h->ev_out);
     }
     for (void *p : h->owned) (void)hipFree(p);
     if (h->host_scal) (void)hipHostFree(h->host_scal);

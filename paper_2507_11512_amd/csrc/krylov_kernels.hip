@@ -12,27 +12,12 @@
 // of the Hessenberg column (Alg. 3, "Update QR with Given's rotations") runs
 // in FP64 in the finish kernel of the norm pass, so the whole inner step
 // needs no host round trip except the small residual-estimate read.
-#include "hpgmx_internal.hpp"
+#include "ell_device.hpp"
 
+#include <cstdlib>
 #include <stdexcept>
 
 namespace hpgmx {
-
-template <typename V> struct VecOf2 { using T = float; };
-template <> struct VecOf2<double> { using T = double; };
-
-template <typename V> __device__ __forceinline__ V ldnt(const V *p) { return __builtin_nontemporal_load(p); }
-template <> __device__ __forceinline__ __half ldnt<__half>(const __half *p)
-{
-    return __ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
-}
-template <> __device__ __forceinline__ bf16 ldnt<bf16>(const bf16 *p)
-{
-    return __ushort_as_bfloat16(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
-}
-template <typename T, typename V> __device__ __forceinline__ T cv(V v) { return (T)v; }
-template <> __device__ __forceinline__ float cv<float, __half>(__half v) { return __half2float(v); }
-template <> __device__ __forceinline__ float cv<float, bf16>(bf16 v) { return __bfloat162float(v); }
 
 #define HPGMX_LAUNCH_CHECK()                                                    \
     do {                                                                        \
@@ -85,31 +70,28 @@ __device__ __forceinline__ i64 col_off(int j, int kb, i64 ldq) { return (i64)(j 
 
 // ---- w = A z fused with h1 = Q_{1:kb}^T w (Alg. 3: SpMV, then the first GEMVT) ----
 template <typename V, int KB>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, int remap, const V *__restrict__ offv,
                                                      const int *__restrict__ offc,
                                                      const V *__restrict__ diag,
-                                                     const typename VecOf2<V>::T *__restrict__ z,
-                                                     const typename VecOf2<V>::T *__restrict__ Q,
+                                                     const typename VecT<V>::T *__restrict__ z,
+                                                     const typename VecT<V>::T *__restrict__ Q,
                                                      i64 ldq, int kb,
-                                                     typename VecOf2<V>::T *__restrict__ w,
+                                                     typename VecT<V>::T *__restrict__ w,
                                                      double *partials, Ctrl *ctrl)
 {
-    using T = typename VecOf2<V>::T;
+    using T = typename VecT<V>::T;
     double acc[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    const i64 stride = (i64)gridDim.x * kBlock;
-    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+    RowLoop rl = row_loop(N, remap);
+    i64 p;
+    while (rl.next(p)) {
         T q[KB];
 #pragma unroll
         for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
         const EllRow er = ell_row(p, N, clog2);
-        T v = cv<T>(ldnt(diag + p)) * z[p];
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const i64 e = er.base + (i64)s * er.stride;
-            v += cv<T>(ldnt(offv + e)) * z[ldnt(offc + e)];
-        }
+        const T dz = to_t<T>(ld_stream(diag + p)) * z[p];
+        const T v = dz + ell_row_dot<T, V, kAllSlots>(offv, offc, z, er);
         w[p] = v;
         const double vd = (double)v;
 #pragma unroll
@@ -136,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 N, const T *__restrict__
 #pragma unroll
         for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
         double v = (double)w[p];
+        sched_fence();
 #pragma unroll
         for (int j = 0; j < KB; ++j) v -= c[j] * (double)q[j];
         const T vt = (T)v;
@@ -226,6 +209,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 N, const T *__restrict_
 #pragma unroll
         for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
         double v = (double)w[p];
+        sched_fence();
 #pragma unroll
         for (int j = 0; j < KB; ++j) v -= c[j] * (double)q[j];
         const T vt = (T)v;
@@ -245,7 +229,7 @@ __global__ __launch_bounds__(kBlock) void k_normalize(i64 N, T *__restrict__ w, 
 }
 
 // ---- FP64 outer residual r = b - A x with ||r||^2 (Alg. 3, residual step) ----
-__global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, const double *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, int remap, const double *__restrict__ offv,
                                                     const int *__restrict__ offc,
                                                     const double *__restrict__ diag,
                                                     const double *__restrict__ x,
@@ -254,16 +238,13 @@ __global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, const doub
                                                     Ctrl *ctrl, int m)
 {
     double acc[1] = {0.0};
-    const i64 stride = (i64)gridDim.x * kBlock;
-    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
+    RowLoop rl = row_loop(N, remap);
+    i64 p;
+    while (rl.next(p)) {
         const EllRow er = ell_row(p, N, clog2);
-        double v = ldnt(diag + p) * x[p];
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const i64 e = er.base + (i64)s * er.stride;
-            v += ldnt(offv + e) * x[ldnt(offc + e)];
-        }
-        const double rv = b[p] - v;
+        const double bp = b[p];
+        const double v = ld_stream(diag + p) * x[p] + ell_row_dot<double, double, kAllSlots>(offv, offc, x, er);
+        const double rv = bp - v;
         r[p] = rv;
         acc[0] += rv * rv;
     }
@@ -363,12 +344,18 @@ __global__ __launch_bounds__(kBlock) void k_stencil_corr(i64 N, int clog2, const
     for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
         const EllRow er = ell_row(p, N, clog2);
         const double l = lam[p];
-        acc[13] += l * x[p];
+        int ci[kSlots];
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int t = s < 13 ? s : s + 1;
-            acc[t] += l * x[ldnt(offc + er.base + (i64)s * er.stride)];
-        }
+        for (int s = 0; s < kSlots; ++s) ci[s] = ld_stream(offc + er.base + (i64)s * er.stride);
+        const double xp = x[p];
+        sched_fence();
+        double xv[kSlots];
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) xv[s] = x[ci[s]];
+        sched_fence();
+        acc[13] += l * xp;
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) acc[s < 13 ? s : s + 1] += l * xv[s];
     }
     store_partials<27>(acc, 27, partials);
 }
@@ -416,6 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(i64 N, const T *__restrict__ Q,
     T q[KB];
 #pragma unroll
     for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kk, ldq) + p];
+    sched_fence();
     double v = 0.0;
 #pragma unroll
     for (int j = 0; j < KB; ++j) v += c[j] * (double)q[j];
@@ -462,10 +450,10 @@ template <typename V>
 static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, const void *Q,
                        i64 ldq, int kb, void *w, double *partials, Ctrl *ctrl, hipStream_t s)
 {
-    using T = typename VecOf2<V>::T;
+    using T = typename VecT<V>::T;
     const dim3 gr(red_blocks(A.g.N)), bl(kBlock);
 #define HPGMX_KB_BODY                                                                          \
-    hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, A.clog2, v, A.col, d, (const T *)z, \
+    hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)z, \
                        (const T *)Q, ldq, kb, (T *)w, partials, ctrl)
     HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
@@ -533,7 +521,7 @@ void launch_resid64(const Matrix &A, const double *x, const double *b, double *r
                     double *partials, Ctrl *ctrl, int m, hipStream_t s)
 {
     const unsigned nb = (unsigned)red_blocks(A.g.N);
-    hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, A.v64, A.col,
+    hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, xcd_remap_enabled(), A.v64, A.col,
                        A.d64, x, b, r, partials, ctrl, m);
     finish(partials, (int)nb, 1, kFinishResid, ctrl, 0, m, s);
     HPGMX_LAUNCH_CHECK();

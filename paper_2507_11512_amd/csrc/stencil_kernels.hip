@@ -5,31 +5,27 @@
 // row per lane, slot-major ELL arrays read with non-temporal loads (each
 // matrix entry is used once per launch) and vector entries gathered through
 // the caches (each is reused by up to 26 rows).
-#include "hpgmx_internal.hpp"
+#include "ell_device.hpp"
 
+#include <cstdlib>
 #include <stdexcept>
 
 namespace hpgmx {
 
-// ---- element access ---------------------------------------------------------
-template <typename V> struct VecOf { using T = float; };
-template <> struct VecOf<double> { using T = double; };
-
-template <typename V> __device__ __forceinline__ V ldm(const V *p) { return __builtin_nontemporal_load(p); }
-template <> __device__ __forceinline__ __half ldm<__half>(const __half *p)
-{
-    return __ushort_as_half(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
-}
-template <> __device__ __forceinline__ bf16 ldm<bf16>(const bf16 *p)
-{
-    return __ushort_as_bfloat16(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
-}
-
-template <typename T, typename V> __device__ __forceinline__ T val(V v) { return (T)v; }
-template <> __device__ __forceinline__ float val<float, __half>(__half v) { return __half2float(v); }
-template <> __device__ __forceinline__ float val<float, bf16>(bf16 v) { return __bfloat162float(v); }
-
 __device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ i64 gtid_xcd(int remap)
+{
+    return (i64)xcd_tile(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
+}
+
+int xcd_remap_enabled()
+{
+    static const int on = [] {
+        const char *e = std::getenv("HPGMX_XCD_REMAP");
+        return (e && *e) ? (std::atoi(e) != 0) : 1;
+    }();
+    return on;
+}
 
 static inline unsigned grid_for(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
@@ -157,30 +153,26 @@ void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat
 // ---- SpMV -------------------------------------------------------------------------------
 // y = A x over all N rows (Sec. 3.2 ELL SpMV).
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, int remap, const V *__restrict__ offv,
                                                  const int *__restrict__ offc,
                                                  const V *__restrict__ diag,
-                                                 const typename VecOf<V>::T *__restrict__ x,
-                                                 typename VecOf<V>::T *__restrict__ y)
+                                                 const typename VecT<V>::T *__restrict__ x,
+                                                 typename VecT<V>::T *__restrict__ y)
 {
-    using T = typename VecOf<V>::T;
-    const i64 p = gtid();
+    using T = typename VecT<V>::T;
+    const i64 p = gtid_xcd(remap);
     if (p >= N) return;
     const EllRow er = ell_row(p, N, clog2);
-    T acc = val<T>(ldm(diag + p)) * x[p];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        const i64 e = er.base + (i64)s * er.stride;
-        acc += val<T>(ldm(offv + e)) * x[ldm(offc + e)];
-    }
-    y[p] = acc;
+    const T dx = to_t<T>(ld_stream(diag + p)) * x[p];
+    y[p] = dx + ell_row_dot<T, V, kAllSlots>(offv, offc, x, er);
 }
 
 template <typename V>
 static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void *y, hipStream_t s)
 {
-    using T = typename VecOf<V>::T;
-    hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2, v, A.col, d,
+    using T = typename VecT<V>::T;
+    hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2,
+                       xcd_remap_enabled(), v, A.col, d,
                        (const T *)x, (T *)y);
     HPGMX_LAUNCH_CHECK();
 }
@@ -205,40 +197,33 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s)
 // that couple to colours relaxed earlier in the sweep (the others still hold
 // zero, and skipping them gives the same result bit for bit).
 template <typename V, unsigned MASK>
-__global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2,
+__global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
                                                const V *__restrict__ offv,
                                                const int *__restrict__ offc,
                                                const V *__restrict__ diag,
-                                               const typename VecOf<V>::T *__restrict__ r,
-                                               typename VecOf<V>::T *z)
+                                               const typename VecT<V>::T *__restrict__ r,
+                                               typename VecT<V>::T *z)
 {
-    using T = typename VecOf<V>::T;
-    const i64 t = gtid();
+    using T = typename VecT<V>::T;
+    const i64 t = gtid_xcd(remap);
     if (t >= cnt) return;
     const i64 p = row0 + t;
     const EllRow er = ell_row(p, N, clog2);
-    T acc = r[p];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        if (MASK & (1u << s)) {
-            const i64 e = er.base + (i64)s * er.stride;
-            acc -= val<T>(ldm(offv + e)) * z[ldm(offc + e)];
-        }
-    }
-    z[p] = acc / val<T>(ldm(diag + p));
+    const T rp = r[p];
+    const T dg = to_t<T>(ld_stream(diag + p));
+    z[p] = (rp - ell_row_dot<T, V, MASK>(offv, offc, z, er)) / dg;
 }
 
-constexpr unsigned kFullMask = (1u << kSlots) - 1u;
 
 template <typename V, unsigned MASK>
 static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z,
                       hipStream_t s)
 {
-    using T = typename VecOf<V>::T;
+    using T = typename VecT<V>::T;
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
     hipLaunchKernelGGL((k_gs<V, MASK>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N,
-                       A.clog2, v, A.col, d, (const T *)r, (T *)z);
+                       A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)r, (T *)z);
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -250,7 +235,7 @@ static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const
                  hipStream_t s)
 {
     if (mode == kGsFull) {
-        gs_launch<V, kFullMask>(A, v, d, c, r, z, s);
+        gs_launch<V, kAllSlots>(A, v, d, c, r, z, s);
     } else if (mode == kGsZeroForward) {
         switch (c) {
             HPGMX_GS_CASE(0, true) HPGMX_GS_CASE(1, true) HPGMX_GS_CASE(2, true) HPGMX_GS_CASE(3, true)
@@ -280,34 +265,32 @@ void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, v
 // coarse level's natural order: row q of that block is coarse point
 // (q % cx, (q / cx) % cy, q / (cx cy)).  Only those rows are evaluated.
 template <typename V>
-__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2, int remap,
+                                                     const V *__restrict__ offv,
                                                      const int *__restrict__ offc,
                                                      const V *__restrict__ diag,
-                                                     const typename VecOf<V>::T *__restrict__ r,
-                                                     const typename VecOf<V>::T *__restrict__ z,
-                                                     typename VecOf<V>::T *__restrict__ rc)
+                                                     const typename VecT<V>::T *__restrict__ r,
+                                                     const typename VecT<V>::T *__restrict__ z,
+                                                     typename VecT<V>::T *__restrict__ rc)
 {
-    using T = typename VecOf<V>::T;
-    const i64 q = gtid();
+    using T = typename VecT<V>::T;
+    const i64 q = gtid_xcd(remap);
     if (q >= gc.N) return;
     const i64 N = gf.N, p = gf.off[4] + q;
     const EllRow er = ell_row(p, N, clog2);
-    T acc = val<T>(ldm(diag + p)) * z[p];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        const i64 e = er.base + (i64)s * er.stride;
-        acc += val<T>(ldm(offv + e)) * z[ldm(offc + e)];
-    }
+    const T rp = r[p];
+    const T acc = to_t<T>(ld_stream(diag + p)) * z[p] + ell_row_dot<T, V, kAllSlots>(offv, offc, z, er);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
-    rc[to_internal(gc, I, J, K)] = r[p] - acc;
+    rc[to_internal(gc, I, J, K)] = rp - acc;
 }
 
 template <typename V>
 static void restrict_t(const Matrix &A, const Geom &gc, const V *v, const V *d, const void *r,
                        const void *z, void *rc, hipStream_t s)
 {
-    using T = typename VecOf<V>::T;
-    hipLaunchKernelGGL(k_restrict<V>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc, A.clog2, v, A.col,
+    using T = typename VecT<V>::T;
+    hipLaunchKernelGGL(k_restrict<V>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc, A.clog2,
+                       xcd_remap_enabled(), v, A.col,
                        d, (const T *)r, (const T *)z, (T *)rc);
     HPGMX_LAUNCH_CHECK();
 }

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(HERE, "libhpgmx.so")
 F64, F32, F16, BF16 = 0, 1, 2, 3
 GS_FORWARD, GS_BACKWARD, GS_SYMMETRIC = 0, 1, 2
 SOLVE_PROFILE = 1
+SOLVE_GRAPH = 2
 
 K_GS, K_GS_ZERO, K_RESTRICT, K_PROLONG, K_SPMV_DOT, K_CGS_DOT, K_CGS_NORM, K_NORMALIZE, \
     K_RESID64, K_CAST, K_TRSM, K_GEMV, K_UPDATE, K_PERMUTE = range(14)
@@ -181,13 +182,13 @@ def mg_setup(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD):
 
 
 def gmres_ir_solve(h, b, x, restart=30, max_iters=10000, tol=1e-9, inner_dtype=F32,
-                   hist_len=0, profile=False):
+                   hist_len=0, profile=False, graph=False):
     """Solves in place: x holds x0 on entry and the solution on exit."""
     import numpy as np
     hist = np.zeros(max(hist_len, 1))
     desc = SolveDesc(int(restart), int(max_iters), float(tol), int(inner_dtype),
                      hist.ctypes.data_as(C.POINTER(C.c_double)) if hist_len > 0 else None,
-                     int(hist_len), SOLVE_PROFILE if profile else 0)
+                     int(hist_len), (SOLVE_PROFILE if profile else 0) | (SOLVE_GRAPH if graph else 0))
     st = SolveStats()
     _check(h, lib.hpgmx_gmres_ir_solve(h, _ptr(b), _ptr(x), C.byref(desc), C.byref(st)))
     s = Stats(st.iters, st.restarts, bool(st.converged), bool(st.breakdown), st.rho0,
@@ -287,12 +288,12 @@ class Problem:
         return b
 
     def solve(self, b, x0=None, tol=1e-9, restart=30, max_iters=10000, precision="mxp",
-              hist_len=0, profile=False):
+              hist_len=0, profile=False, graph=False):
         import torch
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         prec = self._PREC[precision] if isinstance(precision, str) else int(precision)
         with torch.cuda.stream(self.stream):
-            out = gmres_ir_solve(self.h, b, x, restart, max_iters, tol, prec, hist_len, profile)
+            out = gmres_ir_solve(self.h, b, x, restart, max_iters, tol, prec, hist_len, profile, graph)
         return (x, *out) if isinstance(out, tuple) else (x, out)
 
     def stencil_grad(self, lam, x):

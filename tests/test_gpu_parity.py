@@ -323,3 +323,22 @@ def test_zero_guess_ignores_stale_contents(hp, dtype):
     zc = nan.clone()
     hp.vcycle(P.h, dtype, dev(r, dtype), zc)
     assert bool(torch.isfinite(zc).all())
+
+
+@pytest.mark.parametrize("precision", ["mxp", "fp64"])
+@pytest.mark.parametrize("restart", [30, 5])
+def test_graph_replay_matches_eager(hp, precision, restart):
+    """Inner steps replayed from captured hipGraphs give bit-identical solves,
+    on every replay, with eager work in between."""
+    import torch
+    dims = (32, 32, 32)
+    P = problem(hp, dims, 4)
+    b = dev(oracle.spmv(dims, inputs.ones(dims)), 0)
+    x_e, st_e = P.solve(b, tol=1e-9, restart=restart, precision=precision)
+    y = torch.zeros(P.N, dtype=torch.float32, device="cuda")
+    for rep in range(3):
+        x_g, st_g = P.solve(b, tol=1e-9, restart=restart, precision=precision, graph=True)
+        assert st_g.iters == st_e.iters and st_g.restarts == st_e.restarts
+        assert torch.equal(x_g, x_e), rep
+        hp.spmv(P.h, 0, 1, x_g.float(), y)      # eager work between replays
+        torch.cuda.synchronize()
