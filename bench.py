@@ -17,6 +17,12 @@ Phases (Sec. 3 "The HPG-MxP benchmark"):
      HBM bandwidth, a streaming-copy bandwidth reference, and the CPU oracle
      timed on a bounded sample of the same workload.
 `value` = flops(model) / time of the mixed-precision solves x min(1, n_d/n_ir).
+
+With --nrhs k (k = 2..8) the same phases run on k right-hand sides at once
+through the batched solver (the batched workload: 192^3, k = 8,
+b_j = A u_j with u_j ~ N(0, 1) seeded 11512 + j): the batched kernels'
+tile shapes are autotuned first, `value` is the aggregate rate over the k
+right-hand sides, and n_d, n_ir are summed over them.
 """
 import argparse
 import hashlib
@@ -54,6 +60,10 @@ def parse():
                     help="inner precision of the mixed-precision solver (fp16/bf16: 16-bit matrices)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying captured inner steps")
+    ap.add_argument("--nrhs", type=int, default=1,
+                    help="right-hand sides solved at once (>1: the batched solver)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched runs: keep the library's fixed tile rule")
     return ap.parse_args()
 
 
@@ -98,9 +108,51 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
     return B
 
 
+def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
+    """As kernel_bytes_table for K right-hand sides in lockstep."""
+    from collections import defaultdict
+    B = defaultdict(float)
+    L = pm.level_dims(cfg.dims, cfg.levels)
+
+    def vcyc():
+        for l, d in enumerate(L):
+            rows = pm.nrows(d)
+            coarsest = l == cfg.levels - 1
+            nsweeps_zero = 1 if (cfg.coarsest if coarsest else cfg.pre) > 0 else 0
+            for c in range(8):
+                B[(hp.K_GS_ZERO, l)] += nsweeps_zero * pm.bgs_colour_bytes(
+                    rows // 8, pm.zero_guess_active_slots(c), dtype, K)
+            full = (cfg.coarsest - 1) if coarsest else (cfg.pre - 1 + cfg.post)
+            B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.bgs_colour_bytes(rows // 8, pm.SLOTS, dtype, K)
+            if not coarsest:
+                rc = pm.nrows(L[l + 1])
+                B[(hp.K_RESTRICT, l)] += pm.brestrict_bytes(rc, dtype, K)
+                B[(hp.K_PROLONG, l)] += pm.bprolong_bytes(rc, dtype, K)
+
+    N = pm.nrows(cfg.dims)
+    w = pm.wb(dtype)
+    for kk in cycles:
+        B[(hp.K_RESID64, 0)] += pm.bresid64_bytes(N, K)
+        B[(hp.K_CAST, 0)] += N * K * (8 + w)
+        for k in range(kk):
+            vcyc()
+            B[(hp.K_SPMV, 0)] += pm.bspmv_bytes(N, dtype, K)
+            B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, K)
+            B[(hp.K_CGS_DOT, 0)] += K * pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_CGS_NORM, 0)] += K * pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_NORMALIZE, 0)] += 2 * N * K * w
+        B[(hp.K_GEMV, 0)] += N * K * (kk + 1) * w
+        vcyc()
+        B[(hp.K_UPDATE, 0)] += N * K * (16 + w)
+    B[(hp.K_RESID64, 0)] += pm.bresid64_bytes(N, K)
+    B[(hp.K_PERMUTE, 0)] += 3 * 2 * N * K * 8
+    return B
+
+
 def source_sha():
     h = hashlib.sha256()
-    for f in ("stencil_kernels.hip", "krylov_kernels.hip", "api.hip", "hpgmx_internal.hpp"):
+    for f in ("stencil_kernels.hip", "krylov_kernels.hip", "krylov_batch.hip", "batch_kernels.hip",
+              "hpgmx_internal.hpp", "ell_device.hpp", "krylov_device.hpp"):
         with open(os.path.join(ROOT, "paper_2507_11512_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -138,6 +190,8 @@ def main():
     from paper_2507_11512_amd import perfmodel as pm
 
     torch.cuda.set_device(0)
+    if args.nrhs > 1:
+        return run_batched(args, hp, pm, torch, np)
     graph = not args.eager
     PREC = {"fp64": "fp64", "mxp": args.inner}
     n, L, m = args.n, args.levels, args.restart
@@ -196,16 +250,7 @@ def main():
     prof_precs = () if args.no_profile else (("mxp", inner_code),) if args.no_fp64 else (("mxp", inner_code), ("fp64", hp.F64))
     for prec, dt_code in prof_precs:
         _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], profile=True)
-        B = kernel_bytes_table(cfg, cycles, dt_code, hp, pm)
-        for (kid, lvl), nbytes in sorted(B.items()):
-            ms, cnt = hp.profile_get(P.h, kid, lvl)
-            if cnt == 0 or ms <= 0:
-                continue
-            name = f"{hp.KERNEL_NAMES[kid]}_l{lvl}_{prec}"
-            gbps = nbytes / (ms / 1e3) / 1e9
-            kernels[name] = {"launches": cnt, "total_ms": round(ms, 4), "avg_us": round(ms / cnt * 1e3, 3),
-                             "bytes_per_launch": nbytes / cnt, "GBps": round(gbps, 1),
-                             "frac_peak": round(gbps / PEAK_HBM_GBPS, 4)}
+        profile_kernels(hp, P.h, kernel_bytes_table(cfg, cycles, dt_code, hp, pm), prec, kernels)
         log(f"profiled {prec} solve: {st.solve_ms:.1f} ms with events")
     mxp_k = {k: v for k, v in kernels.items() if k.endswith("_mxp")}
     dom_name = max(mxp_k, key=lambda k: mxp_k[k]["total_ms"]) if mxp_k else None
@@ -272,6 +317,154 @@ def main():
                      "bytes_per_launch": dominant["bytes_per_launch"] if dominant else None,
                      "avg_us": dominant["avg_us"] if dominant else None,
                      "traffic": traffic, "copy_GBps": round(copy_gbps, 1)},
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    P.close()
+    print(json.dumps(out), flush=True)
+
+
+def profile_kernels(hp, handle, table, prec_tag, kernels):
+    for (kid, lvl), nbytes in sorted(table.items()):
+        ms, cnt = hp.profile_get(handle, kid, lvl)
+        if cnt == 0 or ms <= 0:
+            continue
+        name = f"{hp.KERNEL_NAMES[kid]}_l{lvl}_{prec_tag}"
+        gbps = nbytes / (ms / 1e3) / 1e9
+        kernels[name] = {"launches": cnt, "total_ms": round(ms, 4), "avg_us": round(ms / cnt * 1e3, 3),
+                         "bytes_per_launch": nbytes / cnt, "GBps": round(gbps, 1),
+                         "frac_peak": round(gbps / PEAK_HBM_GBPS, 4)}
+
+
+def run_batched(args, hp, pm, torch, np):
+    """The phases of main() for k right-hand sides in lockstep."""
+    k = args.nrhs
+    if k > hp.MAX_BATCH:
+        raise SystemExit(f"--nrhs must be at most {hp.MAX_BATCH}")
+    graph = not args.eager
+    n, L, m = args.n, args.levels, args.restart
+    cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=0, restart=m)
+    N = n ** 3
+    from paper_2507_11512_amd import inputs
+    log(f"setup {n}^3 levels={L}, {k} right-hand sides (device: {torch.cuda.get_device_name(0)})")
+    t = time.time()
+    P = hp.Problem(n, beta=0.5, levels=L, sweep="forward")
+    U_ = torch.stack([torch.from_numpy(inputs.batch_u((n, n, n), j)) for j in range(k)]).cuda()
+    B = torch.empty_like(U_)
+    for j in range(k):
+        hp.rhs_from_x(P.h, U_[j], B[j])
+    torch.cuda.synchronize()
+    log(f"setup done in {time.time() - t:.2f}s")
+    tuning = {}
+    if not args.no_autotune:
+        for name, code in (("fp32", hp.F32), ("fp64", hp.F64)):
+            tt = hp.batch_autotune(P.h, k, code)
+            tuning[name] = {hp.BK_NAMES[b]: tt["rhs_per_lane"][b][:L] for b in range(hp.BK_COUNT)}
+            log(f"autotuned tiles ({name}): {tuning[name]}")
+
+    PREC = {"fp64": "fp64", "mxp": "mxp"}
+    val = {}
+    n_d = n_ir = None
+    if not args.no_validation:
+        xs = {}
+        for prec in ("fp64", "mxp"):
+            X, sts = P.solve_batched(B, tol=1e-9, restart=m, precision=PREC[prec], graph=graph)
+            errs = [((X[j] - U_[j]).norm() / U_[j].norm()).item() for j in range(k)]
+            xs[prec] = X
+            val[prec] = {"iters": [s.iters for s in sts], "converged": all(s.converged for s in sts),
+                         "max_final_rel_res": max(s.final_rel_res for s in sts),
+                         "time_to_1e-9_s": sts[0].solve_ms / 1e3, "max_x_err_vs_u": max(errs)}
+            log(f"validation {prec}: iters={val[prec]['iters']} max res={val[prec]['max_final_rel_res']:.3e} "
+                f"max |x-u|/|u|={max(errs):.3e} time={sts[0].solve_ms / 1e3:.3f}s")
+        val["mxp"]["max_x_err_vs_fp64"] = max(
+            ((xs["mxp"][j] - xs["fp64"][j]).norm() / xs["fp64"][j].norm()).item() for j in range(k))
+        del xs
+        n_d, n_ir = sum(val["fp64"]["iters"]), sum(val["mxp"]["iters"])
+    penalty = pm.penalty(n_d, n_ir)
+
+    cycles = pm.fixed_iteration_cycles(args.iters, m)
+    flops = k * pm.solve_flops(cfg, cycles)
+    res = {}
+    for prec in (("mxp",) if args.no_fp64 else ("mxp", "fp64")):
+        for _ in range(args.warmup):
+            P.solve_batched(B, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, sts = P.solve_batched(B, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec],
+                                     graph=graph)
+            assert all(s.iters == args.iters for s in sts)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        res[prec] = {"s_per_solve": dt, "gflops_raw": flops / dt / 1e9}
+        log(f"timed batched {prec}: {dt * 1e3:.1f} ms per {k}-rhs solve ({args.iters} iters) -> "
+            f"{flops / dt / 1e9:.1f} GFLOP/s raw")
+    value = res["mxp"]["gflops_raw"] * penalty
+    fp64_gflops = res["fp64"]["gflops_raw"] if "fp64" in res else None
+
+    kernels = {}
+    if not args.no_profile:
+        for prec, code in (("mxp", hp.F32),) + (() if args.no_fp64 else (("fp64", hp.F64),)):
+            _, sts = P.solve_batched(B, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec],
+                                     profile=True)
+            profile_kernels(hp, P.h, kernel_bytes_table_batched(cfg, cycles, code, 8 if k > 4 else (4 if k > 2 else 2),
+                                                                hp, pm), prec, kernels)
+            log(f"profiled batched {prec} solve: {sts[0].solve_ms:.1f} ms with events")
+    mxp_k = {kk_: v for kk_, v in kernels.items() if kk_.endswith("_mxp")}
+    dom_name = max(mxp_k, key=lambda q: mxp_k[q]["total_ms"]) if mxp_k else None
+    dominant = mxp_k[dom_name] if mxp_k else None
+    for name, v in sorted(mxp_k.items(), key=lambda kv: -kv[1]["total_ms"])[:12]:
+        log(f"  {name:24s} {v['total_ms']:9.2f} ms  {v['launches']:6d} launches  {v['GBps']:7.1f} GB/s")
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        bh = B[0].cpu().numpy()
+        t0 = time.perf_counter()
+        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0)
+        dt = time.perf_counter() - t0
+        cflops = pm.solve_flops(cfg, [args.cpu_iters])
+        cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"{n}^3 FP64 oracle on right-hand side 0 alone (the oracle solves one at a time), "
+                         f"one GMRES({m}) cycle cut at {args.cpu_iters} inner steps, {dt:.1f} s wall"}
+        log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
+
+    traffic = load_traffic(dom_name, dominant["bytes_per_launch"]) if dominant else None
+    out = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["mxp"]["s_per_solve"] * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-inner/f64-outer",
+        "data": f"synthetic: generated 27-point stencil, b_j = A u_j, u_j ~ N(0,1) seeded 11512+j, x0 = 0",
+        "config": {"workload": f"hpg-mxp batched {n}^3 27-pt nonsym beta=0.5, {k} right-hand sides, "
+                               f"GMRES({m})-IR (fp32 inner), {L}-level V-cycle fwd multicolour GS 1/1/1, "
+                               f"{args.iters} inner steps per solve",
+                   "grid": [n, n, n], "unknowns": N, "nrhs": k, "restart": m, "levels": L,
+                   "iters_per_solve": args.iters,
+                   "launch": "eager" if args.eager else "hipGraph per inner step",
+                   "tiles": tuning or "fixed rule"},
+        "fp64_gflops": round(fp64_gflops, 2) if fp64_gflops else None,
+        "speedup_vs_fp64": round(value / fp64_gflops, 4) if fp64_gflops else None,
+        "raw_speedup_vs_fp64": round(res["mxp"]["gflops_raw"] / fp64_gflops, 4) if fp64_gflops else None,
+        "penalty": round(penalty, 4),
+        "n_d": n_d, "n_ir": n_ir,
+        "validation": val,
+        "fp64_ms_per_step": round(res["fp64"]["s_per_solve"] * 1e3, 3) if "fp64" in res else None,
+        "flops_per_solve": flops,
+        "roofline": {"bound": "hbm", "kernel": dom_name,
+                     "achieved": dominant["GBps"] if dominant else None, "peak": PEAK_HBM_GBPS,
+                     "unit": "GB/s", "frac": dominant["frac_peak"] if dominant else None,
+                     "bytes_per_launch": dominant["bytes_per_launch"] if dominant else None,
+                     "avg_us": dominant["avg_us"] if dominant else None,
+                     "traffic": traffic},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

@@ -218,9 +218,88 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
 #define HPGMX_K_GEMV 11        /* u = Q y                                      */
 #define HPGMX_K_UPDATE 12      /* x += z in FP64                              */
 #define HPGMX_K_PERMUTE 13     /* natural <-> colour-blocked order            */
-#define HPGMX_K_COUNT 14
+#define HPGMX_K_SPMV 14        /* w = A z alone (batched solves)              */
+#define HPGMX_K_DOT 15         /* h1 = Q^T w alone (batched solves)           */
+#define HPGMX_K_COUNT 16
 hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *total_ms,
                                long long *launches);
+
+/* ---- several right-hand sides at once --------------------------------------
+ * A batch of nrhs <= 8 right-hand sides shares one pass over the matrix: the
+ * SpMV, the Gauss-Seidel sweeps and the fused restriction read each matrix
+ * row once for all of them (Sec. 3.2's kernels, generalised to a block of
+ * vectors), while every right-hand side keeps its own Krylov basis,
+ * Hessenberg matrix, rotations and convergence test.  Batched vectors are
+ * passed as nrhs contiguous vectors one after the other, [nrhs][N] in the
+ * natural order of the level (a row-major (nrhs, N) tensor).  Internally
+ * the batch is padded to K = 2, 4 or 8 interleaved vectors; padded entries
+ * are zero.  Batched calls take dtype HPGMX_F64 or HPGMX_F32 (EINVAL for the
+ * 16-bit matrix types).
+ *
+ * Tile shapes.  The batched stencil kernels run R of the K right-hand sides
+ * of a row per lane (R = 1, 2, 4 or 8, R <= K; K / R lanes share a row).
+ * hpgmx_batch_autotune times every R for every kernel kind and level on the
+ * device and keeps the fastest; without it the library uses a fixed rule
+ * (R = K on levels with at least 2^22 / K rows, R = 1 below).  The choice
+ * never changes results: per (row, right-hand side) the arithmetic is the
+ * same for every R. */
+#define HPGMX_BK_SPMV 0      /* batched SpMV                                  */
+#define HPGMX_BK_GS 1        /* one colour of a batched GS sweep              */
+#define HPGMX_BK_GS_ZERO 2   /* one colour of a batched sweep from zero       */
+#define HPGMX_BK_RESTRICT 3  /* batched fused residual-restriction            */
+#define HPGMX_BK_RESID64 4   /* batched FP64 outer residual (level 0)         */
+#define HPGMX_BK_COUNT 5
+typedef struct {
+    int rhs_per_lane[HPGMX_BK_COUNT][8]; /* R per kernel kind and level (0 = rule) */
+    double ms[HPGMX_BK_COUNT][8];        /* autotune: time of the chosen R (ms;
+                                            a full sweep for the GS kinds)     */
+} hpgmx_batch_tuning;
+
+/* Times every tile shape for a batch of nrhs right-hand sides with matrices
+ * in `dtype`, adopts the fastest, and writes the table to *out (may be
+ * NULL).  Blocks.  Overwrites the handle's batched work vectors. */
+hpgmx_status hpgmx_batch_autotune(hpgmx_handle h, int nrhs, int dtype, hpgmx_batch_tuning *out);
+
+/* Adopts a tile table (entries 0 use the fixed rule; others must divide the
+ * padded batch width K).  hpgmx_batch_get_tuning reads the table in use. */
+hpgmx_status hpgmx_batch_set_tuning(hpgmx_handle h, int nrhs, int dtype, const hpgmx_batch_tuning *in);
+hpgmx_status hpgmx_batch_get_tuning(hpgmx_handle h, int nrhs, int dtype, hpgmx_batch_tuning *out);
+
+/* Extra device bytes the batched state for nrhs right-hand sides, the
+ * hierarchy `mg`, restart length `restart` and the inner dtypes in
+ * dtype_mask (bits 1 << HPGMX_F64, 1 << HPGMX_F32) needs on top of
+ * hpgmx_workspace_bytes (a bound workspace must hold both). */
+hpgmx_status hpgmx_workspace_bytes_batched(hpgmx_handle h, const hpgmx_mg_desc *mg, int nrhs, int restart,
+                                           unsigned dtype_mask, size_t *bytes);
+
+/* Y[j] = A_level X[j] for j < nrhs (X, Y: [nrhs][N_level], must not overlap). */
+hpgmx_status hpgmx_spmv_batched(hpgmx_handle h, int level, int dtype, int nrhs, const void *X, void *Y);
+
+/* One Gauss-Seidel sweep of kind `sweep` for every right-hand side
+ * (as hpgmx_smooth; R, Z: [nrhs][N_level], Z updated in place). */
+hpgmx_status hpgmx_smooth_batched(hpgmx_handle h, int level, int dtype, int sweep, int nrhs,
+                                  const void *R, void *Z, int zero_guess);
+
+/* Z[j] = M^{-1} R[j]: one batched V-cycle per right-hand side (as
+ * hpgmx_vcycle; R, Z: [nrhs][N]). */
+hpgmx_status hpgmx_vcycle_batched(hpgmx_handle h, int dtype, int nrhs, const void *R, void *Z);
+
+/* Alg. 3 for nrhs right-hand sides in lockstep.  B: FP64 [nrhs][N]; X: FP64
+ * [nrhs][N], initial guesses on entry, solutions on exit; stats: nrhs
+ * entries (may be NULL).  desc->inner_dtype is HPGMX_F64 or HPGMX_F32;
+ * desc->res_hist_host, if set, holds nrhs rows of res_hist_len entries.
+ * Right-hand side j follows exactly the sequence of steps its own
+ * hpgmx_gmres_ir_solve would take: it stops taking Krylov steps in a cycle
+ * when its estimate drops below tol, when its new Krylov vector breaks down,
+ * or when its own iteration count reaches max_iters; the others carry on,
+ * and a right-hand side that has stopped leaves its solution untouched
+ * (its extra lockstep work is discarded).  The call returns when every
+ * right-hand side has converged or run out of iterations.  Flag
+ * HPGMX_SOLVE_AUTOTUNE runs hpgmx_batch_autotune first if this (nrhs,
+ * dtype) has no table yet. */
+#define HPGMX_SOLVE_AUTOTUNE 4
+hpgmx_status hpgmx_gmres_ir_solve_batched(hpgmx_handle h, int nrhs, const double *B, double *X,
+                                          const hpgmx_solve_desc *desc, hpgmx_solve_stats *stats);
 
 /* Streaming copy of `bytes` (multiple of 16) from src to dst, `reps` times,
  * timed with HIP events: the measured-bandwidth reference for the roofline

@@ -49,6 +49,29 @@ struct Krylov {
 
 inline int vt_of(Prec p) { return p == P64 ? 0 : 1; }
 
+// Tile table of the batched stencil kernels: R (right-hand sides per lane)
+// per kernel kind and level; 0 = the fixed rule.
+struct BatchTune {
+    int R[HPGMX_BK_COUNT][kMaxLevels] = {};
+    double ms[HPGMX_BK_COUNT][kMaxLevels] = {};
+    bool set = false;
+};
+
+// State of batched solves with K interleaved right-hand sides.  Vectors are
+// [N][K] in the colour-blocked order; those that are gathered from hold
+// (N + 1) K entries with row N zero.
+struct Batch {
+    int K = 0;
+    double *b = nullptr, *x = nullptr, *r64 = nullptr;      // FP64, level 0
+    Ctrl *ctrl = nullptr;                                    // one per right-hand side
+    double *partials = nullptr;                              // kMaxBasis * K columns
+    double *host_scal = nullptr;                             // pinned scalar blocks
+    void *lr[2][kMaxLevels] = {}, *lz[2][kMaxLevels] = {};  // levels >= 1, [0] double, [1] float
+    Krylov kry[2];                                           // per vector type
+    void *tmp[2][3] = {};                                    // ABI staging and autotuning
+    BatchTune tune[2];
+};
+
 }  // namespace
 
 struct hpgmx_ctx {
@@ -77,7 +100,10 @@ struct hpgmx_ctx {
     // can be captured, and one instantiated graph per (dtype, k, m).
     hipStream_t own = nullptr;
     hipEvent_t ev_in = nullptr, ev_out = nullptr;
-    std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;
+    std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (dtype, k, m, K)
+
+    // batched solves, by interleave width K
+    std::map<int, Batch> batches;
 
     void drop_graphs()
     {
@@ -430,6 +456,63 @@ Scal read_scal(hpgmx_ctx *c)
     return s;
 }
 
+// Graph replay needs a capturable stream and no memset nodes (a level with
+// zero sweeps clears its vector with a memset); profiling times single
+// launches, so it runs eagerly.
+bool graphs_allowed(const hpgmx_ctx *c, const hpgmx_solve_desc *d)
+{
+    const hpgmx_mg_desc &mgd = c->mg;
+    return (d->flags & HPGMX_SOLVE_GRAPH) && !c->prof && mgd.pre_sweeps > 0 && mgd.post_sweeps > 0 &&
+           mgd.coarsest_sweeps > 0;
+}
+
+// While alive (and `on`), the handle's work goes to its private stream,
+// ordered after the work already on the caller's stream and before the
+// caller's later work.
+struct GraphStream {
+    hpgmx_ctx *c;
+    hipStream_t user;
+    bool on;
+    GraphStream(hpgmx_ctx *c_, bool on_) : c(c_), user(c_->stream), on(on_)
+    {
+        if (!on) return;
+        if (!c->own) {
+            hip_check(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+            hip_check(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
+            hip_check(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
+        }
+        hip_check(hipEventRecord(c->ev_in, user), "hipEventRecord");
+        hip_check(hipStreamWaitEvent(c->own, c->ev_in, 0), "hipStreamWaitEvent");
+        c->stream = c->own;
+    }
+    ~GraphStream()
+    {
+        if (!on) return;
+        (void)hipEventRecord(c->ev_out, c->stream);
+        (void)hipStreamWaitEvent(user, c->ev_out, 0);
+        c->stream = user;
+    }
+};
+
+// Runs `step` as an instantiated graph: captured on first use of `key`,
+// replayed afterwards.
+template <typename F>
+void replay_step(hpgmx_ctx *c, const std::tuple<int, int, int, int> &key, F &&step)
+{
+    auto it = c->graphs.find(key);
+    if (it == c->graphs.end()) {
+        hipGraph_t g = nullptr;
+        hipGraphExec_t ge = nullptr;
+        hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+        step();
+        hip_check(hipStreamEndCapture(c->stream, &g), "hipStreamEndCapture");
+        hip_check(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+        (void)hipGraphDestroy(g);
+        it = c->graphs.emplace(key, ge).first;
+    }
+    hip_check(hipGraphLaunch(it->second, c->stream), "hipGraphLaunch");
+}
+
 hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_desc *d,
                    hpgmx_solve_stats *st)
 {
@@ -449,32 +532,8 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
     // Graph replay needs a capturable stream and no memset nodes (a level with
     // zero sweeps clears its vector with a memset); profiling times single
     // launches, so it runs eagerly.
-    const hpgmx_mg_desc &mgd = c->mg;
-    const bool use_graph = (d->flags & HPGMX_SOLVE_GRAPH) && !c->prof && mgd.pre_sweeps > 0 &&
-                           mgd.post_sweeps > 0 && mgd.coarsest_sweeps > 0;
-    hipStream_t user_stream = c->stream;
-    if (use_graph) {
-        if (!c->own) {
-            hip_check(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking), "hipStreamCreateWithFlags");
-            hip_check(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming), "hipEventCreate");
-            hip_check(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming), "hipEventCreate");
-        }
-        hip_check(hipEventRecord(c->ev_in, user_stream), "hipEventRecord");
-        hip_check(hipStreamWaitEvent(c->own, c->ev_in, 0), "hipStreamWaitEvent");
-        c->stream = c->own;
-    }
-    struct RestoreStream {
-        hpgmx_ctx *c;
-        hipStream_t user;
-        bool on;
-        ~RestoreStream()
-        {
-            if (!on) return;
-            (void)hipEventRecord(c->ev_out, c->stream);
-            (void)hipStreamWaitEvent(user, c->ev_out, 0);
-            c->stream = user;
-        }
-    } restore{c, user_stream, use_graph};
+    const bool use_graph = graphs_allowed(c, d);
+    GraphStream gs_scope(c, use_graph);
     if (c->prof) {
         std::memset(c->prof_ms, 0, sizeof(c->prof_ms));
         std::memset(c->prof_n, 0, sizeof(c->prof_n));
@@ -494,7 +553,7 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
         ProfScope ps(c, HPGMX_K_PERMUTE, 0);
         launch_nat2int(g0, P64, x, P64, c->x_int, c->stream);
     }
-    launch_norm64(N, c->b_int, c->partials, c->ctrl, c->stream);
+    launch_norm64(N, 1, c->b_int, c->partials, c->ctrl, kFinishRho0, 0, c->stream);
     Scal sc = read_scal(c);
     const double rho0 = sc.rho0;
     S.rho0 = rho0;
@@ -521,7 +580,7 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             if (its >= d->max_iters) break;
             {
                 ProfScope ps(c, HPGMX_K_CAST, 0);
-                launch_cast(N, p, c->r64, c->ctrl, col(0), c->stream);
+                launch_cast(N, 1, p, c->r64, c->ctrl, col(0), c->stream);
             }
             int kk = 0;
             for (int k = 0; k < m; ++k) {
@@ -535,35 +594,19 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                     }
                     {
                         ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
-                        launch_cgs_dot(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                        launch_cgs_dot(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
-                        launch_cgs_norm(N, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
+                        launch_cgs_norm(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
-                        launch_normalize(N, p, col(k + 1), c->ctrl, c->stream);
+                        launch_normalize(N, 1, p, col(k + 1), c->ctrl, c->stream);
                     }
                 };
-                if (use_graph) {
-                    const auto key = std::make_tuple((int)p, k, m);
-                    auto it = c->graphs.find(key);
-                    if (it == c->graphs.end()) {
-                        hipGraph_t g = nullptr;
-                        hipGraphExec_t ge = nullptr;
-                        hip_check(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal),
-                                  "hipStreamBeginCapture");
-                        step();
-                        hip_check(hipStreamEndCapture(c->stream, &g), "hipStreamEndCapture");
-                        hip_check(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0), "hipGraphInstantiate");
-                        (void)hipGraphDestroy(g);
-                        it = c->graphs.emplace(key, ge).first;
-                    }
-                    hip_check(hipGraphLaunch(it->second, c->stream), "hipGraphLaunch");
-                } else {
-                    step();
-                }
+                if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, 1), step);
+                else step();
                 sc = read_scal(c);
                 rho = sc.rho;
                 kk = k + 1;
@@ -577,11 +620,11 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             if (sc.nonfinite) { status = HPGMX_ENONFINITE; c->err = "Krylov vector is not finite"; break; }
             {
                 ProfScope ps(c, HPGMX_K_TRSM, 0);
-                launch_trsm(c->ctrl, kk, m, c->stream);
+                launch_trsm(c->ctrl, KCount{{kk}}, 1, m, c->stream);
             }
             {
                 ProfScope ps(c, HPGMX_K_GEMV, 0);
-                launch_gemv(N, p, K.Q, ldq, kk, c->ctrl, K.u, c->stream);
+                launch_gemv(N, 1, p, K.Q, ldq, kk, c->ctrl, K.u, c->stream);
             }
             vcycle(c, 0, p, K.u, K.z);
             {
@@ -609,6 +652,441 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
     return status;
 }
 
+// ---- batched solves ------------------------------------------------------------------------------
+int batch_width(int nrhs) { return nrhs <= 2 ? 2 : nrhs <= 4 ? 4 : 8; }
+
+void *gathered_batch(hpgmx_ctx *c, i64 N, int K, Prec p)
+{
+    const size_t vb = vec_bytes(p);
+    char *v = (char *)c->dalloc((size_t)(N + 1) * K * vb);
+    hip_check(hipMemsetAsync(v + (size_t)N * K * vb, 0, K * vb, c->stream), "hipMemsetAsync");
+    return v;
+}
+
+// The staging buffers serve every level: re-zero row N of the level used.
+void zero_batch_row(hpgmx_ctx *c, void *v, i64 N, int K, Prec p)
+{
+    const size_t vb = vec_bytes(p);
+    hip_check(hipMemsetAsync((char *)v + (size_t)N * K * vb, 0, K * vb, c->stream), "hipMemsetAsync");
+}
+
+Batch &ensure_batch(hpgmx_ctx *c, int K)
+{
+    Batch &B = c->batches[K];
+    if (B.K) return B;
+    const i64 N0 = c->lv[0].A.g.N;
+    B.b = (double *)c->dalloc((size_t)N0 * K * 8);
+    B.x = (double *)gathered_batch(c, N0, K, P64);
+    B.r64 = (double *)c->dalloc((size_t)N0 * K * 8);
+    B.ctrl = (Ctrl *)c->dalloc(K * sizeof(Ctrl));
+    hip_check(hipMemsetAsync(B.ctrl, 0, K * sizeof(Ctrl), c->stream), "hipMemsetAsync");
+    B.partials = (double *)c->dalloc((size_t)kMaxRedBlocks * kMaxBasis * K * 8);
+    if (!B.host_scal)
+        hip_check(hipHostMalloc((void **)&B.host_scal, (size_t)K * 64, hipHostMallocDefault), "hipHostMalloc");
+    B.K = K;
+    return B;
+}
+
+// Level vectors and (m > 0) the Krylov workspace of vector type p.
+void ensure_batch_prec(hpgmx_ctx *c, Batch &B, Prec p, int m)
+{
+    const int vt = vt_of(p), K = B.K;
+    ensure_prec(c, p);
+    ensure_prec(c, P64);
+    for (size_t l = 1; l < c->lv.size(); ++l) {
+        if (!B.lr[vt][l]) {
+            B.lr[vt][l] = gathered_batch(c, c->lv[l].A.g.N, K, p);
+            B.lz[vt][l] = gathered_batch(c, c->lv[l].A.g.N, K, p);
+        }
+    }
+    if (m <= 0) return;
+    const i64 N0 = c->lv[0].A.g.N;
+    Krylov &Kr = B.kry[vt];
+    if (Kr.m < m) {
+        c->drop_graphs();
+        if (!c->ws_base && Kr.Q) {
+            hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+            for (auto it = c->owned.begin(); it != c->owned.end(); ++it)
+                if (*it == Kr.Q) { (void)hipFree(Kr.Q); c->owned.erase(it); break; }
+        }
+        Kr.ldq = krylov_ldq(N0 * K);
+        Kr.Q = c->dalloc((size_t)Kr.ldq * (m + 1) * vec_bytes(p));
+        Kr.m = m;
+    }
+    if (!Kr.z) {
+        Kr.z = gathered_batch(c, N0, K, p);
+        Kr.u = c->dalloc((size_t)N0 * K * vec_bytes(p));
+    }
+}
+
+void ensure_batch_tmp(hpgmx_ctx *c, Batch &B, int vt)
+{
+    const i64 N0 = c->lv[0].A.g.N;
+    for (int i = 0; i < 3; ++i)
+        if (!B.tmp[vt][i]) B.tmp[vt][i] = gathered_batch(c, N0, B.K, vt == 0 ? P64 : P32);
+}
+
+// R of a batched kernel: the adopted table, else the fixed rule (every lane
+// takes the whole row on large levels, one right-hand side per lane on
+// small ones, where parallelism is scarce).
+int tile_r(const hpgmx_ctx *c, const Batch &B, Prec p, int kind, int l)
+{
+    const int R = B.tune[vt_of(p)].R[kind][l];
+    if (R > 0) return R;
+    return c->lv[l].A.g.N * B.K >= (1ll << 22) ? B.K : 1;
+}
+
+void bsweep_colours(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z, bool forward, bool zero,
+                    int skip_first_colour)
+{
+    const Matrix &A = c->lv[l].A;
+    const int R = tile_r(c, B, p, zero ? HPGMX_BK_GS_ZERO : HPGMX_BK_GS, l);
+    for (int n = 0; n < 8; ++n) {
+        const int col = forward ? n : 7 - n;
+        if (n == 0 && skip_first_colour) continue;
+        const int mode = !zero ? kGsFull : forward ? kGsZeroForward : kGsZeroBackward;
+        ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
+        launch_bgs_colour(A, p, B.K, R, col, mode, r, z, c->stream);
+    }
+}
+
+void bsmooth_level(hpgmx_ctx *c, Batch &B, int l, Prec p, int kind, const void *r, void *z, bool zero,
+                   int nsweeps)
+{
+    if (nsweeps <= 0) {
+        if (zero)
+            hip_check(hipMemsetAsync(z, 0, (size_t)c->lv[l].A.g.N * B.K * vec_bytes(p), c->stream),
+                      "hipMemsetAsync");
+        return;
+    }
+    for (int s = 0; s < nsweeps; ++s) {
+        const bool zg = zero && s == 0;
+        if (kind == HPGMX_GS_FORWARD) {
+            bsweep_colours(c, B, l, p, r, z, true, zg, 0);
+        } else if (kind == HPGMX_GS_BACKWARD) {
+            bsweep_colours(c, B, l, p, r, z, false, zg, 0);
+        } else {
+            bsweep_colours(c, B, l, p, r, z, true, zg, 0);
+            bsweep_colours(c, B, l, p, r, z, false, false, 1);  // colour 7 is unchanged
+        }
+    }
+}
+
+// The V-cycle of vcycle() for K right-hand sides at once.
+void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z)
+{
+    const hpgmx_mg_desc &mg = c->mg;
+    const int vt = vt_of(p);
+    if (l == mg.levels - 1) {
+        bsmooth_level(c, B, l, p, mg.sweep, r, z, true, mg.coarsest_sweeps);
+        return;
+    }
+    const Geom &gc = c->lv[l + 1].A.g;
+    bsmooth_level(c, B, l, p, mg.sweep, r, z, true, mg.pre_sweeps);
+    {
+        ProfScope ps(c, HPGMX_K_RESTRICT, l);
+        launch_brestrict(c->lv[l].A, gc, p, B.K, tile_r(c, B, p, HPGMX_BK_RESTRICT, l), r, z, B.lr[vt][l + 1],
+                         c->stream);
+    }
+    bvcycle(c, B, l + 1, p, B.lr[vt][l + 1], B.lz[vt][l + 1]);
+    {
+        ProfScope ps(c, HPGMX_K_PROLONG, l);
+        launch_bprolong(c->lv[l].A.g, gc, p, B.K, B.lz[vt][l + 1], z, c->stream);
+    }
+    bsmooth_level(c, B, l, p, mg.sweep, r, z, false, mg.post_sweeps);
+}
+
+// Times every R for every batched kernel kind and level (on zeroed staging
+// vectors) and adopts the fastest.
+void autotune(hpgmx_ctx *c, Batch &B, Prec p)
+{
+    const int vt = vt_of(p), K = B.K;
+    ensure_batch_prec(c, B, p, 0);
+    ensure_batch_tmp(c, B, vt);
+    ensure_batch_tmp(c, B, 0);
+    const i64 N0 = c->lv[0].A.g.N;
+    for (int w = 0; w < 2; ++w)
+        for (int i = 0; i < 3; ++i)
+            if (B.tmp[w][i])
+                hip_check(hipMemsetAsync(B.tmp[w][i], 0, (size_t)(N0 + 1) * K * (w == 0 ? 8 : 4), c->stream),
+                          "hipMemsetAsync");
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    constexpr int kReps = 5;
+    auto time_it = [&](auto &&launch) -> double {
+        launch();
+        hip_check(hipEventRecord(e0, c->stream), "hipEventRecord");
+        for (int r = 0; r < kReps; ++r) launch();
+        hip_check(hipEventRecord(e1, c->stream), "hipEventRecord");
+        hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+        return ms / kReps;
+    };
+    BatchTune T{};
+    for (int k = 0; k < HPGMX_BK_COUNT; ++k)
+        for (int l = 0; l < kMaxLevels; ++l) T.ms[k][l] = -1.0;
+    void *t0 = B.tmp[vt][0], *t1 = B.tmp[vt][1], *t2 = B.tmp[vt][2];
+    const int L = (int)c->lv.size();
+    for (int l = 0; l < L; ++l) {
+        const Matrix &A = c->lv[l].A;
+        for (int R = 1; R <= K; R *= 2) {
+            double t[HPGMX_BK_COUNT];
+            for (double &v : t) v = -1.0;
+            t[HPGMX_BK_SPMV] = time_it([&] { launch_bspmv(A, p, K, R, t0, t1, c->stream); });
+            t[HPGMX_BK_GS] = time_it([&] {
+                for (int col = 0; col < 8; ++col) launch_bgs_colour(A, p, K, R, col, kGsFull, t0, t1, c->stream);
+            });
+            t[HPGMX_BK_GS_ZERO] = time_it([&] {
+                for (int col = 0; col < 8; ++col)
+                    launch_bgs_colour(A, p, K, R, col, kGsZeroForward, t0, t1, c->stream);
+            });
+            if (l + 1 < L)
+                t[HPGMX_BK_RESTRICT] = time_it(
+                    [&] { launch_brestrict(A, c->lv[l + 1].A.g, p, K, R, t0, t1, t2, c->stream); });
+            if (l == 0)
+                t[HPGMX_BK_RESID64] = time_it([&] {
+                    launch_bresid64(A, K, R, (const double *)B.tmp[0][0], (const double *)B.tmp[0][1],
+                                    (double *)B.tmp[0][2], B.partials, B.ctrl, 1, c->stream);
+                });
+            for (int k = 0; k < HPGMX_BK_COUNT; ++k) {
+                if (t[k] < 0.0) continue;
+                if (T.ms[k][l] < 0.0 || t[k] < T.ms[k][l]) {
+                    T.ms[k][l] = t[k];
+                    T.R[k][l] = R;
+                }
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    for (int k = 0; k < HPGMX_BK_COUNT; ++k)
+        for (int l = 0; l < kMaxLevels; ++l)
+            if (T.ms[k][l] < 0.0) T.ms[k][l] = 0.0;
+    T.set = true;
+    B.tune[vt] = T;
+    c->drop_graphs();  // captured steps hold the old tiles
+}
+
+void read_scal_batch(hpgmx_ctx *c, Batch &B, Scal *out)
+{
+    hip_check(hipMemcpy2DAsync(B.host_scal, sizeof(Scal), &B.ctrl[0].rho, sizeof(Ctrl), sizeof(Scal), B.K,
+                               hipMemcpyDeviceToHost, c->stream),
+              "hipMemcpy2DAsync");
+    hip_check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+    std::memcpy(out, B.host_scal, B.K * sizeof(Scal));
+}
+
+hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const hpgmx_solve_desc *d,
+                    hpgmx_solve_stats *st)
+{
+    const int m = d->restart;
+    const Prec p = (Prec)d->inner_dtype;
+    const int K = batch_width(nrhs);
+    Batch &B = ensure_batch(c, K);
+    ensure_batch_prec(c, B, p, m);
+    if ((d->flags & HPGMX_SOLVE_AUTOTUNE) && !B.tune[vt_of(p)].set) autotune(c, B, p);
+    Krylov &Kr = B.kry[vt_of(p)];
+    const Matrix &A0 = c->lv[0].A;
+    const Geom &g0 = A0.g;
+    const i64 N = g0.N, M = N * K;
+    const size_t vb = vec_bytes(p);
+    char *Q = (char *)Kr.Q;
+    const i64 ldq = Kr.ldq;
+    auto col = [&](int j) { return (void *)(Q + (size_t)j * ldq * vb); };
+
+    c->prof = (d->flags & HPGMX_SOLVE_PROFILE) != 0;
+    const bool use_graph = graphs_allowed(c, d);
+    GraphStream gs_scope(c, use_graph);
+    if (c->prof) {
+        std::memset(c->prof_ms, 0, sizeof(c->prof_ms));
+        std::memset(c->prof_n, 0, sizeof(c->prof_n));
+        c->evused = 0;
+    }
+    hpgmx_solve_stats S[kMaxBatch] = {};
+    hipEvent_t e0, e1;
+    hip_check(hipEventCreate(&e0), "hipEventCreate");
+    hip_check(hipEventCreate(&e1), "hipEventCreate");
+    hip_check(hipEventRecord(e0, c->stream), "hipEventRecord");
+    {
+        ProfScope ps(c, HPGMX_K_PERMUTE, 0);
+        launch_bnat2int(g0, P64, P64, K, nrhs, Bn, B.b, c->stream);
+    }
+    {
+        ProfScope ps(c, HPGMX_K_PERMUTE, 0);
+        launch_bnat2int(g0, P64, P64, K, nrhs, Xn, B.x, c->stream);
+    }
+    launch_norm64(M, K, B.b, B.partials, B.ctrl, kFinishRho0, 0, c->stream);
+    Scal sc[kMaxBatch];
+    read_scal_batch(c, B, sc);
+    double rho0[kMaxBatch], rho[kMaxBatch];
+    bool done[kMaxBatch];
+    int its[kMaxBatch] = {};
+    hpgmx_status status = HPGMX_OK;
+    for (int j = 0; j < K; ++j) {
+        rho0[j] = sc[j].rho0;
+        S[j].rho0 = rho0[j];
+        if (j < nrhs && sc[j].nonfinite) {
+            status = HPGMX_ENONFINITE;
+            c->err = "right-hand side " + std::to_string(j) + " is not finite";
+        }
+        done[j] = rho0[j] == 0.0;  // b = 0: x = 0 (set below)
+        if (done[j]) S[j].converged = 1;
+    }
+    if (status == HPGMX_OK) {
+        for (;;) {
+            {
+                ProfScope ps(c, HPGMX_K_RESID64, 0);
+                launch_bresid64(A0, K, tile_r(c, B, p, HPGMX_BK_RESID64, 0), B.x, B.b, B.r64, B.partials, B.ctrl,
+                                m, c->stream);
+            }
+            read_scal_batch(c, B, sc);
+            bool bad = false, any = false;
+            for (int j = 0; j < K; ++j) {
+                rho[j] = sc[j].rho;
+                if (done[j]) continue;
+                S[j].final_rel_res = rho[j] / rho0[j];
+                if (sc[j].nonfinite) { bad = true; continue; }
+                if (rho[j] / rho0[j] < d->tol) { S[j].converged = 1; done[j] = true; continue; }
+                if (its[j] >= d->max_iters) { done[j] = true; continue; }
+                any = true;
+            }
+            if (bad) { status = HPGMX_ENONFINITE; c->err = "outer residual is not finite"; break; }
+            if (!any) break;
+            {
+                ProfScope ps(c, HPGMX_K_CAST, 0);
+                launch_cast(M, K, p, B.r64, B.ctrl, col(0), c->stream);
+            }
+            int kk[kMaxBatch] = {};
+            bool cyc[kMaxBatch];
+            for (int j = 0; j < K; ++j) cyc[j] = !done[j];
+            bool nonfin = false;
+            for (int k = 0; k < m; ++k) {
+                bool act = false;
+                for (int j = 0; j < K; ++j) {
+                    if (cyc[j] && rho[j] / rho0[j] < d->tol) cyc[j] = false;
+                    act = act || cyc[j];
+                }
+                if (!act) break;
+                // one inner step for every right-hand side: z = M^{-1} q_k,
+                // w = A z, CGS2, Givens, q_{k+1}
+                auto step = [&]() {
+                    bvcycle(c, B, 0, p, col(k), Kr.z);
+                    {
+                        ProfScope ps(c, HPGMX_K_SPMV, 0);
+                        launch_bspmv(A0, p, K, tile_r(c, B, p, HPGMX_BK_SPMV, 0), Kr.z, col(k + 1), c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_DOT, 0);
+                        launch_dot(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
+                        launch_cgs_dot(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
+                        launch_cgs_norm(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, k, m, c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
+                        launch_normalize(M, K, p, col(k + 1), B.ctrl, c->stream);
+                    }
+                };
+                if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, K), step);
+                else step();
+                read_scal_batch(c, B, sc);
+                for (int j = 0; j < K; ++j) {
+                    if (!cyc[j]) continue;
+                    rho[j] = sc[j].rho;
+                    kk[j] = k + 1;
+                    ++its[j];
+                    if (d->res_hist_host && j < nrhs && its[j] - 1 < d->res_hist_len)
+                        d->res_hist_host[(size_t)j * d->res_hist_len + its[j] - 1] = rho[j] / rho0[j];
+                    S[j].est_rel_res = rho[j] / rho0[j];
+                    if (sc[j].nonfinite) { nonfin = true; cyc[j] = false; continue; }
+                    if (sc[j].breakdown) { S[j].breakdown = 1; cyc[j] = false; continue; }
+                    if (its[j] >= d->max_iters) cyc[j] = false;
+                }
+                if (nonfin) break;
+            }
+            if (nonfin) { status = HPGMX_ENONFINITE; c->err = "Krylov vector is not finite"; break; }
+            KCount kc{};
+            int kmax = 0;
+            for (int j = 0; j < K; ++j) {
+                kc.v[j] = kk[j];
+                kmax = kk[j] > kmax ? kk[j] : kmax;
+                if (kk[j] > 0) ++S[j].restarts;
+            }
+            {
+                ProfScope ps(c, HPGMX_K_TRSM, 0);
+                launch_trsm(B.ctrl, kc, K, m, c->stream);
+            }
+            {
+                ProfScope ps(c, HPGMX_K_GEMV, 0);
+                launch_gemv(M, K, p, Kr.Q, ldq, kmax, B.ctrl, Kr.u, c->stream);
+            }
+            bvcycle(c, B, 0, p, Kr.u, Kr.z);
+            {
+                ProfScope ps(c, HPGMX_K_UPDATE, 0);
+                launch_update(M, p, Kr.z, B.x, c->stream);
+            }
+        }
+        for (int j = 0; j < K; ++j) S[j].iters = its[j];
+        {
+            ProfScope ps(c, HPGMX_K_PERMUTE, 0);
+            launch_bint2nat(g0, P64, P64, K, nrhs, B.x, Xn, c->stream);
+        }
+        for (int j = 0; j < nrhs; ++j)
+            if (rho0[j] == 0.0)
+                hip_check(hipMemsetAsync(Xn + (size_t)j * N, 0, (size_t)N * 8, c->stream), "hipMemsetAsync");
+    }
+    hip_check(hipEventRecord(e1, c->stream), "hipEventRecord");
+    hip_check(hipEventSynchronize(e1), "hipEventSynchronize");
+    float ms = 0.f;
+    hip_check(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (c->prof) c->prof_collect();
+    c->prof = false;
+    if (st)
+        for (int j = 0; j < nrhs; ++j) {
+            st[j] = S[j];
+            st[j].solve_ms = ms;
+        }
+    return status;
+}
+
+size_t plan_batch_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int nrhs, int m, unsigned mask)
+{
+    const int K = batch_width(nrhs);
+    size_t tot = 0;
+    auto add = [&](size_t b) { tot += round_up(b ? b : 1); };
+    const size_t N0 = (size_t)pd.nx * pd.ny * pd.nz;
+    add(N0 * K * 8); add((N0 + 1) * K * 8); add(N0 * K * 8);  // b, x, r in FP64
+    add(K * sizeof(Ctrl));
+    add((size_t)kMaxRedBlocks * kMaxBasis * K * 8);
+    for (int vt = 0; vt < 2; ++vt) {
+        if (!((mask >> (vt == 0 ? HPGMX_F64 : HPGMX_F32)) & 1u)) continue;
+        const size_t vb = vt == 0 ? 8 : 4;
+        int nx = pd.nx / 2, ny = pd.ny / 2, nz = pd.nz / 2;
+        for (int l = 1; l < mg.levels; ++l) {
+            const size_t N = (size_t)nx * ny * nz;
+            add((N + 1) * K * vb);
+            add((N + 1) * K * vb);
+            nx /= 2; ny /= 2; nz /= 2;
+        }
+        add((size_t)krylov_ldq((i64)(N0 * K)) * (m + 1) * vb);
+        add((N0 + 1) * K * vb);
+        add(N0 * K * vb);
+        for (int i = 0; i < 3; ++i) add((N0 + 1) * K * vb);  // staging (ABI calls, autotuning)
+    }
+    if (!((mask >> HPGMX_F64) & 1u))
+        for (int i = 0; i < 3; ++i) add((N0 + 1) * K * 8);  // FP64 staging of the residual tuning
+    return tot;
+}
+
 // ---- argument checks --------------------------------------------------------------------------
 void check_ready(hpgmx_ctx *c)
 {
@@ -632,6 +1110,41 @@ void check_level(hpgmx_ctx *c, int level, bool need_coarser)
 void check_ptr(const void *p, const char *name)
 {
     if (!p) fail(HPGMX_EINVAL, std::string(name) + " is NULL");
+}
+
+Prec check_batch_dtype(int dtype)
+{
+    if (dtype != HPGMX_F64 && dtype != HPGMX_F32)
+        fail(HPGMX_EINVAL, "batched calls take dtype HPGMX_F64 or HPGMX_F32");
+    return (Prec)dtype;
+}
+
+void check_nrhs(int nrhs)
+{
+    if (nrhs < 1 || nrhs > kMaxBatch) fail(HPGMX_EINVAL, "nrhs must be 1..8");
+}
+
+void check_solve_desc(const hpgmx_solve_desc *desc)
+{
+    check_ptr(desc, "desc");
+    if (desc->restart < 1 || desc->restart > kMaxRestart) fail(HPGMX_EINVAL, "restart must be 1..63");
+    if (desc->max_iters < 0) fail(HPGMX_EINVAL, "max_iters must be >= 0");
+    if (!(desc->tol >= 0.0)) fail(HPGMX_EINVAL, "tol must be >= 0");
+    check_dtype(desc->inner_dtype);
+    if (desc->res_hist_len < 0) fail(HPGMX_EINVAL, "res_hist_len must be >= 0");
+}
+
+void fill_tuning(const hpgmx_ctx *c, const Batch &B, Prec p, hpgmx_batch_tuning *out)
+{
+    std::memset(out, 0, sizeof(*out));
+    const int L = (int)c->lv.size();
+    for (int k = 0; k < HPGMX_BK_COUNT; ++k)
+        for (int l = 0; l < L && l < 8; ++l) {
+            if (k == HPGMX_BK_RESTRICT && l + 1 >= L) continue;
+            if (k == HPGMX_BK_RESID64 && l > 0) continue;
+            out->rhs_per_lane[k][l] = tile_r(c, B, p, k, l);
+            out->ms[k][l] = B.tune[vt_of(p)].ms[k][l];
+        }
 }
 
 template <typename F>
@@ -776,12 +1289,7 @@ hpgmx_status hpgmx_gmres_ir_solve(hpgmx_handle h, const double *b, double *x,
         check_ready(h);
         check_ptr(b, "b");
         check_ptr(x, "x");
-        check_ptr(desc, "desc");
-        if (desc->restart < 1 || desc->restart > kMaxRestart) fail(HPGMX_EINVAL, "restart must be 1..63");
-        if (desc->max_iters < 0) fail(HPGMX_EINVAL, "max_iters must be >= 0");
-        if (!(desc->tol >= 0.0)) fail(HPGMX_EINVAL, "tol must be >= 0");
-        check_dtype(desc->inner_dtype);
-        if (desc->res_hist_len < 0) fail(HPGMX_EINVAL, "res_hist_len must be >= 0");
+        check_solve_desc(desc);
         return solve(h, b, x, desc, stats);
     });
 }
@@ -934,6 +1442,156 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
     });
 }
 
+hpgmx_status hpgmx_workspace_bytes_batched(hpgmx_handle h, const hpgmx_mg_desc *mg, int nrhs, int restart,
+                                           unsigned dtype_mask, size_t *bytes)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ptr(mg, "mg");
+        check_ptr(bytes, "bytes");
+        check_nrhs(nrhs);
+        if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
+        if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
+        *bytes = plan_batch_bytes(h->prob, *mg, nrhs, restart, dtype_mask & 0x3u);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_batch_autotune(hpgmx_handle h, int nrhs, int dtype, hpgmx_batch_tuning *out)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        Batch &B = ensure_batch(h, batch_width(nrhs));
+        autotune(h, B, p);
+        if (out) fill_tuning(h, B, p, out);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_batch_set_tuning(hpgmx_handle h, int nrhs, int dtype, const hpgmx_batch_tuning *in)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        check_ptr(in, "in");
+        const int K = batch_width(nrhs);
+        for (int k = 0; k < HPGMX_BK_COUNT; ++k)
+            for (int l = 0; l < 8; ++l) {
+                const int R = in->rhs_per_lane[k][l];
+                if (R != 0 && !batch_shape_ok(K, R))
+                    fail(HPGMX_EINVAL, "rhs_per_lane must be 0 or a power of two dividing " + std::to_string(K));
+            }
+        Batch &B = ensure_batch(h, K);
+        BatchTune T{};
+        for (int k = 0; k < HPGMX_BK_COUNT; ++k)
+            for (int l = 0; l < 8 && l < kMaxLevels; ++l) {
+                T.R[k][l] = in->rhs_per_lane[k][l];
+                T.ms[k][l] = in->ms[k][l];
+            }
+        T.set = true;
+        B.tune[vt_of(p)] = T;
+        h->drop_graphs();
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_batch_get_tuning(hpgmx_handle h, int nrhs, int dtype, hpgmx_batch_tuning *out)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        check_ptr(out, "out");
+        Batch &B = ensure_batch(h, batch_width(nrhs));
+        fill_tuning(h, B, p, out);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_spmv_batched(hpgmx_handle h, int level, int dtype, int nrhs, const void *X, void *Y)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, false);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        check_ptr(X, "X");
+        check_ptr(Y, "Y");
+        const int K = batch_width(nrhs), vt = vt_of(p);
+        Batch &B = ensure_batch(h, K);
+        ensure_batch_prec(h, B, p, 0);
+        ensure_batch_tmp(h, B, vt);
+        const Matrix &A = h->lv[level].A;
+        zero_batch_row(h, B.tmp[vt][0], A.g.N, K, p);
+        launch_bnat2int(A.g, p, p, K, nrhs, X, B.tmp[vt][0], h->stream);
+        launch_bspmv(A, p, K, tile_r(h, B, p, HPGMX_BK_SPMV, level), B.tmp[vt][0], B.tmp[vt][1], h->stream);
+        launch_bint2nat(A.g, p, p, K, nrhs, B.tmp[vt][1], Y, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_smooth_batched(hpgmx_handle h, int level, int dtype, int sweep, int nrhs, const void *R,
+                                  void *Z, int zero_guess)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, false);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        if (sweep < HPGMX_GS_FORWARD || sweep > HPGMX_GS_SYMMETRIC) fail(HPGMX_EINVAL, "unknown sweep kind");
+        check_ptr(R, "R");
+        check_ptr(Z, "Z");
+        const int K = batch_width(nrhs), vt = vt_of(p);
+        Batch &B = ensure_batch(h, K);
+        ensure_batch_prec(h, B, p, 0);
+        ensure_batch_tmp(h, B, vt);
+        const Matrix &A = h->lv[level].A;
+        zero_batch_row(h, B.tmp[vt][1], A.g.N, K, p);
+        launch_bnat2int(A.g, p, p, K, nrhs, R, B.tmp[vt][0], h->stream);
+        if (!zero_guess) launch_bnat2int(A.g, p, p, K, nrhs, Z, B.tmp[vt][1], h->stream);
+        bsmooth_level(h, B, level, p, sweep, B.tmp[vt][0], B.tmp[vt][1], zero_guess != 0, 1);
+        launch_bint2nat(A.g, p, p, K, nrhs, B.tmp[vt][1], Z, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_vcycle_batched(hpgmx_handle h, int dtype, int nrhs, const void *R, void *Z)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        check_ptr(R, "R");
+        check_ptr(Z, "Z");
+        const int K = batch_width(nrhs), vt = vt_of(p);
+        Batch &B = ensure_batch(h, K);
+        ensure_batch_prec(h, B, p, 0);
+        ensure_batch_tmp(h, B, vt);
+        const Matrix &A = h->lv[0].A;
+        zero_batch_row(h, B.tmp[vt][1], A.g.N, K, p);
+        launch_bnat2int(A.g, p, p, K, nrhs, R, B.tmp[vt][0], h->stream);
+        bvcycle(h, B, 0, p, B.tmp[vt][0], B.tmp[vt][1]);
+        launch_bint2nat(A.g, p, p, K, nrhs, B.tmp[vt][1], Z, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_gmres_ir_solve_batched(hpgmx_handle h, int nrhs, const double *B, double *X,
+                                          const hpgmx_solve_desc *desc, hpgmx_solve_stats *stats)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_nrhs(nrhs);
+        check_ptr(B, "B");
+        check_ptr(X, "X");
+        check_solve_desc(desc);
+        check_batch_dtype(desc->inner_dtype);
+        return bsolve(h, nrhs, B, X, desc, stats);
+    });
+}
+
 hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *total_ms,
                                long long *launches)
 {
@@ -991,6 +1649,8 @@ hpgmx_status hpgmx_destroy(hpgmx_handle h)
     }
     for (void *p : h->owned) (void)hipFree(p);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
+    for (auto &kv : h->batches)
+        if (kv.second.host_scal) (void)hipHostFree(kv.second.host_scal);
     delete h;
     return HPGMX_OK;
 }

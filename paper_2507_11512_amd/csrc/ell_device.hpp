@@ -13,6 +13,8 @@
 
 #include "hpgmx_internal.hpp"
 
+#include <stdexcept>
+
 namespace hpgmx {
 
 template <typename V> struct VecT { using T = float; };
@@ -111,5 +113,119 @@ __device__ __forceinline__ RowLoop row_loop(i64 N, int remap)
 
 // Remapping switch (HPGMX_XCD_REMAP=0 turns it off for layout studies).
 int xcd_remap_enabled();
+
+__device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ i64 gtid_xcd(int remap)
+{
+    return (i64)xcd_tile(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
+}
+
+static inline unsigned grid_for(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+#define HPGMX_LAUNCH_CHECK()                                                    \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));  \
+    } while (0)
+
+// ---- deterministic block partial sums ----------------------------------------------
+// Lane l of a launch holds NA accumulators acc[a]; lanes with equal l % L
+// (L divides 64) belong together.  The workgroup's sum of acc[a] over the
+// lanes of group g goes to partial column (a / R) * (L R) + g R + a % R, row
+// blockIdx.x of partials (columns kMaxRedBlocks apart, contiguous for the
+// finish kernel).  L = R = 1: column a holds the sum over all lanes.  The
+// adds run in a fixed order (butterfly within a wavefront, then wavefronts
+// in order), so results do not depend on timing.
+template <int NA, int L, int R>
+__device__ __forceinline__ void store_partials_g(const double (&acc)[NA], int na, double *partials)
+{
+    __shared__ double red[kBlock / 64][NA * L];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+        if (a < na) {
+            double v = acc[a];
+#pragma unroll
+            for (int o = 32; o >= L; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane < L) red[wave][a * L + lane] = v;
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < na * L; t += kBlock) {
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kBlock / 64; ++w) s += red[w][t];
+        const int a = t / L, g = t % L;
+        const int col = (a / R) * (L * R) + g * R + a % R;
+        partials[(i64)col * kMaxRedBlocks + blockIdx.x] = s;
+    }
+}
+
+// ---- several right-hand sides per row ----------------------------------------------
+// A batch of K vectors is stored interleaved: entry j of row p at [p * K + j],
+// so the K values a row needs from one neighbour are one contiguous run.  A
+// lane handles R consecutive right-hand sides of one row (K / R lanes share
+// the row); R is the tile shape the autotuner chooses.
+template <typename T, int R> struct alignas(sizeof(T) * R) Pack {
+    T v[R];
+};
+template <typename T, int R> __device__ __forceinline__ Pack<T, R> ldp(const T *p)
+{
+    return *reinterpret_cast<const Pack<T, R> *>(p);
+}
+template <typename T, int R> __device__ __forceinline__ void stp(T *p, const Pack<T, R> &v)
+{
+    *reinterpret_cast<Pack<T, R> *>(p) = v;
+}
+
+// Gathered neighbour values in flight per lane: about 256 bytes, so that a
+// wide lane (R = 8) stays within the register file.
+template <typename T, int R> constexpr int gather_group()
+{
+    const int g = 256 / (R * (int)sizeof(T));
+    return g >= kSlots ? kSlots : (g < 2 ? 2 : g);
+}
+
+// acc[r] = sum over the slots in MASK of a(p,s) * x[col(p,s) * K + r] (slot
+// order, as ell_row_dot); x points at this lane's first right-hand side.
+// The row's values and columns are loaded first, then the gathers go out in
+// groups of gather_group() slots.
+template <typename T, typename V, int K, int R, unsigned MASK>
+__device__ __forceinline__ void ell_row_dot_b(const V *__restrict__ offv, const int *__restrict__ offc,
+                                              const T *x, const EllRow &er, T (&acc)[R])
+{
+    V a[kSlots];
+    int ci[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) {
+            const i64 e = er.base + (i64)s * er.stride;
+            a[s] = ld_stream(offv + e);
+            ci[s] = ld_stream(offc + e);
+        }
+    }
+    sched_fence();
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = (T)0;
+    constexpr int G = gather_group<T, R>();
+#pragma unroll
+    for (int s0 = 0; s0 < kSlots; s0 += G) {
+        Pack<T, R> xv[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int s = s0 + u;
+            if (s < kSlots && (MASK & (1u << s))) xv[u] = ldp<T, R>(x + (i64)ci[s] * K);
+        }
+        sched_fence();
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int s = s0 + u;
+            if (s < kSlots && (MASK & (1u << s))) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) acc[r] += to_t<T>(a[s]) * xv[u].v[r];
+            }
+        }
+    }
+}
 
 }  // namespace hpgmx

@@ -38,6 +38,7 @@ constexpr int kMaxLevels = 8;
 constexpr int kMaxRestart = 63;   // m; the basis holds m + 1 vectors
 constexpr int kMaxBasis = 64;     // kMaxRestart + 1
 constexpr int kBlock = 256;       // threads per workgroup (4 wavefronts)
+constexpr int kMaxBatch = 8;      // right-hand sides of one batched solve
 constexpr int kMaxRedBlocks = 1024;  // workgroups of the grid-stride reductions
 constexpr int kDefaultEllChunkLog2 = 8;  // ELL chunking default (see ell_row)
 // Extra elements between Krylov basis columns, so that columns do not start
@@ -193,22 +194,65 @@ void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void
                     hipStream_t s);
 
 // Krylov kernels.  Q is column-major with leading dimension ldq >= N.
+//
+// The vector kernels take M elements of K interleaved right-hand sides
+// (M = rows * K; element e is row e / K of right-hand side e % K) and one
+// control block per right-hand side (ctrl[0..K)).  K is 1 for the single
+// solve and 2, 4 or 8 for a batch; a column of a batched basis holds M
+// elements.
 int red_blocks(i64 N);
+// The finish kernel: one workgroup per right-hand side adds partial columns
+// i * K + j (i < kb) over nb workgroups and applies `mode` to ctrl[j].
+void launch_finish(const double *partials, int nb, int kb, int K, int mode, Ctrl *ctrl, int k, int m,
+                   hipStream_t s);
 void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 ldq, int kb,
                      void *w, double *partials, Ctrl *ctrl, hipStream_t s);
-void launch_cgs_dot(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
+                Ctrl *ctrl, hipStream_t s);
+void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                     Ctrl *ctrl, hipStream_t s);
-void launch_cgs_norm(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                      Ctrl *ctrl, int k, int m, hipStream_t s);
-void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s);
+void launch_normalize(i64 M, int K, Prec p, void *w, const Ctrl *ctrl, hipStream_t s);
 void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
                     double *partials, Ctrl *ctrl, int m, hipStream_t s);
-void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStream_t s);
-void launch_cast(i64 N, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s);
-void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s);
-void launch_gemv(i64 N, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u,
+// ||v_j||^2 per right-hand side, then the finish `mode` (kFinishRho0 or
+// kFinishResid with restart length m).
+void launch_norm64(i64 M, int K, const double *v, double *partials, Ctrl *ctrl, int mode, int m,
+                   hipStream_t s);
+void launch_cast(i64 M, int K, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s);
+// Completed Krylov steps per right-hand side (the size of each back-solve).
+struct KCount {
+    int v[kMaxBatch];
+};
+void launch_trsm(Ctrl *ctrl, const KCount &kc, int K, int m, hipStream_t s);
+void launch_gemv(i64 M, int K, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u,
                  hipStream_t s);
-void launch_update(i64 N, Prec p, const void *z, double *x, hipStream_t s);
+void launch_update(i64 M, Prec p, const void *z, double *x, hipStream_t s);
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
+
+// ---- batched stencil kernels (K interleaved right-hand sides, K = 2, 4, 8) ----
+// Vectors hold N * K entries ([p * K + j]); a vector that is gathered from
+// holds (N + 1) * K with row N zero.  R right-hand sides per lane (R divides
+// K): the tile shape chosen per kernel and level by the autotuner.  p is
+// P64 or P32 (batched solves keep FP64 or FP32 matrices).
+bool batch_shape_ok(int K, int R);
+void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s);
+void launch_bgs_colour(const Matrix &A, Prec p, int K, int R, int c, int mode, const void *r,
+                       void *z, hipStream_t s);
+void launch_brestrict(const Matrix &Af, const Geom &gc, Prec p, int K, int R, const void *r,
+                      const void *z, void *rc, hipStream_t s);
+void launch_bprolong(const Geom &gf, const Geom &gc, Prec p, int K, const void *zc, void *z,
+                     hipStream_t s);
+// r = b - A x in FP64 for K right-hand sides, then rho_j = ||r_j|| into
+// ctrl[j] (start of a cycle, as launch_resid64) by the norm kernel.
+void launch_bresid64(const Matrix &A, int K, int R, const double *x, const double *b, double *r,
+                     double *partials, Ctrl *ctrl, int m, hipStream_t s);
+// [nrhs][N] natural order <-> [N][K] colour-blocked interleaved (right-hand
+// sides nrhs..K-1 are zero-filled on the way in and dropped on the way out).
+void launch_bnat2int(const Geom &g, Prec src, Prec dst, int K, int nrhs, const void *nat, void *in,
+                     hipStream_t s);
+void launch_bint2nat(const Geom &g, Prec src, Prec dst, int K, int nrhs, const void *in, void *nat,
+                     hipStream_t s);
 
 }  // namespace hpgmx

@@ -1,0 +1,134 @@
+// Device templates of the Krylov vector passes, shared by the single-solve
+// and the batched translation units: the first GEMVT of a batch, the two
+// fused CGS2 update passes and the reduction helpers they use.
+//
+// The vector kernels serve K right-hand sides stored interleaved (element
+// e = p * K + j is row p of right-hand side j).  They run one lane per
+// element; since K divides the workgroup size, a lane's right-hand side is
+// threadIdx.x % K for the whole grid-stride loop, and each right-hand side
+// has its own control block ctrl[j] (coefficients, Hessenberg matrix,
+// rotations).  K = 1 is the single solve.
+#pragma once
+
+#include "ell_device.hpp"
+
+namespace hpgmx {
+
+// ---- reduction helpers -------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int K> __device__ __forceinline__ int rhs_of_thread() { return (int)(threadIdx.x & (K - 1)); }
+
+// Coefficient arrays of the control block staged by the CGS and GEMV passes.
+enum CoefSel { kCoefH1, kCoefH2, kCoefY };
+
+// c[i * K + j] = coefficient i of right-hand side j (0 for i >= kb).
+template <int KB, int K>
+__device__ __forceinline__ void stage_coefs(double *c, const Ctrl *ctrl, int kb, CoefSel sel)
+{
+    for (int t = threadIdx.x; t < KB * K; t += kBlock) {
+        const int i = t / K, j = t % K;
+        const double *src = sel == kCoefH1 ? ctrl[j].h1 : sel == kCoefH2 ? ctrl[j].h2 : ctrl[j].y;
+        c[t] = i < kb ? src[i] : 0.0;
+    }
+    __syncthreads();
+}
+
+// Column j of the basis for a kernel compiled for KB columns: loads are
+// issued for all KB columns unconditionally (so they can all be in flight at
+// once); columns at or beyond kb re-read column kb-1 from cache and carry a
+// zero coefficient.
+__device__ __forceinline__ i64 col_off(int j, int kb, i64 ldq) { return (i64)(j < kb ? j : kb - 1) * ldq; }
+
+// ---- h1 = Q_{1:kb}^T w per right-hand side (the first GEMVT of a batch, whose
+// SpMV runs in its own kernel) ----
+template <typename T, int KB, int K>
+__global__ __launch_bounds__(kBlock) void k_dot(i64 M, const T *__restrict__ Q, i64 ldq, int kb,
+                                                const T *__restrict__ w, double *partials)
+{
+    double acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
+        T q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + e];
+        const double vd = (double)w[e];
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
+    }
+    store_partials_g<KB, K, 1>(acc, kb, partials);
+}
+
+// ---- w -= Q h1 fused with h2 = Q^T w (the reorthogonalisation GEMV and GEMVT) ----
+template <typename T, int KB, int K>
+__global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 M, const T *__restrict__ Q, i64 ldq, int kb,
+                                                    T *__restrict__ w, double *partials,
+                                                    const Ctrl *ctrl)
+{
+    __shared__ double c[KB * K];
+    stage_coefs<KB, K>(c, ctrl, kb, kCoefH1);
+    const double *cj = c + rhs_of_thread<K>();
+    double acc[KB];
+#pragma unroll
+    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
+        T q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + e];
+        double v = (double)w[e];
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
+        const T vt = (T)v;
+        w[e] = vt;
+        const double vd = (double)vt;
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
+    }
+    store_partials_g<KB, K, 1>(acc, kb, partials);
+}
+
+// ---- w -= Q h2 fused with ||w||^2, then the Givens step -------------------------------------
+template <typename T, int KB, int K>
+__global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict__ Q, i64 ldq, int kb,
+                                                     T *__restrict__ w, double *partials,
+                                                     const Ctrl *ctrl)
+{
+    __shared__ double c[KB * K];
+    stage_coefs<KB, K>(c, ctrl, kb, kCoefH2);
+    const double *cj = c + rhs_of_thread<K>();
+    double acc[1] = {0.0};
+    const i64 stride = (i64)gridDim.x * kBlock;
+    for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
+        T q[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + e];
+        double v = (double)w[e];
+        sched_fence();
+#pragma unroll
+        for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
+        const T vt = (T)v;
+        w[e] = vt;
+        acc[0] += (double)vt * (double)vt;
+    }
+    store_partials_g<1, K, 1>(acc, 1, partials);
+}
+
+// Batched instances (K = 2, 4, 8) of the CGS2 passes, compiled in
+// krylov_batch.hip; each launches its finish kernel as the single-solve
+// launchers do.
+void batch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+                   Ctrl *ctrl, hipStream_t s);
+void batch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+                    Ctrl *ctrl, int k, int m, hipStream_t s);
+
+}  // namespace hpgmx

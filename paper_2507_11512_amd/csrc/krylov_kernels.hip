@@ -4,69 +4,32 @@
 // and the mixed-precision solution update.
 //
 // Reductions (inner products and norms) are deterministic: every workgroup
-// of a fixed-size grid-stride launch writes its partial sums, and a
-// one-workgroup finish kernel adds them in workgroup order.  The kernel
-// boundary makes the partial sums visible, so the streaming kernels need no
-// device-scope fences (on gfx950 a device-scope release writes back the
-// XCD's L2, which costs far more than the extra launch).  The Givens update
-// of the Hessenberg column (Alg. 3, "Update QR with Given's rotations") runs
-// in FP64 in the finish kernel of the norm pass, so the whole inner step
-// needs no host round trip except the small residual-estimate read.
-#include "ell_device.hpp"
+// of a fixed-size grid-stride launch writes its partial sums, and a finish
+// kernel (one workgroup per right-hand side) adds them in workgroup order.
+// The kernel boundary makes the partial sums visible, so the streaming
+// kernels need no device-scope fences (on gfx950 a device-scope release
+// writes back the XCD's L2, which costs far more than the extra launch).
+// The Givens update of the Hessenberg column (Alg. 3, "Update QR with
+// Given's rotations") runs in FP64 in the finish kernel of the norm pass, so
+// the whole inner step needs no host round trip except the small
+// residual-estimate read.
+//
+// The vector passes also serve K interleaved right-hand sides (see
+// krylov_device.hpp); the batched instances of the CGS2 passes are compiled
+// in krylov_batch.hip.
+#include "krylov_device.hpp"
 
 #include <cstdlib>
 #include <stdexcept>
+#include <type_traits>
 
 namespace hpgmx {
-
-#define HPGMX_LAUNCH_CHECK()                                                    \
-    do {                                                                        \
-        hipError_t e_ = hipGetLastError();                                      \
-        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));  \
-    } while (0)
 
 int red_blocks(i64 N)
 {
     const i64 b = (N + kBlock - 1) / kBlock;
     return (int)(b < kMaxRedBlocks ? (b < 1 ? 1 : b) : kMaxRedBlocks);
 }
-
-// ---- reduction helpers -------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// Writes this workgroup's sums of acc[0..kb) to partials[j * kMaxRedBlocks + blockIdx.x]
-// (column j of the partial sums is contiguous for the finish kernel).
-template <int KB>
-__device__ __forceinline__ void store_partials(const double (&acc)[KB], int kb, double *partials)
-{
-    __shared__ double red[kBlock / 64][KB];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int j = 0; j < KB; ++j) {
-        if (j < kb) {
-            const double v = wave_sum(acc[j]);
-            if (lane == 0) red[wave][j] = v;
-        }
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < kb) {
-        double s = 0.0;
-#pragma unroll
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w][threadIdx.x];
-        partials[(i64)threadIdx.x * kMaxRedBlocks + blockIdx.x] = s;
-    }
-}
-
-// Column j of the basis for a kernel compiled for KB columns: loads are
-// issued for all KB columns unconditionally (so they can all be in flight at
-// once); columns at or beyond kb re-read column kb-1 from cache and carry a
-// zero coefficient.
-__device__ __forceinline__ i64 col_off(int j, int kb, i64 ldq) { return (i64)(j < kb ? j : kb - 1) * ldq; }
 
 // ---- w = A z fused with h1 = Q_{1:kb}^T w (Alg. 3: SpMV, then the first GEMVT) ----
 template <typename V, int KB>
@@ -77,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, int remap
                                                      const typename VecT<V>::T *__restrict__ Q,
                                                      i64 ldq, int kb,
                                                      typename VecT<V>::T *__restrict__ w,
-                                                     double *partials, Ctrl *ctrl)
+                                                     double *partials)
 {
     using T = typename VecT<V>::T;
     double acc[KB];
@@ -97,37 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, int remap
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
     }
-    store_partials<KB>(acc, kb, partials);
-}
-
-// ---- w -= Q h1 fused with h2 = Q^T w (the reorthogonalisation GEMV and GEMVT) ----
-template <typename T, int KB>
-__global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 N, const T *__restrict__ Q, i64 ldq, int kb,
-                                                    T *__restrict__ w, double *partials,
-                                                    Ctrl *ctrl)
-{
-    __shared__ double c[KB];
-    if ((int)threadIdx.x < KB) c[threadIdx.x] = (int)threadIdx.x < kb ? ctrl->h1[threadIdx.x] : 0.0;
-    __syncthreads();
-    double acc[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    const i64 stride = (i64)gridDim.x * kBlock;
-    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
-        T q[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
-        double v = (double)w[p];
-        sched_fence();
-#pragma unroll
-        for (int j = 0; j < KB; ++j) v -= c[j] * (double)q[j];
-        const T vt = (T)v;
-        w[p] = vt;
-        const double vd = (double)vt;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
-    }
-    store_partials<KB>(acc, kb, partials);
+    store_partials_g<KB, 1, 1>(acc, kb, partials);
 }
 
 // Givens update of Hessenberg column k (0-based) in FP64, by one workgroup:
@@ -193,39 +126,13 @@ __device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
     }
 }
 
-// ---- w -= Q h2 fused with ||w||^2, then the Givens step -------------------------------------
-template <typename T, int KB>
-__global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 N, const T *__restrict__ Q, i64 ldq, int kb,
-                                                     T *__restrict__ w, double *partials,
-                                                     Ctrl *ctrl, int k, int m)
-{
-    __shared__ double c[KB];
-    if ((int)threadIdx.x < KB) c[threadIdx.x] = (int)threadIdx.x < kb ? ctrl->h2[threadIdx.x] : 0.0;
-    __syncthreads();
-    double acc[1] = {0.0};
-    const i64 stride = (i64)gridDim.x * kBlock;
-    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) {
-        T q[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
-        double v = (double)w[p];
-        sched_fence();
-#pragma unroll
-        for (int j = 0; j < KB; ++j) v -= c[j] * (double)q[j];
-        const T vt = (T)v;
-        w[p] = vt;
-        acc[0] += (double)vt * (double)vt;
-    }
-    store_partials<1>(acc, 1, partials);
-}
-
 // ---- q_{k+1} = w / beta -------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_normalize(i64 N, T *__restrict__ w, const Ctrl *ctrl)
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_normalize(i64 M, T *__restrict__ w, const Ctrl *ctrl)
 {
-    const double s = ctrl->inv_beta;
-    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (p < N) w[p] = (T)((double)w[p] * s);
+    const double s = ctrl[rhs_of_thread<K>()].inv_beta;
+    const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (e < M) w[e] = (T)((double)w[e] * s);
 }
 
 // ---- FP64 outer residual r = b - A x with ||r||^2 (Alg. 3, residual step) ----
@@ -234,8 +141,7 @@ __global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, int remap,
                                                     const double *__restrict__ diag,
                                                     const double *__restrict__ x,
                                                     const double *__restrict__ b,
-                                                    double *__restrict__ r, double *partials,
-                                                    Ctrl *ctrl, int m)
+                                                    double *__restrict__ r, double *partials)
 {
     double acc[1] = {0.0};
     RowLoop rl = row_loop(N, remap);
@@ -248,32 +154,36 @@ __global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, int remap,
         r[p] = rv;
         acc[0] += rv * rv;
     }
-    store_partials<1>(acc, 1, partials);
+    store_partials_g<1, 1, 1>(acc, 1, partials);
 }
 
 // ---- rho0 = ||b|| (Alg. 3, first step) -----------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_norm64(i64 N, const double *__restrict__ v,
-                                                   double *partials, Ctrl *ctrl)
+template <int K>
+__global__ __launch_bounds__(kBlock) void k_norm64(i64 M, const double *__restrict__ v, double *partials)
 {
     double acc[1] = {0.0};
     const i64 stride = (i64)gridDim.x * kBlock;
-    for (i64 p = (i64)blockIdx.x * kBlock + threadIdx.x; p < N; p += stride) acc[0] += v[p] * v[p];
-    store_partials<1>(acc, 1, partials);
+    for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) acc[0] += v[e] * v[e];
+    store_partials_g<1, K, 1>(acc, 1, partials);
 }
 
 // ---- finish kernel: add the partial sums of nb workgroups in order -------------------------
 constexpr int kFinishThreads = 1024;
 
-// Wave w sums columns j = w, w + 16, ...; lane l adds workgroups l, l + 64, ...
-// with four independent accumulators, then the wave adds its lanes.
+// Workgroup j finishes right-hand side j: partial columns i * K + j for
+// i < kb, control block ctrl[j].  Wave w sums columns i = w, w + 16, ...;
+// lane l adds workgroups l, l + 64, ... with four independent accumulators,
+// then the wave adds its lanes.
 __global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restrict__ partials,
-                                                           int nb, int kb, int mode, Ctrl *c,
+                                                           int nb, int kb, int K, int mode, Ctrl *ctrl,
                                                            int k, int m)
 {
     __shared__ double tot[kMaxBasis];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int rhs = blockIdx.x;
+    Ctrl *c = ctrl + rhs;
     for (int j = wave; j < kb; j += kFinishThreads / 64) {
-        const double *col = partials + (i64)j * kMaxRedBlocks;
+        const double *col = partials + (i64)(j * K + rhs) * kMaxRedBlocks;
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int b = lane;
         for (; b + 192 < nb; b += 256) {
@@ -322,11 +232,12 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restr
     }
 }
 
-static void finish(const double *partials, int nb, int kb, int mode, Ctrl *ctrl, int k, int m,
+void launch_finish(const double *partials, int nb, int kb, int K, int mode, Ctrl *ctrl, int k, int m,
                    hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(kFinishThreads), 0, s, partials, nb, kb, mode, ctrl,
+    hipLaunchKernelGGL(k_finish, dim3(K), dim3(kFinishThreads), 0, s, partials, nb, kb, K, mode, ctrl,
                        k, m);
+    HPGMX_LAUNCH_CHECK();
 }
 
 // ---- stencil correlation for the adjoint gradient -------------------------------------------
@@ -357,25 +268,30 @@ __global__ __launch_bounds__(kBlock) void k_stencil_corr(i64 N, int clog2, const
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) acc[s < 13 ? s : s + 1] += l * xv[s];
     }
-    store_partials<27>(acc, 27, partials);
+    store_partials_g<27, 1, 1>(acc, 27, partials);
 }
 
 // ---- q_1 = r / rho in the inner dtype --------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_cast(i64 N, const double *__restrict__ r,
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_cast(i64 M, const double *__restrict__ r,
                                                  const Ctrl *ctrl, T *__restrict__ q)
 {
-    const double s = ctrl->inv_rho;
-    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (p < N) q[p] = (T)(r[p] * s);
+    const double s = ctrl[rhs_of_thread<K>()].inv_rho;
+    const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (e < M) q[e] = (T)(r[e] * s);
 }
 
-// ---- y = H(0:kk,0:kk)^{-1} t(0:kk) by back substitution (FP64, one workgroup) ----
+// ---- y = H(0:kk,0:kk)^{-1} t(0:kk) by back substitution (FP64) ----
+// Workgroup j solves for right-hand side j with kk = kc.v[j] columns.
 // Column-oriented: y_i = t_i / H_ii, then every row above subtracts H_ji y_i
-// in parallel; the triangle and t live in LDS.
-__global__ __launch_bounds__(kMaxBasis) void k_trsm(Ctrl *c, int kk, int m)
+// in parallel; the triangle and t live in LDS.  Entries kk..kMaxBasis-1 of
+// y are set to zero, so a basis combination over more columns than kk adds
+// nothing for them.
+__global__ __launch_bounds__(kMaxBasis) void k_trsm(Ctrl *ctrl, KCount kc, int m)
 {
     __shared__ double Hs[kMaxBasis][kMaxBasis + 1], ts[kMaxBasis], ys[kMaxBasis];
+    Ctrl *c = ctrl + blockIdx.x;
+    const int kk = kc.v[blockIdx.x];
     const int t = threadIdx.x;
     for (int j = 0; j < kk; ++j)
         if (t <= j) Hs[t][j] = c->H[(i64)j * (m + 1) + t];
@@ -387,35 +303,32 @@ __global__ __launch_bounds__(kMaxBasis) void k_trsm(Ctrl *c, int kk, int m)
         if (t == 0) ys[i] = yi;
         __syncthreads();
     }
-    if (t < kk) c->y[t] = ys[t];
+    c->y[t] = t < kk ? ys[t] : 0.0;
 }
 
 // ---- u = Q(:,0:kk) y ------------------------------------------------------------------------------
-template <typename T, int KB>
-__global__ __launch_bounds__(kBlock) void k_gemv(i64 N, const T *__restrict__ Q, i64 ldq, int kk,
+// Runs once per restart cycle, so the column count is a runtime loop.
+template <typename T, int K>
+__global__ __launch_bounds__(kBlock) void k_gemv(i64 M, const T *__restrict__ Q, i64 ldq, int kk,
                                                  const Ctrl *ctrl, T *__restrict__ u)
 {
-    __shared__ double c[KB];
-    if ((int)threadIdx.x < KB) c[threadIdx.x] = (int)threadIdx.x < kk ? ctrl->y[threadIdx.x] : 0.0;
-    __syncthreads();
-    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (p >= N) return;
-    T q[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kk, ldq) + p];
-    sched_fence();
+    __shared__ double c[kMaxBasis * K];
+    stage_coefs<kMaxBasis, K>(c, ctrl, kk, kCoefY);
+    const double *cj = c + rhs_of_thread<K>();
+    const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= M) return;
     double v = 0.0;
-#pragma unroll
-    for (int j = 0; j < KB; ++j) v += c[j] * (double)q[j];
-    u[p] = (T)v;
+#pragma unroll 8
+    for (int j = 0; j < kk; ++j) v += cj[j * K] * (double)Q[(i64)j * ldq + e];
+    u[e] = (T)v;
 }
 
 // ---- x += z with the sum in FP64 (Alg. 3: the update must be double) ----
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(i64 N, const T *__restrict__ z, double *__restrict__ x)
+__global__ __launch_bounds__(kBlock) void k_update(i64 M, const T *__restrict__ z, double *__restrict__ x)
 {
-    const i64 p = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (p < N) x[p] += (double)z[p];
+    const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (e < M) x[e] += (double)z[e];
 }
 
 // ---- streaming copy (bandwidth reference) -------------------------------------------------------------
@@ -447,6 +360,18 @@ static inline unsigned grid_n(i64 n) { return (unsigned)((n + kBlock - 1) / kBlo
     default: throw std::runtime_error("basis size out of range");                            \
     }
 
+// Interleave widths: K = 1 (single solve) and the batch widths 2, 4, 8.
+template <typename F> static void with_k(int K, F &&f)
+{
+    switch (K) {
+    case 1: f(std::integral_constant<int, 1>{}); break;
+    case 2: f(std::integral_constant<int, 2>{}); break;
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    default: throw std::runtime_error("unsupported batch width");
+    }
+}
+
 template <typename V>
 static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, const void *Q,
                        i64 ldq, int kb, void *w, double *partials, Ctrl *ctrl, hipStream_t s)
@@ -455,11 +380,11 @@ static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, c
     const dim3 gr(red_blocks(A.g.N)), bl(kBlock);
 #define HPGMX_KB_BODY                                                                          \
     hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)z, \
-                       (const T *)Q, ldq, kb, (T *)w, partials, ctrl)
+                       (const T *)Q, ldq, kb, (T *)w, partials)
     HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
-    finish(partials, (int)gr.x, kb, kFinishH1, ctrl, 0, 0, s);
     HPGMX_LAUNCH_CHECK();
+    launch_finish(partials, (int)gr.x, kb, 1, kFinishH1, ctrl, 0, 0, s);
 }
 
 void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 ldq, int kb,
@@ -473,48 +398,53 @@ void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 
     }
 }
 
-void launch_cgs_dot(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                     Ctrl *ctrl, hipStream_t s)
 {
-    const dim3 gr(red_blocks(N)), bl(kBlock);
+    if (K > 1) return batch_cgs_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
+    const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_dot<double, KB>), gr, bl, 0, s, N, (const double *)Q, ldq, kb, (double *)w, partials, ctrl)
+    hipLaunchKernelGGL((k_cgs_dot<double, KB, 1>), gr, bl, 0, s, M, (const double *)Q, ldq, kb, (double *)w, partials, ctrl)
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     } else {
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_dot<float, KB>), gr, bl, 0, s, N, (const float *)Q, ldq, kb, (float *)w, partials, ctrl)
+    hipLaunchKernelGGL((k_cgs_dot<float, KB, 1>), gr, bl, 0, s, M, (const float *)Q, ldq, kb, (float *)w, partials, ctrl)
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     }
-    finish(partials, (int)gr.x, kb, kFinishH2, ctrl, 0, 0, s);
     HPGMX_LAUNCH_CHECK();
+    launch_finish(partials, (int)gr.x, kb, 1, kFinishH2, ctrl, 0, 0, s);
 }
 
-void launch_cgs_norm(i64 N, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
+void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                      Ctrl *ctrl, int k, int m, hipStream_t s)
 {
-    const dim3 gr(red_blocks(N)), bl(kBlock);
+    if (K > 1) return batch_cgs_norm(M, K, p, Q, ldq, kb, w, partials, ctrl, k, m, s);
+    const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_norm<double, KB>), gr, bl, 0, s, N, (const double *)Q, ldq, kb, (double *)w, partials, ctrl, k, m)
+    hipLaunchKernelGGL((k_cgs_norm<double, KB, 1>), gr, bl, 0, s, M, (const double *)Q, ldq, kb, (double *)w, partials, ctrl)
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     } else {
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_norm<float, KB>), gr, bl, 0, s, N, (const float *)Q, ldq, kb, (float *)w, partials, ctrl, k, m)
+    hipLaunchKernelGGL((k_cgs_norm<float, KB, 1>), gr, bl, 0, s, M, (const float *)Q, ldq, kb, (float *)w, partials, ctrl)
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     }
-    finish(partials, (int)gr.x, 1, kFinishNormGivens, ctrl, k, m, s);
     HPGMX_LAUNCH_CHECK();
+    launch_finish(partials, (int)gr.x, 1, 1, kFinishNormGivens, ctrl, k, m, s);
 }
 
-void launch_normalize(i64 N, Prec p, void *w, const Ctrl *ctrl, hipStream_t s)
+void launch_normalize(i64 M, int K, Prec p, void *w, const Ctrl *ctrl, hipStream_t s)
 {
-    if (p == P64) hipLaunchKernelGGL(k_normalize<double>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (double *)w, ctrl);
-    else hipLaunchKernelGGL(k_normalize<float>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (float *)w, ctrl);
+    with_k(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        if (p == P64) hipLaunchKernelGGL((k_normalize<double, KK>), dim3(grid_n(M)), dim3(kBlock), 0, s, M, (double *)w, ctrl);
+        else hipLaunchKernelGGL((k_normalize<float, KK>), dim3(grid_n(M)), dim3(kBlock), 0, s, M, (float *)w, ctrl);
+    });
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -523,17 +453,21 @@ void launch_resid64(const Matrix &A, const double *x, const double *b, double *r
 {
     const unsigned nb = (unsigned)red_blocks(A.g.N);
     hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, xcd_remap_enabled(), A.v64, A.col,
-                       A.d64, x, b, r, partials, ctrl, m);
-    finish(partials, (int)nb, 1, kFinishResid, ctrl, 0, m, s);
+                       A.d64, x, b, r, partials);
     HPGMX_LAUNCH_CHECK();
+    launch_finish(partials, (int)nb, 1, 1, kFinishResid, ctrl, 0, m, s);
 }
 
-void launch_norm64(i64 N, const double *v, double *partials, Ctrl *ctrl, hipStream_t s)
+void launch_norm64(i64 M, int K, const double *v, double *partials, Ctrl *ctrl, int mode, int m,
+                   hipStream_t s)
 {
-    const unsigned nb = (unsigned)red_blocks(N);
-    hipLaunchKernelGGL(k_norm64, dim3(nb), dim3(kBlock), 0, s, N, v, partials, ctrl);
-    finish(partials, (int)nb, 1, kFinishRho0, ctrl, 0, 0, s);
+    const unsigned nb = (unsigned)red_blocks(M);
+    with_k(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        hipLaunchKernelGGL((k_norm64<KK>), dim3(nb), dim3(kBlock), 0, s, M, v, partials);
+    });
     HPGMX_LAUNCH_CHECK();
+    launch_finish(partials, (int)nb, 1, K, mode, ctrl, 0, m, s);
 }
 
 void launch_stencil_correlation(const Matrix &A, const double *lam, const double *x,
@@ -542,44 +476,45 @@ void launch_stencil_correlation(const Matrix &A, const double *lam, const double
     const unsigned nb = (unsigned)red_blocks(A.g.N);
     hipLaunchKernelGGL(k_stencil_corr, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, A.col, lam, x,
                        partials);
-    finish(partials, (int)nb, 27, kFinishCorr, ctrl, 0, 0, s);
+    HPGMX_LAUNCH_CHECK();
+    launch_finish(partials, (int)nb, 27, 1, kFinishCorr, ctrl, 0, 0, s);
+}
+
+void launch_cast(i64 M, int K, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s)
+{
+    with_k(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        if (p == P64) hipLaunchKernelGGL((k_cast<double, KK>), dim3(grid_n(M)), dim3(kBlock), 0, s, M, r, ctrl, (double *)q);
+        else hipLaunchKernelGGL((k_cast<float, KK>), dim3(grid_n(M)), dim3(kBlock), 0, s, M, r, ctrl, (float *)q);
+    });
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_cast(i64 N, Prec p, const double *r, const Ctrl *ctrl, void *q, hipStream_t s)
+void launch_trsm(Ctrl *ctrl, const KCount &kc, int K, int m, hipStream_t s)
 {
-    if (p == P64) hipLaunchKernelGGL(k_cast<double>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, r, ctrl, (double *)q);
-    else hipLaunchKernelGGL(k_cast<float>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, r, ctrl, (float *)q);
+    hipLaunchKernelGGL(k_trsm, dim3(K), dim3(kMaxBasis), 0, s, ctrl, kc, m);
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_trsm(Ctrl *ctrl, int kk, int m, hipStream_t s)
+void launch_gemv(i64 M, int K, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u,
+                 hipStream_t s)
 {
-    hipLaunchKernelGGL(k_trsm, dim3(1), dim3(kMaxBasis), 0, s, ctrl, kk, m);
+    if (kk < 0 || kk > kMaxBasis) throw std::runtime_error("basis size out of range");
+    const dim3 gr(grid_n(M)), bl(kBlock);
+    with_k(K, [&](auto kc) {
+        constexpr int KK = decltype(kc)::value;
+        if (p == P64)
+            hipLaunchKernelGGL((k_gemv<double, KK>), gr, bl, 0, s, M, (const double *)Q, ldq, kk, ctrl, (double *)u);
+        else
+            hipLaunchKernelGGL((k_gemv<float, KK>), gr, bl, 0, s, M, (const float *)Q, ldq, kk, ctrl, (float *)u);
+    });
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_gemv(i64 N, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u, hipStream_t s)
+void launch_update(i64 M, Prec p, const void *z, double *x, hipStream_t s)
 {
-    const dim3 gr(grid_n(N)), bl(kBlock);
-    if (p == P64) {
-#define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_gemv<double, KB>), gr, bl, 0, s, N, (const double *)Q, ldq, kk, ctrl, (double *)u)
-        HPGMX_KB_SWITCH(kk)
-#undef HPGMX_KB_BODY
-    } else {
-#define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_gemv<float, KB>), gr, bl, 0, s, N, (const float *)Q, ldq, kk, ctrl, (float *)u)
-        HPGMX_KB_SWITCH(kk)
-#undef HPGMX_KB_BODY
-    }
-    HPGMX_LAUNCH_CHECK();
-}
-
-void launch_update(i64 N, Prec p, const void *z, double *x, hipStream_t s)
-{
-    if (p == P64) hipLaunchKernelGGL(k_update<double>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (const double *)z, x);
-    else hipLaunchKernelGGL(k_update<float>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, (const float *)z, x);
+    if (p == P64) hipLaunchKernelGGL(k_update<double>, dim3(grid_n(M)), dim3(kBlock), 0, s, M, (const double *)z, x);
+    else hipLaunchKernelGGL(k_update<float>, dim3(grid_n(M)), dim3(kBlock), 0, s, M, (const float *)z, x);
     HPGMX_LAUNCH_CHECK();
 }
 

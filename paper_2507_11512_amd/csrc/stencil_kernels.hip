@@ -12,12 +12,6 @@
 
 namespace hpgmx {
 
-__device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
-__device__ __forceinline__ i64 gtid_xcd(int remap)
-{
-    return (i64)xcd_tile(blockIdx.x, gridDim.x, remap) * blockDim.x + threadIdx.x;
-}
-
 int xcd_remap_enabled()
 {
     static const int on = [] {
@@ -26,14 +20,6 @@ int xcd_remap_enabled()
     }();
     return on;
 }
-
-static inline unsigned grid_for(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
-
-#define HPGMX_LAUNCH_CHECK()                                                    \
-    do {                                                                        \
-        hipError_t e_ = hipGetLastError();                                      \
-        if (e_ != hipSuccess) throw std::runtime_error(hipGetErrorString(e_));  \
-    } while (0)
 
 // ---- geometry -----------------------------------------------------------------
 Geom make_geom(int nx, int ny, int nz)

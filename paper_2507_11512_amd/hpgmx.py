@@ -17,12 +17,19 @@ F64, F32, F16, BF16 = 0, 1, 2, 3
 GS_FORWARD, GS_BACKWARD, GS_SYMMETRIC = 0, 1, 2
 SOLVE_PROFILE = 1
 SOLVE_GRAPH = 2
+SOLVE_AUTOTUNE = 4
 
 K_GS, K_GS_ZERO, K_RESTRICT, K_PROLONG, K_SPMV_DOT, K_CGS_DOT, K_CGS_NORM, K_NORMALIZE, \
-    K_RESID64, K_CAST, K_TRSM, K_GEMV, K_UPDATE, K_PERMUTE = range(14)
-K_COUNT = 14
+    K_RESID64, K_CAST, K_TRSM, K_GEMV, K_UPDATE, K_PERMUTE, K_SPMV, K_DOT = range(16)
+K_COUNT = 16
 KERNEL_NAMES = ["gs", "gs_zero", "restrict", "prolong", "spmv_dot", "cgs_dot", "cgs_norm",
-                "normalize", "resid64", "cast", "trsm", "gemv", "update", "permute"]
+                "normalize", "resid64", "cast", "trsm", "gemv", "update", "permute", "spmv", "dot"]
+
+# batched kernel kinds of the tile table
+BK_SPMV, BK_GS, BK_GS_ZERO, BK_RESTRICT, BK_RESID64 = range(5)
+BK_COUNT = 5
+BK_NAMES = ["spmv", "gs", "gs_zero", "restrict", "resid64"]
+MAX_BATCH = 8
 
 STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ESTATE", -5: "ENONFINITE"}
 
@@ -31,7 +38,9 @@ EXPORTS = ["hpgmx_setup_problem", "hpgmx_setup_problem_stencil", "hpgmx_stencil_
            "hpgmx_mg_setup", "hpgmx_gmres_ir_solve", "hpgmx_spmv", "hpgmx_smooth",
            "hpgmx_vcycle", "hpgmx_restrict_residual", "hpgmx_prolong_add",
            "hpgmx_rhs_from_x", "hpgmx_profile_get", "hpgmx_stream_copy", "hpgmx_destroy",
-           "hpgmx_last_error"]
+           "hpgmx_last_error", "hpgmx_batch_autotune", "hpgmx_batch_set_tuning",
+           "hpgmx_batch_get_tuning", "hpgmx_workspace_bytes_batched", "hpgmx_spmv_batched",
+           "hpgmx_smooth_batched", "hpgmx_vcycle_batched", "hpgmx_gmres_ir_solve_batched"]
 
 
 class ProblemDesc(C.Structure):
@@ -59,6 +68,10 @@ class SolveStats(C.Structure):
                 ("est_rel_res", C.c_double), ("solve_ms", C.c_double)]
 
 
+class BatchTuning(C.Structure):
+    _fields_ = [("rhs_per_lane", (C.c_int * 8) * BK_COUNT), ("ms", (C.c_double * 8) * BK_COUNT)]
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
@@ -83,6 +96,14 @@ def _load():
         "hpgmx_profile_get": [H, i, i, C.POINTER(d), C.POINTER(C.c_longlong)],
         "hpgmx_stream_copy": [H, vp, vp, C.c_size_t, i, C.POINTER(d)],
         "hpgmx_destroy": [H],
+        "hpgmx_batch_autotune": [H, i, i, C.POINTER(BatchTuning)],
+        "hpgmx_batch_set_tuning": [H, i, i, C.POINTER(BatchTuning)],
+        "hpgmx_batch_get_tuning": [H, i, i, C.POINTER(BatchTuning)],
+        "hpgmx_workspace_bytes_batched": [H, C.POINTER(MgDesc), i, i, C.c_uint, C.POINTER(C.c_size_t)],
+        "hpgmx_spmv_batched": [H, i, i, i, vp, vp],
+        "hpgmx_smooth_batched": [H, i, i, i, i, vp, vp, i],
+        "hpgmx_vcycle_batched": [H, i, i, vp, vp],
+        "hpgmx_gmres_ir_solve_batched": [H, i, vp, vp, C.POINTER(SolveDesc), C.POINTER(SolveStats)],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -224,6 +245,79 @@ def rhs_from_x(h, x, b):
     _check(h, lib.hpgmx_rhs_from_x(h, _ptr(x), _ptr(b)))
 
 
+def _tuning_dict(t):
+    return {"rhs_per_lane": [[t.rhs_per_lane[k][l] for l in range(8)] for k in range(BK_COUNT)],
+            "ms": [[t.ms[k][l] for l in range(8)] for k in range(BK_COUNT)]}
+
+
+def batch_autotune(h, nrhs, dtype):
+    """Times every tile shape of the batched kernels and adopts the fastest;
+    returns the table ({"rhs_per_lane": [kind][level], "ms": [kind][level]})."""
+    t = BatchTuning()
+    _check(h, lib.hpgmx_batch_autotune(h, int(nrhs), int(dtype), C.byref(t)))
+    return _tuning_dict(t)
+
+
+def batch_set_tuning(h, nrhs, dtype, rhs_per_lane):
+    """rhs_per_lane: [kind][level] (0 = the library's fixed rule), or an int for all."""
+    t = BatchTuning()
+    for k in range(BK_COUNT):
+        for l in range(8):
+            v = rhs_per_lane if isinstance(rhs_per_lane, int) else rhs_per_lane[k][l]
+            t.rhs_per_lane[k][l] = int(v)
+    _check(h, lib.hpgmx_batch_set_tuning(h, int(nrhs), int(dtype), C.byref(t)))
+
+
+def batch_get_tuning(h, nrhs, dtype):
+    t = BatchTuning()
+    _check(h, lib.hpgmx_batch_get_tuning(h, int(nrhs), int(dtype), C.byref(t)))
+    return _tuning_dict(t)
+
+
+def workspace_bytes_batched(h, nrhs, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD, restart=30,
+                            dtype_mask=(1 << F64) | (1 << F32)):
+    mg = MgDesc(levels, pre, post, coarsest, sweep)
+    out = C.c_size_t()
+    _check(h, lib.hpgmx_workspace_bytes_batched(h, C.byref(mg), int(nrhs), int(restart), int(dtype_mask),
+                                                C.byref(out)))
+    return out.value
+
+
+def spmv_batched(h, level, dtype, X, Y):
+    """Y[j] = A X[j]; X, Y: (nrhs, N_level) GPU tensors."""
+    _check(h, lib.hpgmx_spmv_batched(h, int(level), int(dtype), int(X.shape[0]), _ptr(X), _ptr(Y)))
+
+
+def smooth_batched(h, level, dtype, sweep, R, Z, zero_guess=False):
+    _check(h, lib.hpgmx_smooth_batched(h, int(level), int(dtype), int(sweep), int(R.shape[0]), _ptr(R),
+                                       _ptr(Z), int(bool(zero_guess))))
+
+
+def vcycle_batched(h, dtype, R, Z):
+    _check(h, lib.hpgmx_vcycle_batched(h, int(dtype), int(R.shape[0]), _ptr(R), _ptr(Z)))
+
+
+def gmres_ir_solve_batched(h, B, X, restart=30, max_iters=10000, tol=1e-9, inner_dtype=F32,
+                           hist_len=0, profile=False, graph=False, autotune=False):
+    """Solves in place for every row of X (nrhs, N); returns a list of Stats
+    (and the (nrhs, hist_len) residual histories if hist_len > 0)."""
+    import numpy as np
+    nrhs = int(B.shape[0])
+    hist = np.zeros((nrhs, max(hist_len, 1)))
+    flags = (SOLVE_PROFILE if profile else 0) | (SOLVE_GRAPH if graph else 0) | \
+        (SOLVE_AUTOTUNE if autotune else 0)
+    desc = SolveDesc(int(restart), int(max_iters), float(tol), int(inner_dtype),
+                     hist.ctypes.data_as(C.POINTER(C.c_double)) if hist_len > 0 else None,
+                     int(hist_len), flags)
+    st = (SolveStats * nrhs)()
+    _check(h, lib.hpgmx_gmres_ir_solve_batched(h, nrhs, _ptr(B), _ptr(X), C.byref(desc), st))
+    out = [Stats(s.iters, s.restarts, bool(s.converged), bool(s.breakdown), s.rho0, s.final_rel_res,
+                 s.est_rel_res, s.solve_ms) for s in st]
+    if hist_len > 0:
+        return out, [hist[j, :min(out[j].iters, hist_len)].copy() for j in range(nrhs)]
+    return out
+
+
 def profile_get(h, kernel, level=0):
     ms, n = C.c_double(), C.c_longlong()
     _check(h, lib.hpgmx_profile_get(h, int(kernel), int(level), C.byref(ms), C.byref(n)))
@@ -295,6 +389,17 @@ class Problem:
         with torch.cuda.stream(self.stream):
             out = gmres_ir_solve(self.h, b, x, restart, max_iters, tol, prec, hist_len, profile, graph)
         return (x, *out) if isinstance(out, tuple) else (x, out)
+
+    def solve_batched(self, B, X0=None, tol=1e-9, restart=30, max_iters=10000, precision="mxp",
+                      hist_len=0, profile=False, graph=False, autotune=False):
+        """B: (nrhs, N) FP64 GPU tensor, nrhs <= 8.  Returns (X, [Stats per rhs])."""
+        import torch
+        X = torch.zeros_like(B) if X0 is None else X0.clone()
+        prec = self._PREC[precision] if isinstance(precision, str) else int(precision)
+        with torch.cuda.stream(self.stream):
+            out = gmres_ir_solve_batched(self.h, B, X, restart, max_iters, tol, prec, hist_len, profile,
+                                         graph, autotune)
+        return (X, *out) if isinstance(out, tuple) else (X, out)
 
     def stencil_grad(self, lam, x):
         """27 FP64 values sum_i lam_i x_{i + d_t} (see hpgmx_stencil_grad)."""

@@ -161,6 +161,38 @@ def resid64_bytes(rows):
     return rows * (SLOTS * 12 + 8 + 4 * 8)
 
 
+# ---- bytes of the batched kernels (K interleaved right-hand sides) -------------------------------
+# The matrix is read once per launch for all K vectors; vector traffic scales
+# with K.  Per right-hand side and row the matrix share is (26 (v + 4) + v) / K.
+def bgs_colour_bytes(rows, active_slots, dtype, K):
+    v, w = vb(dtype), wb(dtype)
+    return rows * (active_slots * (v + 4) + v + 3 * K * w)
+
+
+def bspmv_bytes(rows, dtype, K):
+    v, w = vb(dtype), wb(dtype)
+    return rows * (SLOTS * (v + 4) + v + 2 * K * w)
+
+
+def brestrict_bytes(coarse_rows, dtype, K):
+    v, w = vb(dtype), wb(dtype)
+    return coarse_rows * (SLOTS * (v + 4) + v + 3 * K * w)
+
+
+def bprolong_bytes(coarse_rows, dtype, K):
+    return coarse_rows * 3 * K * wb(dtype)
+
+
+def bresid64_bytes(rows, K):
+    """b - A x (b, x read, r written) plus the norm pass over r."""
+    return rows * (SLOTS * 12 + 8 + 4 * 8 * K)
+
+
+def bdot_bytes(rows, kb, dtype, K):
+    """h1 = Q^T w: kb basis columns and w, each K entries per row."""
+    return rows * K * (kb + 1) * wb(dtype)
+
+
 def zero_guess_active_slots(colour, forward=True):
     """Slots of a colour-c row that couple to colours relaxed earlier."""
     n = 0

@@ -174,3 +174,48 @@ def test_mid_128_config(hp, x0, precision):
     assert dx <= 1e-8
     if precision == "fp64":
         assert abs(st.iters - ref["iters"]) <= 2
+
+
+# ---- the batched workload: 192^3, k = 8 right-hand sides ------------------------------------
+@pytest.fixture(scope="module")
+def p192(hp):
+    print("[setup] 192^3, 4 levels, forward GS, 8 right-hand sides (the batched configuration)", flush=True)
+    P = hp.Problem(192, beta=0.5, levels=4, sweep="forward")
+    t = hp.batch_autotune(P.h, 8, hp.F32)
+    print(f"[setup] autotuned tiles: {t['rhs_per_lane']}", flush=True)
+    yield P
+    P.close()
+
+
+def test_spmv_batched_192_sampled(hp, p192):
+    d = (192, 192, 192)
+    X = np.stack([inputs.uniform(d, 60 + j).astype(np.float32).astype(np.float64) for j in range(8)])
+    Y = dev(np.zeros(X.shape), 1)
+    hp.spmv_batched(p192.h, 0, hp.F32, dev(X, 1), Y)
+    got = host(Y)
+    rows = sample_rows(d, 8000, 4)
+    for j in range(8):
+        ref = oracle.spmv_rows(d, X[j], rows)
+        scale = 26.0 * np.abs(X[j][rows]) + abs_offdiag_rows(d, X[j], rows)
+        assert np.all(np.abs(got[j][rows] - ref) <= 2 * gamma(28, U32) * scale), j
+
+
+def test_solve_batched_192(hp, p192):
+    """b_j = A u_j: every right-hand side reaches the 1e-9 residual, its
+    solution is u_j up to the residual's amplification, and right-hand side 0
+    takes the iterations of its own single solve."""
+    d = (192, 192, 192)
+    U_ = np.stack([inputs.batch_u(d, j) for j in range(8)])
+    Bh = np.stack([oracle.spmv(d, U_[j]) for j in range(8)])
+    X, stats = p192.solve_batched(dev(Bh, 0), tol=1e-9, restart=30, precision="mxp", graph=True)
+    Xh = host(X)
+    for j in range(8):
+        res = np.linalg.norm(Bh[j] - oracle.spmv(d, Xh[j])) / np.linalg.norm(Bh[j])
+        err = np.linalg.norm(Xh[j] - U_[j]) / np.linalg.norm(U_[j])
+        print(f"[192^3 batch j={j}] iters={stats[j].iters} res={res:.3e} |x-u|/|u|={err:.3e} "
+              f"time={stats[j].solve_ms / 1e3:.2f}s", flush=True)
+        assert stats[j].converged and res <= 1e-9
+        assert err <= 1e-7
+    x0, st0 = p192.solve(dev(Bh[0], 0), tol=1e-9, restart=30, precision="mxp")
+    print(f"[192^3 single j=0] iters={st0.iters} time={st0.solve_ms / 1e3:.2f}s", flush=True)
+    assert abs(stats[0].iters - st0.iters) <= 2

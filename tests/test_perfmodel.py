@@ -43,3 +43,14 @@ def test_fixed_iteration_cycles_and_flops():
     # about 10.5 GFLOP per inner step at 320^3 (SpMV, two GS sweeps per
     # level, CGS2 of 8 k N flops)
     assert 2.9e12 < f < 3.3e12
+
+
+def test_batched_bytes_reduce_to_single_at_k1():
+    for dt in (0, 1):
+        assert pm.bspmv_bytes(1000, dt, 1) == pm.spmv_bytes(1000, dt)
+        assert pm.bgs_colour_bytes(1000, 13, dt, 1) == pm.gs_colour_bytes(1000, 13, dt)
+        assert pm.brestrict_bytes(1000, dt, 1) == pm.restrict_bytes(1000, dt)
+        assert pm.bprolong_bytes(1000, dt, 1) == pm.prolong_bytes(1000, dt)
+    assert pm.bresid64_bytes(1000, 1) == pm.resid64_bytes(1000)
+    # FP32, k = 8: the matrix (216 B/row) is shared, 8 vectors of 4 B in and out
+    assert pm.bspmv_bytes(1, 1, 8) == 26 * 8 + 4 + 2 * 8 * 4
