@@ -158,9 +158,10 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_name, per_launch_bytes):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources."""
+def load_traffic(workload, kernel_name):
+    """HBM bytes per launch from committed rocprofv3 counter runs of this
+    workload ("320^3", "192^3x8"), if they were taken on the current kernel
+    sources."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -170,7 +171,7 @@ def load_traffic(kernel_name, per_launch_bytes):
         return None
     if t.get("source_sha") != source_sha():
         return None
-    k = t.get("kernels", {}).get(kernel_name)
+    k = t.get("workloads", {}).get(workload, {}).get("kernels", {}).get(kernel_name)
     if not k:
         return None
     return k.get("hbm_bytes_per_launch")
@@ -283,7 +284,7 @@ def main():
                          f"V-cycle), {dt:.1f} s wall"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
 
-    traffic = load_traffic(dom_name, dominant["bytes_per_launch"]) if dominant else None
+    traffic = load_traffic(f"{n}^3", dom_name) if dominant else None
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -416,6 +417,14 @@ def run_batched(args, hp, pm, torch, np):
     for name, v in sorted(mxp_k.items(), key=lambda kv: -kv[1]["total_ms"])[:12]:
         log(f"  {name:24s} {v['total_ms']:9.2f} ms  {v['launches']:6d} launches  {v['GBps']:7.1f} GB/s")
 
+    nbytes = 1 << 31
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    cms = hp.stream_copy(P.h, src, dst, nbytes, reps=10)
+    copy_gbps = 2 * nbytes / (cms / 1e3) / 1e9
+    del src, dst
+    log(f"stream copy: {copy_gbps:.1f} GB/s (read+write)")
+
     cpu = None
     if not args.no_cpu:
         import oracle
@@ -430,7 +439,7 @@ def run_batched(args, hp, pm, torch, np):
                          f"one GMRES({m}) cycle cut at {args.cpu_iters} inner steps, {dt:.1f} s wall"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
 
-    traffic = load_traffic(dom_name, dominant["bytes_per_launch"]) if dominant else None
+    traffic = load_traffic(f"{n}^3x{k}", dom_name) if dominant else None
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -464,7 +473,7 @@ def run_batched(args, hp, pm, torch, np):
                      "unit": "GB/s", "frac": dominant["frac_peak"] if dominant else None,
                      "bytes_per_launch": dominant["bytes_per_launch"] if dominant else None,
                      "avg_us": dominant["avg_us"] if dominant else None,
-                     "traffic": traffic},
+                     "traffic": traffic, "copy_GBps": round(copy_gbps, 1)},
         "kernels": kernels,
         "cpu_baseline": cpu,
     }

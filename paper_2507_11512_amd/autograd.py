@@ -8,6 +8,11 @@ theta reversed) and returns
     dL/db     = lam,
     dL/dtheta = -sum_i lam_i x_{i + d_t}   (t = 0..26, in-grid pairs only).
 
+b may also be a batch of k <= 8 right-hand sides, shape (k, N): then both
+solves run through the batched solver (each right-hand side keeps its own
+Krylov process) and dL/dtheta sums the correlations of the k pairs
+(lam_j, x_j).
+
 Both solves and the gradient reduction run in the HIP library; this module
 only wires them into torch.autograd.
 """
@@ -41,11 +46,18 @@ class StencilSolver:
         return self._cache[k]
 
     def solve(self, problem, rhs):
-        x, st = problem.solve(rhs.contiguous(), tol=self.tol, restart=self.restart,
-                              max_iters=self.max_iters, precision=self.precision)
-        self.last_stats = st
-        if not st.converged:
-            raise RuntimeError(f"stencil solve did not converge (rel. residual {st.final_rel_res:.3e})")
+        rhs = rhs.contiguous()
+        if rhs.dim() == 2:
+            x, sts = problem.solve_batched(rhs, tol=self.tol, restart=self.restart,
+                                           max_iters=self.max_iters, precision=self.precision)
+        else:
+            x, st = problem.solve(rhs, tol=self.tol, restart=self.restart,
+                                  max_iters=self.max_iters, precision=self.precision)
+            sts = [st]
+        self.last_stats = sts if rhs.dim() == 2 else sts[0]
+        for st in sts:
+            if not st.converged:
+                raise RuntimeError(f"stencil solve did not converge (rel. residual {st.final_rel_res:.3e})")
         return x
 
     def __call__(self, b, theta):
@@ -73,5 +85,8 @@ class StencilSolve(torch.autograd.Function):
         solver = ctx.solver
         fwd, adj = solver.problems(theta)
         lam = solver.solve(adj, g.to(torch.float64).contiguous())
-        grad_theta = -fwd.stencil_grad(lam, x)
+        if lam.dim() == 2:
+            grad_theta = -sum(fwd.stencil_grad(lam[j], x[j]) for j in range(lam.shape[0]))
+        else:
+            grad_theta = -fwd.stencil_grad(lam, x)
         return lam, grad_theta.to(theta.dtype), None

@@ -129,3 +129,42 @@ def test_adjoint_of_beta_family_is_negated_beta(hp, torch):
     lo, _ = oracle.gmres_ir(D, g, levels=3, beta=-0.5, tol=1e-11)
     assert np.linalg.norm(lam.cpu().numpy() - lo) <= 1e-8 * np.linalg.norm(lo)
     P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mxp"])
+def test_autograd_batched_gradients(hp, torch, precision):
+    """k = 3 right-hand sides through the batched solver: the gradients equal
+    the sums of the per-right-hand-side dense FP64 gradients and the central
+    differences of L = sum_j g_j . x_j."""
+    from paper_2507_11512_amd.autograd import StencilSolver
+    k = 3
+    th = perturbed_theta(21)
+    A = refimpl.stencil_matrix(D, th).toarray()
+    Ub = np.stack([inputs.batch_u(D, j) for j in range(k)])
+    Bh = Ub @ A.T                        # rows b_j = A u_j
+    G = np.stack([inputs.normal(D, 11612 + j) for j in range(k)])
+    solver = StencilSolver(D, levels=3, tol=1e-12, precision=precision)
+    bt = dev(Bh, torch).requires_grad_(True)
+    tt = dev(th, torch).requires_grad_(True)
+    X = solver(bt, tt)
+    assert X.shape == (k, D[0] ** 3)
+    L = (dev(G, torch) * X).sum()
+    L.backward()
+    Xs = np.linalg.solve(A, Bh.T).T
+    Ls = np.linalg.solve(A.T, G.T).T
+    shifts = [refimpl.shift_matrix(D, s % 3 - 1, (s // 3) % 3 - 1, s // 9 - 1) for s in range(27)]
+    grad_theta_ref = np.array([-sum(Ls[j] @ (shifts[s] @ Xs[j]) for j in range(k)) for s in range(27)])
+    assert np.linalg.norm(X.detach().cpu().numpy() - Xs) <= 1e-9 * np.linalg.norm(Xs)
+    assert np.linalg.norm(bt.grad.cpu().numpy() - Ls) <= 1e-9 * np.linalg.norm(Ls)
+    gt = tt.grad.cpu().numpy()
+    assert np.allclose(gt, grad_theta_ref, rtol=1e-7, atol=1e-9 * np.abs(grad_theta_ref).max())
+    eps = 1e-4
+    for s in (1, 13, 22):
+        tp, tm = th.copy(), th.copy()
+        tp[s] += eps
+        tm[s] -= eps
+        Lp = float((dev(G, torch) * solver(dev(Bh, torch), dev(tp, torch))).sum())
+        Lm = float((dev(G, torch) * solver(dev(Bh, torch), dev(tm, torch))).sum())
+        fd = (Lp - Lm) / (2 * eps)
+        assert np.isclose(gt[s], fd, rtol=1e-5, atol=1e-7 * np.abs(gt).max()), (s, gt[s], fd)
+    solver.close()
