@@ -64,6 +64,14 @@ def parse():
                     help="right-hand sides solved at once (>1: the batched solver)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched runs: keep the library's fixed tile rule")
+    ap.add_argument("--validation", choices=["standard", "fullscale"], default="standard",
+                    help="validation mode (Sec. 3.3); fullscale: MxP must reach the residual the FP64 "
+                         "solver reached within --val-max-iters")
+    ap.add_argument("--val-max-iters", type=int, default=10000, help="FP64 iteration limit of the validation")
+    ap.add_argument("--duration", type=float, default=None,
+                    help="fill this many seconds per timed phase with solves instead of running --steps "
+                         "(the benchmark's official running time is 1800 s)")
+    ap.add_argument("--report", default=None, help="write the benchmark report (text) to this path")
     return ap.parse_args()
 
 
@@ -96,8 +104,9 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
         B[(hp.K_CAST, 0)] += N * (8 + w)
         for k in range(kk):
             vcyc()
-            B[(hp.K_SPMV_DOT, 0)] += pm.spmv_dot_bytes(N, k + 1, dtype)
-            B[(hp.K_CGS_DOT, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_SPMV, 0)] += pm.spmv_bytes(N, dtype)
+            B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, 1)
+            B[(hp.K_CGS_DOT, 0)] += pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
             B[(hp.K_NORMALIZE, 0)] += 2 * N * w
         B[(hp.K_GEMV, 0)] += N * (kk + 1) * w
@@ -138,7 +147,7 @@ def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
             vcyc()
             B[(hp.K_SPMV, 0)] += pm.bspmv_bytes(N, dtype, K)
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, K)
-            B[(hp.K_CGS_DOT, 0)] += K * pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_CGS_DOT, 0)] += K * pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += K * pm.cgs_pass_bytes(N, k + 1, dtype)
             B[(hp.K_NORMALIZE, 0)] += 2 * N * K * w
         B[(hp.K_GEMV, 0)] += N * K * (kk + 1) * w
@@ -206,40 +215,49 @@ def main():
     log(f"setup done in {time.time() - t:.2f}s")
 
     # ---- 1. validation ---------------------------------------------------------------
+    from paper_2507_11512_amd import driver
     n_d = n_ir = None
     val = {}
+    validation = None
     if not args.no_validation:
         xs = {}
-        for prec in ("fp64", "mxp"):
-            x, st = P.solve(b, tol=1e-9, restart=m, max_iters=10000, precision=PREC[prec], graph=graph)
+
+        def solve(prec, tol, max_iters):
+            x, st = P.solve(b, tol=tol, restart=m, max_iters=max_iters, precision=PREC[prec], graph=graph)
             err = (x - 1.0).norm().item() / (N ** 0.5)
             xs[prec] = x
             val[prec] = {"iters": st.iters, "restarts": st.restarts, "converged": st.converged,
-                         "final_rel_res": st.final_rel_res, "time_to_1e-9_s": st.solve_ms / 1e3,
+                         "final_rel_res": st.final_rel_res, "time_to_tol_s": st.solve_ms / 1e3, "tol": tol,
                          "x_err_vs_ones": err}
-            log(f"validation {prec}: iters={st.iters} res={st.final_rel_res:.3e} "
+            log(f"validation {prec}: tol={tol:.3e} iters={st.iters} res={st.final_rel_res:.3e} "
                 f"|x-1|/|1|={err:.3e} time={st.solve_ms / 1e3:.3f}s")
+            return driver.SolveOutcome(st.iters, st.converged, st.final_rel_res, st.solve_ms / 1e3)
+        validation = driver.validate(solve, args.validation, tol=1e-9, max_iters=args.val_max_iters)
+        val["mode"] = args.validation
+        val["tau"] = validation.tau
         val["mxp"]["x_err_vs_fp64"] = ((xs["mxp"] - xs["fp64"]).norm() / xs["fp64"].norm()).item()
         del xs
-        n_d, n_ir = val["fp64"]["iters"], val["mxp"]["iters"]
+        n_d, n_ir = validation.n_d, validation.n_ir
     penalty = pm.penalty(n_d, n_ir)
 
     # ---- 2./3. timed phases ------------------------------------------------------------------
     cycles = pm.fixed_iteration_cycles(args.iters, m)
     flops = pm.solve_flops(cfg, cycles)
     res = {}
+    phases = {}
     for prec in (("mxp",) if args.no_fp64 else ("mxp", "fp64")):
         for _ in range(args.warmup):
             P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], graph=graph)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(args.steps):
+
+        def once():
             _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], graph=graph)
             assert st.iters == args.iters
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        res[prec] = {"s_per_solve": dt, "gflops_raw": flops / dt / 1e9, "rel_res_after": st.final_rel_res}
-        log(f"timed {prec}: {dt * 1e3:.1f} ms/solve ({args.iters} iters) -> "
+        ph = timed(driver, once, args, torch)
+        phases["mxp" if prec == "mxp" else "double"] = ph
+        dt = ph.seconds_per_solve
+        res[prec] = {"s_per_solve": dt, "gflops_raw": flops / dt / 1e9, "solves": ph.solves}
+        log(f"timed {prec}: {ph.solves} solves, {dt * 1e3:.1f} ms/solve ({args.iters} iters) -> "
             f"{flops / dt / 1e9:.1f} GFLOP/s raw")
     value = res["mxp"]["gflops_raw"] * penalty
     fp64_gflops = res["fp64"]["gflops_raw"] if "fp64" in res else None
@@ -285,12 +303,22 @@ def main():
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
 
     traffic = load_traffic(f"{n}^3", dom_name) if dominant else None
+    if args.report:
+        write_report(args.report, driver,
+                     {"grid": f"{n} x {n} x {n} ({N} unknowns)",
+                      "operator": "27-point nonsymmetric stencil, beta = 0.5, Dirichlet-truncated",
+                      "solver": f"GMRES({m})-IR, {args.inner} inner / fp64 outer; {L}-level V-cycle, "
+                                "forward multicolour Gauss-Seidel 1/1/1",
+                      "inner steps per timed solve": args.iters,
+                      "launch": "eager" if args.eager else "hipGraph per inner step",
+                      "device": torch.cuda.get_device_name(0)},
+                     validation, phases, flops, kernels, L)
     out = {
         "metric": METRIC,
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": res["mxp"]["solves"],
         "warmup": args.warmup,
         "ms_per_step": round(res["mxp"]["s_per_solve"] * 1e3, 3),
         "higher_is_better": True,
@@ -325,6 +353,34 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def timed(driver, once, args, torch):
+    """One timed phase: --steps solves, or --duration seconds of them."""
+    def run():
+        once()
+        torch.cuda.synchronize()
+    torch.cuda.synchronize()
+    if args.duration is not None:
+        return driver.timed_phase(run, duration=args.duration)
+    return driver.timed_phase(run, steps=args.steps)
+
+
+def write_report(path, driver, problem, validation, phases, flops, kernels, levels):
+    """The benchmark report; motif times per solve from the profiled solves."""
+    motifs = {}
+    for tag, name in (("mxp", "mxp"), ("fp64", "double")):
+        per = {}
+        for kname, v in kernels.items():
+            if not kname.endswith("_" + tag):
+                continue
+            base = kname.rsplit("_", 2)[0]
+            per[base] = per.get(base, 0.0) + v["total_ms"]
+        if per:
+            motifs[name] = driver.motif_times(per)
+    with open(path, "w") as f:
+        f.write(driver.report(problem, validation, phases, flops, motifs))
+    log(f"report written to {path}")
+
+
 def profile_kernels(hp, handle, table, prec_tag, kernels):
     for (kid, lvl), nbytes in sorted(table.items()):
         ms, cnt = hp.profile_get(handle, kid, lvl)
@@ -342,6 +398,9 @@ def run_batched(args, hp, pm, torch, np):
     k = args.nrhs
     if k > hp.MAX_BATCH:
         raise SystemExit(f"--nrhs must be at most {hp.MAX_BATCH}")
+    if args.validation != "standard":
+        raise SystemExit("batched runs validate in the standard mode only")
+    from paper_2507_11512_amd import driver
     graph = not args.eager
     n, L, m = args.n, args.levels, args.restart
     cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=0, restart=m)
@@ -390,14 +449,14 @@ def run_batched(args, hp, pm, torch, np):
         for _ in range(args.warmup):
             P.solve_batched(B, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], graph=graph)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
+
+        def once():
             _, sts = P.solve_batched(B, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec],
                                      graph=graph)
             assert all(s.iters == args.iters for s in sts)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / args.steps
-        res[prec] = {"s_per_solve": dt, "gflops_raw": flops / dt / 1e9}
+        ph = timed(driver, once, args, torch)
+        dt = ph.seconds_per_solve
+        res[prec] = {"s_per_solve": dt, "gflops_raw": flops / dt / 1e9, "solves": ph.solves}
         log(f"timed batched {prec}: {dt * 1e3:.1f} ms per {k}-rhs solve ({args.iters} iters) -> "
             f"{flops / dt / 1e9:.1f} GFLOP/s raw")
     value = res["mxp"]["gflops_raw"] * penalty
@@ -445,7 +504,7 @@ def run_batched(args, hp, pm, torch, np):
         "value": round(value, 2),
         "unit": "GFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": res["mxp"]["solves"],
         "warmup": args.warmup,
         "ms_per_step": round(res["mxp"]["s_per_solve"] * 1e3, 3),
         "higher_is_better": True,

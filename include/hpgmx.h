@@ -208,9 +208,9 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
 #define HPGMX_K_GS_ZERO 1      /* one colour of a sweep from a zero guess     */
 #define HPGMX_K_RESTRICT 2     /* fused residual-restriction                  */
 #define HPGMX_K_PROLONG 3      /* prolongation-correction                    */
-#define HPGMX_K_SPMV_DOT 4     /* w = A z fused with h1 = Q^T w               */
-#define HPGMX_K_CGS_DOT 5      /* w -= Q h1 fused with h2 = Q^T w             */
-#define HPGMX_K_CGS_NORM 6     /* w -= Q h2 fused with ||w||^2 and Givens     */
+#define HPGMX_K_SPMV_DOT 4     /* reserved (a fused SpMV + GEMVT; not launched) */
+#define HPGMX_K_CGS_DOT 5      /* h2 = Q^T (w - Q h1)                         */
+#define HPGMX_K_CGS_NORM 6     /* w -= Q (h1 + h2), ||w||^2 and Givens        */
 #define HPGMX_K_NORMALIZE 7    /* q_{k+1} = w / ||w||                         */
 #define HPGMX_K_RESID64 8      /* r = b - A x in FP64 with ||r||^2            */
 #define HPGMX_K_CAST 9         /* q_1 = r / rho (cast to the inner dtype)      */
@@ -218,8 +218,8 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
 #define HPGMX_K_GEMV 11        /* u = Q y                                      */
 #define HPGMX_K_UPDATE 12      /* x += z in FP64                              */
 #define HPGMX_K_PERMUTE 13     /* natural <-> colour-blocked order            */
-#define HPGMX_K_SPMV 14        /* w = A z alone (batched solves)              */
-#define HPGMX_K_DOT 15         /* h1 = Q^T w alone (batched solves)           */
+#define HPGMX_K_SPMV 14        /* w = A z                                     */
+#define HPGMX_K_DOT 15         /* h1 = Q^T w                                  */
 #define HPGMX_K_COUNT 16
 hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *total_ms,
                                long long *launches);

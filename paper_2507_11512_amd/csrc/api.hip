@@ -589,8 +589,12 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                 auto step = [&]() {
                     vcycle(c, 0, p, col(k), K.z);
                     {
-                        ProfScope ps(c, HPGMX_K_SPMV_DOT, 0);
-                        launch_spmv_dot(A0, p, K.z, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                        ProfScope ps(c, HPGMX_K_SPMV, 0);
+                        launch_spmv(A0, p, K.z, col(k + 1), c->stream);
+                    }
+                    {
+                        ProfScope ps(c, HPGMX_K_DOT, 0);
+                        launch_dot(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_CGS_DOT, 0);

@@ -205,12 +205,13 @@ int red_blocks(i64 N);
 // i * K + j (i < kb) over nb workgroups and applies `mode` to ctrl[j].
 void launch_finish(const double *partials, int nb, int kb, int K, int mode, Ctrl *ctrl, int k, int m,
                    hipStream_t s);
-void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 ldq, int kb,
-                     void *w, double *partials, Ctrl *ctrl, hipStream_t s);
+// h1 = Q^T w alone (the first GEMVT when the SpMV runs as its own kernel).
 void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
                 Ctrl *ctrl, hipStream_t s);
+// h2 = Q^T (w - Q h1); w is not written.
 void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                     Ctrl *ctrl, hipStream_t s);
+// w <- w - Q (h1 + h2), ||w||^2 and the Givens step of column k.
 void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                      Ctrl *ctrl, int k, int m, hipStream_t s);
 void launch_normalize(i64 M, int K, Prec p, void *w, const Ctrl *ctrl, hipStream_t s);

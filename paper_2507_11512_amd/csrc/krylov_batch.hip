@@ -35,8 +35,8 @@ template <typename F> static void with_bk(int K, Prec p, F &&f)
     throw std::runtime_error("unsupported batch width");
 }
 
-void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
-                Ctrl *ctrl, hipStream_t s)
+void batch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
+               Ctrl *ctrl, hipStream_t s)
 {
     const dim3 gr(red_blocks(M)), bl(kBlock);
     with_bk(K, p, [&](auto kc, auto *tag) {
@@ -59,7 +59,7 @@ void batch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w
         constexpr int KK = decltype(kc)::value;
         using T = std::remove_pointer_t<decltype(tag)>;
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_dot<T, KB, KK>), gr, bl, 0, s, M, (const T *)Q, ldq, kb, (T *)w, partials, ctrl)
+    hipLaunchKernelGGL((k_cgs_dot<T, KB, KK>), gr, bl, 0, s, M, (const T *)Q, ldq, kb, (const T *)w, partials, ctrl)
         HPGMX_KB8_SWITCH(kb)
 #undef HPGMX_KB_BODY
     });

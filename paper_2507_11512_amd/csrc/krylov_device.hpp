@@ -25,7 +25,7 @@ __device__ __forceinline__ double wave_sum(double v)
 template <int K> __device__ __forceinline__ int rhs_of_thread() { return (int)(threadIdx.x & (K - 1)); }
 
 // Coefficient arrays of the control block staged by the CGS and GEMV passes.
-enum CoefSel { kCoefH1, kCoefH2, kCoefY };
+enum CoefSel { kCoefH1, kCoefH12, kCoefY };
 
 // c[i * K + j] = coefficient i of right-hand side j (0 for i >= kb).
 template <int KB, int K>
@@ -33,8 +33,12 @@ __device__ __forceinline__ void stage_coefs(double *c, const Ctrl *ctrl, int kb,
 {
     for (int t = threadIdx.x; t < KB * K; t += kBlock) {
         const int i = t / K, j = t % K;
-        const double *src = sel == kCoefH1 ? ctrl[j].h1 : sel == kCoefH2 ? ctrl[j].h2 : ctrl[j].y;
-        c[t] = i < kb ? src[i] : 0.0;
+        double v = 0.0;
+        if (i < kb) {
+            const Ctrl &cj = ctrl[j];
+            v = sel == kCoefH1 ? cj.h1[i] : sel == kCoefH12 ? cj.h1[i] + cj.h2[i] : cj.y[i];
+        }
+        c[t] = v;
     }
     __syncthreads();
 }
@@ -67,10 +71,14 @@ __global__ __launch_bounds__(kBlock) void k_dot(i64 M, const T *__restrict__ Q, 
     store_partials_g<KB, K, 1>(acc, kb, partials);
 }
 
-// ---- w -= Q h1 fused with h2 = Q^T w (the reorthogonalisation GEMV and GEMVT) ----
+// ---- h2 = Q^T (w - Q h1) (the reorthogonalisation GEMV and GEMVT) ----
+// w - Q h1 is kept in FP64 in registers and not stored: the norm pass forms
+// w - Q (h1 + h2) from the original w, which is the same vector in exact
+// arithmetic, rounds to the storage type once instead of twice, and saves
+// one write of w per step.
 template <typename T, int KB, int K>
 __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 M, const T *__restrict__ Q, i64 ldq, int kb,
-                                                    T *__restrict__ w, double *partials,
+                                                    const T *__restrict__ w, double *partials,
                                                     const Ctrl *ctrl)
 {
     __shared__ double c[KB * K];
@@ -88,23 +96,20 @@ __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 M, const T *__restrict__
         sched_fence();
 #pragma unroll
         for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
-        const T vt = (T)v;
-        w[e] = vt;
-        const double vd = (double)vt;
 #pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
+        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * v;
     }
     store_partials_g<KB, K, 1>(acc, kb, partials);
 }
 
-// ---- w -= Q h2 fused with ||w||^2, then the Givens step -------------------------------------
+// ---- w -= Q (h1 + h2) fused with ||w||^2, then the Givens step ----------------------------
 template <typename T, int KB, int K>
 __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict__ Q, i64 ldq, int kb,
                                                      T *__restrict__ w, double *partials,
                                                      const Ctrl *ctrl)
 {
     __shared__ double c[KB * K];
-    stage_coefs<KB, K>(c, ctrl, kb, kCoefH2);
+    stage_coefs<KB, K>(c, ctrl, kb, kCoefH12);
     const double *cj = c + rhs_of_thread<K>();
     double acc[1] = {0.0};
     const i64 stride = (i64)gridDim.x * kBlock;
@@ -123,9 +128,11 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict_
     store_partials_g<1, K, 1>(acc, 1, partials);
 }
 
-// Batched instances (K = 2, 4, 8) of the CGS2 passes, compiled in
+// Batched instances (K = 2, 4, 8) of the Krylov passes, compiled in
 // krylov_batch.hip; each launches its finish kernel as the single-solve
 // launchers do.
+void batch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
+               Ctrl *ctrl, hipStream_t s);
 void batch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                    Ctrl *ctrl, hipStream_t s);
 void batch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,

@@ -1,7 +1,7 @@
-// Krylov-side kernels of Alg. 3: the SpMV fused with the first CGS2 inner
-// products, the two fused CGS2 update passes, the normalisation, the FP64
-// outer residual, the projected least-squares solve, the basis combination
-// and the mixed-precision solution update.
+// Krylov-side kernels of Alg. 3: the first CGS2 inner products, the two
+// fused CGS2 update passes, the normalisation, the FP64 outer residual, the
+// projected least-squares solve, the basis combination and the
+// mixed-precision solution update.
 //
 // Reductions (inner products and norms) are deterministic: every workgroup
 // of a fixed-size grid-stride launch writes its partial sums, and a finish
@@ -29,38 +29,6 @@ int red_blocks(i64 N)
 {
     const i64 b = (N + kBlock - 1) / kBlock;
     return (int)(b < kMaxRedBlocks ? (b < 1 ? 1 : b) : kMaxRedBlocks);
-}
-
-// ---- w = A z fused with h1 = Q_{1:kb}^T w (Alg. 3: SpMV, then the first GEMVT) ----
-template <typename V, int KB>
-__global__ __launch_bounds__(kBlock) void k_spmv_dot(i64 N, int clog2, int remap, const V *__restrict__ offv,
-                                                     const int *__restrict__ offc,
-                                                     const V *__restrict__ diag,
-                                                     const typename VecT<V>::T *__restrict__ z,
-                                                     const typename VecT<V>::T *__restrict__ Q,
-                                                     i64 ldq, int kb,
-                                                     typename VecT<V>::T *__restrict__ w,
-                                                     double *partials)
-{
-    using T = typename VecT<V>::T;
-    double acc[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
-    RowLoop rl = row_loop(N, remap);
-    i64 p;
-    while (rl.next(p)) {
-        T q[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + p];
-        const EllRow er = ell_row(p, N, clog2);
-        const T dz = to_t<T>(ld_stream(diag + p)) * z[p];
-        const T v = dz + ell_row_dot<T, V, kAllSlots>(offv, offc, z, er);
-        w[p] = v;
-        const double vd = (double)v;
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
-    }
-    store_partials_g<KB, 1, 1>(acc, kb, partials);
 }
 
 // Givens update of Hessenberg column k (0-based) in FP64, by one workgroup:
@@ -372,30 +340,24 @@ template <typename F> static void with_k(int K, F &&f)
     }
 }
 
-template <typename V>
-static void spmv_dot_t(const Matrix &A, const V *v, const V *d, const void *z, const void *Q,
-                       i64 ldq, int kb, void *w, double *partials, Ctrl *ctrl, hipStream_t s)
+void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
+                Ctrl *ctrl, hipStream_t s)
 {
-    using T = typename VecT<V>::T;
-    const dim3 gr(red_blocks(A.g.N)), bl(kBlock);
-#define HPGMX_KB_BODY                                                                          \
-    hipLaunchKernelGGL((k_spmv_dot<V, KB>), gr, bl, 0, s, A.g.N, A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)z, \
-                       (const T *)Q, ldq, kb, (T *)w, partials)
-    HPGMX_KB_SWITCH(kb)
+    if (K > 1) return batch_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
+    const dim3 gr(red_blocks(M)), bl(kBlock);
+    if (p == P64) {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_dot<double, KB, 1>), gr, bl, 0, s, M, (const double *)Q, ldq, kb, (const double *)w, partials)
+        HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
+    } else {
+#define HPGMX_KB_BODY \
+    hipLaunchKernelGGL((k_dot<float, KB, 1>), gr, bl, 0, s, M, (const float *)Q, ldq, kb, (const float *)w, partials)
+        HPGMX_KB_SWITCH(kb)
+#undef HPGMX_KB_BODY
+    }
     HPGMX_LAUNCH_CHECK();
     launch_finish(partials, (int)gr.x, kb, 1, kFinishH1, ctrl, 0, 0, s);
-}
-
-void launch_spmv_dot(const Matrix &A, Prec p, const void *z, const void *Q, i64 ldq, int kb,
-                     void *w, double *partials, Ctrl *ctrl, hipStream_t s)
-{
-    switch (p) {
-    case P64: spmv_dot_t(A, A.v64, A.d64, z, Q, ldq, kb, w, partials, ctrl, s); break;
-    case P32: spmv_dot_t(A, A.v32, A.d32, z, Q, ldq, kb, w, partials, ctrl, s); break;
-    case P16: spmv_dot_t(A, A.v16, A.d16, z, Q, ldq, kb, w, partials, ctrl, s); break;
-    case PB16: spmv_dot_t(A, A.vb16, A.db16, z, Q, ldq, kb, w, partials, ctrl, s); break;
-    }
 }
 
 void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
@@ -405,12 +367,12 @@ void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_dot<double, KB, 1>), gr, bl, 0, s, M, (const double *)Q, ldq, kb, (double *)w, partials, ctrl)
+    hipLaunchKernelGGL((k_cgs_dot<double, KB, 1>), gr, bl, 0, s, M, (const double *)Q, ldq, kb, (const double *)w, partials, ctrl)
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     } else {
 #define HPGMX_KB_BODY \
-    hipLaunchKernelGGL((k_cgs_dot<float, KB, 1>), gr, bl, 0, s, M, (const float *)Q, ldq, kb, (float *)w, partials, ctrl)
+    hipLaunchKernelGGL((k_cgs_dot<float, KB, 1>), gr, bl, 0, s, M, (const float *)Q, ldq, kb, (const float *)w, partials, ctrl)
         HPGMX_KB_SWITCH(kb)
 #undef HPGMX_KB_BODY
     }

@@ -140,12 +140,14 @@ def spmv_bytes(rows, dtype):
     return rows * (SLOTS * (v + 4) + v + 2 * w)
 
 
-def spmv_dot_bytes(rows, kb, dtype):
-    return spmv_bytes(rows, dtype) + rows * kb * wb(dtype)
-
-
 def cgs_pass_bytes(rows, kb, dtype):
+    """w <- w - Q c fused with a reduction: kb columns and w read, w written."""
     return rows * (kb + 2) * wb(dtype)
+
+
+def cgs_dot_bytes(rows, kb, dtype):
+    """h2 = Q^T (w - Q h1) with w not written: kb columns and w read."""
+    return rows * (kb + 1) * wb(dtype)
 
 
 def restrict_bytes(coarse_rows, dtype):
