@@ -108,7 +108,6 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, 1)
             B[(hp.K_CGS_DOT, 0)] += pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
-            B[(hp.K_NORMALIZE, 0)] += 2 * N * w
         B[(hp.K_GEMV, 0)] += N * (kk + 1) * w
         vcyc()
         B[(hp.K_UPDATE, 0)] += N * (16 + w)
@@ -149,7 +148,6 @@ def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, K)
             B[(hp.K_CGS_DOT, 0)] += K * pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += K * pm.cgs_pass_bytes(N, k + 1, dtype)
-            B[(hp.K_NORMALIZE, 0)] += 2 * N * K * w
         B[(hp.K_GEMV, 0)] += N * K * (kk + 1) * w
         vcyc()
         B[(hp.K_UPDATE, 0)] += N * K * (16 + w)

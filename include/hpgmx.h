@@ -211,7 +211,7 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
 #define HPGMX_K_SPMV_DOT 4     /* reserved (a fused SpMV + GEMVT; not launched) */
 #define HPGMX_K_CGS_DOT 5      /* h2 = Q^T (w - Q h1)                         */
 #define HPGMX_K_CGS_NORM 6     /* w -= Q (h1 + h2), ||w||^2 and Givens        */
-#define HPGMX_K_NORMALIZE 7    /* q_{k+1} = w / ||w||                         */
+#define HPGMX_K_NORMALIZE 7    /* reserved (the basis is stored unnormalised)  */
 #define HPGMX_K_RESID64 8      /* r = b - A x in FP64 with ||r||^2            */
 #define HPGMX_K_CAST 9         /* q_1 = r / rho (cast to the inner dtype)      */
 #define HPGMX_K_TRSM 10        /* y = H^{-1} t                                */

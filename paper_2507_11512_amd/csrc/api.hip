@@ -590,7 +590,7 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                     vcycle(c, 0, p, col(k), K.z);
                     {
                         ProfScope ps(c, HPGMX_K_SPMV, 0);
-                        launch_spmv(A0, p, K.z, col(k + 1), c->stream);
+                        launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_DOT, 0);
@@ -603,10 +603,6 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                     {
                         ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
                         launch_cgs_norm(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
-                    }
-                    {
-                        ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
-                        launch_normalize(N, 1, p, col(k + 1), c->ctrl, c->stream);
                     }
                 };
                 if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, 1), step);
@@ -979,7 +975,8 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
                     bvcycle(c, B, 0, p, col(k), Kr.z);
                     {
                         ProfScope ps(c, HPGMX_K_SPMV, 0);
-                        launch_bspmv(A0, p, K, tile_r(c, B, p, HPGMX_BK_SPMV, 0), Kr.z, col(k + 1), c->stream);
+                        launch_bspmv(A0, p, K, tile_r(c, B, p, HPGMX_BK_SPMV, 0), Kr.z, col(k + 1), c->stream,
+                                     B.ctrl, k);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_DOT, 0);
@@ -992,10 +989,6 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
                     {
                         ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
                         launch_cgs_norm(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, k, m, c->stream);
-                    }
-                    {
-                        ProfScope ps(c, HPGMX_K_NORMALIZE, 0);
-                        launch_normalize(M, K, p, col(k + 1), B.ctrl, c->stream);
                     }
                 };
                 if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, K), step);

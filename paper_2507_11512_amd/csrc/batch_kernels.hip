@@ -26,12 +26,15 @@
 namespace hpgmx {
 
 // ---- SpMV --------------------------------------------------------------------------------
+// With ctrl, vector j of the output is scaled by ctrl[j].colscale[k] (the
+// unnormalised-basis scale of the column x was computed from).
 template <typename V, int K, int R>
 __global__ __launch_bounds__(kBlock) void k_bspmv(i64 N, int clog2, int remap, const V *__restrict__ offv,
                                                   const int *__restrict__ offc,
                                                   const V *__restrict__ diag,
                                                   const typename VecT<V>::T *__restrict__ x,
-                                                  typename VecT<V>::T *__restrict__ y)
+                                                  typename VecT<V>::T *__restrict__ y,
+                                                  const Ctrl *ctrl, int k)
 {
     using T = typename VecT<V>::T;
     constexpr int L = K / R;
@@ -49,7 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(i64 N, int clog2, int remap, c
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const T dx = d * xp.v[r];
-        out.v[r] = dx + acc[r];
+        const T v = dx + acc[r];
+        out.v[r] = ctrl ? v * (T)ctrl[g * R + r].colscale[k] : v;
     }
     stp<T, R>(y + o, out);
 }
@@ -227,7 +231,8 @@ template <typename F> static void with_values(const Matrix &A, Prec p, F &&f)
 
 static inline unsigned lanes_grid(i64 rows, int K, int R) { return grid_for(rows * (K / R)); }
 
-void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s)
+void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s,
+                  const Ctrl *ctrl, int k)
 {
     with_values(A, p, [&](auto *v, auto *d) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
@@ -235,7 +240,7 @@ void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y,
         with_kr(K, R, [&](auto kc, auto rc) {
             constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
             hipLaunchKernelGGL((k_bspmv<V, KK, RR>), dim3(lanes_grid(A.g.N, KK, RR)), dim3(kBlock), 0, s,
-                               A.g.N, A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)x, (T *)y);
+                               A.g.N, A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)x, (T *)y, ctrl, k);
         });
     });
     HPGMX_LAUNCH_CHECK();

@@ -150,11 +150,21 @@ inline size_t vec_bytes(Prec p) { return p == P64 ? 8 : 4; }
 // Device-side control block of one Krylov cycle (FP64): Hessenberg matrix
 // (rotated) and its unrotated copy, Givens rotations, right-hand side t,
 // projected solution y, CGS2 coefficients and scalars.
+//
+// Basis columns are stored unnormalised: column j holds w_j, and the basis
+// vector of Alg. 3 is q_j = colscale[j] * w_j (colscale[0] = 1, since q_1 is
+// cast already divided by rho; colscale[j+1] = 1 / ||w_{j+1}|| from the
+// Givens step).  Every consumer applies the scale: the SpMV of the step
+// multiplies its output by the scale of the column it was fed, the inner
+// products and the staged CGS2 / basis-combination coefficients carry it.
+// In exact arithmetic this is Alg. 3; it saves the normalisation pass (a
+// read and a write of one vector per step).
 struct Ctrl {
     double H[kMaxBasis * kMaxRestart];
     double Hbar[kMaxBasis * kMaxRestart];
     double t[kMaxBasis], cs[kMaxBasis], sn[kMaxBasis], y[kMaxBasis];
     double h1[kMaxBasis], h2[kMaxBasis];
+    double colscale[kMaxBasis];
     // scalars read back by the host after every inner step (keep together)
     double rho, inv_rho, beta, inv_beta, nrm2, rho0;
     int breakdown, nonfinite;
@@ -184,7 +194,10 @@ void launch_stencil_correlation(const Matrix &A, const double *lam, const double
                                 double *partials, Ctrl *ctrl, hipStream_t s);
 void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s);
 void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s);
-void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s);
+// y = A x; with ctrl, y = (A x) * ctrl->colscale[k] (the SpMV of inner step
+// k, fed with the unnormalised basis column k).
+void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
+                 const Ctrl *ctrl = nullptr, int k = 0);
 // One colour of a Gauss-Seidel sweep: rows of colour c, slots per `mode`.
 void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
                       hipStream_t s);
@@ -214,7 +227,6 @@ void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *
 // w <- w - Q (h1 + h2), ||w||^2 and the Givens step of column k.
 void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                      Ctrl *ctrl, int k, int m, hipStream_t s);
-void launch_normalize(i64 M, int K, Prec p, void *w, const Ctrl *ctrl, hipStream_t s);
 void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,
                     double *partials, Ctrl *ctrl, int m, hipStream_t s);
 // ||v_j||^2 per right-hand side, then the finish `mode` (kFinishRho0 or
@@ -238,7 +250,9 @@ void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // K): the tile shape chosen per kernel and level by the autotuner.  p is
 // P64 or P32 (batched solves keep FP64 or FP32 matrices).
 bool batch_shape_ok(int K, int R);
-void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s);
+// Y = A X; with ctrl, vector j is scaled by ctrl[j].colscale[k].
+void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s,
+                  const Ctrl *ctrl = nullptr, int k = 0);
 void launch_bgs_colour(const Matrix &A, Prec p, int K, int R, int c, int mode, const void *r,
                        void *z, hipStream_t s);
 void launch_brestrict(const Matrix &Af, const Geom &gc, Prec p, int K, int R, const void *r,

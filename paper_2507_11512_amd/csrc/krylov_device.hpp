@@ -27,7 +27,9 @@ template <int K> __device__ __forceinline__ int rhs_of_thread() { return (int)(t
 // Coefficient arrays of the control block staged by the CGS and GEMV passes.
 enum CoefSel { kCoefH1, kCoefH12, kCoefY };
 
-// c[i * K + j] = coefficient i of right-hand side j (0 for i >= kb).
+// c[i * K + j] = coefficient i of right-hand side j for the stored
+// (unnormalised) column i: the coefficient of q_i times colscale[i]
+// (0 for i >= kb).
 template <int KB, int K>
 __device__ __forceinline__ void stage_coefs(double *c, const Ctrl *ctrl, int kb, CoefSel sel)
 {
@@ -37,6 +39,7 @@ __device__ __forceinline__ void stage_coefs(double *c, const Ctrl *ctrl, int kb,
         if (i < kb) {
             const Ctrl &cj = ctrl[j];
             v = sel == kCoefH1 ? cj.h1[i] : sel == kCoefH12 ? cj.h1[i] + cj.h2[i] : cj.y[i];
+            v *= cj.colscale[i];
         }
         c[t] = v;
     }

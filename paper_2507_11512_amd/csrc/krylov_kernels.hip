@@ -1,7 +1,7 @@
 // Krylov-side kernels of Alg. 3: the first CGS2 inner products, the two
-// fused CGS2 update passes, the normalisation, the FP64 outer residual, the
-// projected least-squares solve, the basis combination and the
-// mixed-precision solution update.
+// fused CGS2 update passes (the new basis vector is stored unnormalised, see
+// Ctrl), the FP64 outer residual, the projected least-squares solve, the
+// basis combination and the mixed-precision solution update.
 //
 // Reductions (inner products and norms) are deterministic: every workgroup
 // of a fixed-size grid-stride launch writes its partial sums, and a finish
@@ -81,6 +81,7 @@ __device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
         c->nrm2 = nrm2;
         c->breakdown = !(beta > 1e-300);
         c->inv_beta = c->breakdown ? 0.0 : 1.0 / beta;
+        c->colscale[k + 1] = c->inv_beta;  // q_{k+1} = w / beta, stored as w
         c->nonfinite = !isfinite(nrm2);
     }
     __syncthreads();
@@ -92,15 +93,6 @@ __device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
         c->t[k] = tk[0];
         c->t[k + 1] = tk[1];
     }
-}
-
-// ---- q_{k+1} = w / beta -------------------------------------------------------------------------
-template <typename T, int K>
-__global__ __launch_bounds__(kBlock) void k_normalize(i64 M, T *__restrict__ w, const Ctrl *ctrl)
-{
-    const double s = ctrl[rhs_of_thread<K>()].inv_beta;
-    const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (e < M) w[e] = (T)((double)w[e] * s);
 }
 
 // ---- FP64 outer residual r = b - A x with ||r||^2 (Alg. 3, residual step) ----
@@ -166,11 +158,11 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restr
     }
     __syncthreads();
     switch (mode) {
-    case kFinishH1:
-        if ((int)threadIdx.x < kb) c->h1[threadIdx.x] = tot[threadIdx.x];
+    case kFinishH1:  // the sums are over stored columns: apply their scales
+        if ((int)threadIdx.x < kb) c->h1[threadIdx.x] = tot[threadIdx.x] * c->colscale[threadIdx.x];
         break;
     case kFinishH2:
-        if ((int)threadIdx.x < kb) c->h2[threadIdx.x] = tot[threadIdx.x];
+        if ((int)threadIdx.x < kb) c->h2[threadIdx.x] = tot[threadIdx.x] * c->colscale[threadIdx.x];
         break;
     case kFinishNormGivens:
         givens_column(c, k, m, tot[0]);
@@ -185,6 +177,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restr
             c->inv_rho = rho > 0.0 ? 1.0 / rho : 0.0;
             c->nonfinite = !isfinite(rho);
             c->breakdown = 0;
+            c->colscale[0] = 1.0;  // q_1 is cast already divided by rho
         }
         break;
     case kFinishRho0:
@@ -398,16 +391,6 @@ void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void 
     }
     HPGMX_LAUNCH_CHECK();
     launch_finish(partials, (int)gr.x, 1, 1, kFinishNormGivens, ctrl, k, m, s);
-}
-
-void launch_normalize(i64 M, int K, Prec p, void *w, const Ctrl *ctrl, hipStream_t s)
-{
-    with_k(K, [&](auto kc) {
-        constexpr int KK = decltype(kc)::value;
-        if (p == P64) hipLaunchKernelGGL((k_normalize<double, KK>), dim3(grid_n(M)), dim3(kBlock), 0, s, M, (double *)w, ctrl);
-        else hipLaunchKernelGGL((k_normalize<float, KK>), dim3(grid_n(M)), dim3(kBlock), 0, s, M, (float *)w, ctrl);
-    });
-    HPGMX_LAUNCH_CHECK();
 }
 
 void launch_resid64(const Matrix &A, const double *x, const double *b, double *r,

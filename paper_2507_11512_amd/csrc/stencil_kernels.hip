@@ -137,39 +137,44 @@ void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat
 }
 
 // ---- SpMV -------------------------------------------------------------------------------
-// y = A x over all N rows (Sec. 3.2 ELL SpMV).
+// y = A x over all N rows (Sec. 3.2 ELL SpMV); with `scale`, y = (A x) * *scale
+// (the unnormalised-basis scale of the column x was computed from).
 template <typename V>
 __global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, int remap, const V *__restrict__ offv,
                                                  const int *__restrict__ offc,
                                                  const V *__restrict__ diag,
                                                  const typename VecT<V>::T *__restrict__ x,
-                                                 typename VecT<V>::T *__restrict__ y)
+                                                 typename VecT<V>::T *__restrict__ y,
+                                                 const double *scale)
 {
     using T = typename VecT<V>::T;
     const i64 p = gtid_xcd(remap);
     if (p >= N) return;
     const EllRow er = ell_row(p, N, clog2);
     const T dx = to_t<T>(ld_stream(diag + p)) * x[p];
-    y[p] = dx + ell_row_dot<T, V, kAllSlots>(offv, offc, x, er);
+    const T v = dx + ell_row_dot<T, V, kAllSlots>(offv, offc, x, er);
+    y[p] = scale ? v * (T)*scale : v;
 }
 
 template <typename V>
-static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void *y, hipStream_t s)
+static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void *y, hipStream_t s,
+                   const double *scale)
 {
     using T = typename VecT<V>::T;
     hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2,
                        xcd_remap_enabled(), v, A.col, d,
-                       (const T *)x, (T *)y);
+                       (const T *)x, (T *)y, scale);
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s)
+void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s, const Ctrl *ctrl, int k)
 {
+    const double *scale = ctrl ? ctrl->colscale + k : nullptr;
     switch (p) {
-    case P64: spmv_t(A, A.v64, A.d64, x, y, s); break;
-    case P32: spmv_t(A, A.v32, A.d32, x, y, s); break;
-    case P16: spmv_t(A, A.v16, A.d16, x, y, s); break;
-    case PB16: spmv_t(A, A.vb16, A.db16, x, y, s); break;
+    case P64: spmv_t(A, A.v64, A.d64, x, y, s, scale); break;
+    case P32: spmv_t(A, A.v32, A.d32, x, y, s, scale); break;
+    case P16: spmv_t(A, A.v16, A.d16, x, y, s, scale); break;
+    case PB16: spmv_t(A, A.vb16, A.db16, x, y, s, scale); break;
     }
 }
 
