@@ -93,7 +93,8 @@ struct hpgmx_ctx {
     double *b_int = nullptr, *x_int = nullptr, *r64 = nullptr;
     double *partials = nullptr;
     Ctrl *ctrl = nullptr;
-    double *host_scal = nullptr;   // pinned copy of the Ctrl scalar block
+    double *host_scal = nullptr;   // pinned copies of the Ctrl scalar block (2 slots)
+    hipEvent_t ev_scal[2] = {nullptr, nullptr};  // scalar copy of slot s has landed
     void *tmp[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
 
     // hipGraph replay of inner steps: a private stream (default priority) that
@@ -456,6 +457,40 @@ Scal read_scal(hpgmx_ctx *c)
     return s;
 }
 
+// Inner steps are pipelined one deep: the host enqueues step k + 1 before it
+// waits for the scalars of step k, so the GPU does not idle for the host's
+// round trip.  The copy of step k's scalars goes to slot k & 1 of the
+// pinned buffer and the host waits on that slot's event only.  A step
+// enqueued past the end of a cycle (convergence, breakdown) is discarded: it
+// writes only Hessenberg column k + 1, t from index k + 1 on and basis
+// column k + 2, which the back-solve and the basis combination of a cycle
+// of k + 1 steps never read, and the next cycle starts afresh.  No step is
+// enqueued past the restart length or the iteration limit.
+void ensure_scal_events(hpgmx_ctx *c)
+{
+    for (auto &e : c->ev_scal)
+        if (!e) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+}
+
+void enqueue_scal(hpgmx_ctx *c, const Ctrl *ctrl, int K, double *host, int slot)
+{
+    char *dst = (char *)host + (size_t)slot * K * 64;
+    if (K == 1)
+        hip_check(hipMemcpyAsync(dst, &ctrl->rho, sizeof(Scal), hipMemcpyDeviceToHost, c->stream),
+                  "hipMemcpyAsync");
+    else
+        hip_check(hipMemcpy2DAsync(dst, sizeof(Scal), &ctrl[0].rho, sizeof(Ctrl), sizeof(Scal), K,
+                                   hipMemcpyDeviceToHost, c->stream),
+                  "hipMemcpy2DAsync");
+    hip_check(hipEventRecord(c->ev_scal[slot], c->stream), "hipEventRecord");
+}
+
+void wait_scal(hpgmx_ctx *c, int K, const double *host, int slot, Scal *out)
+{
+    hip_check(hipEventSynchronize(c->ev_scal[slot]), "hipEventSynchronize");
+    std::memcpy(out, (const char *)host + (size_t)slot * K * 64, K * sizeof(Scal));
+}
+
 // Graph replay needs a capturable stream and no memset nodes (a level with
 // zero sweeps clears its vector with a memset); profiling times single
 // launches, so it runs eagerly.
@@ -583,9 +618,10 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                 launch_cast(N, 1, p, c->r64, c->ctrl, col(0), c->stream);
             }
             int kk = 0;
-            for (int k = 0; k < m; ++k) {
-                if (rho / rho0 < d->tol) break;
-                // one inner step: z = M^{-1} q_k, w = A z, CGS2, Givens, q_{k+1}
+            ensure_scal_events(c);
+            // one inner step: z = M^{-1} q_k, w = A z, CGS2, Givens, q_{k+1},
+            // then the copy of its scalars (see enqueue_scal)
+            auto run_step = [&](int k) {
                 auto step = [&]() {
                     vcycle(c, 0, p, col(k), K.z);
                     {
@@ -607,15 +643,25 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                 };
                 if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, 1), step);
                 else step();
-                sc = read_scal(c);
-                rho = sc.rho;
-                kk = k + 1;
-                ++its;
-                if (d->res_hist_host && its - 1 < d->res_hist_len) d->res_hist_host[its - 1] = rho / rho0;
-                S.est_rel_res = rho / rho0;
-                if (sc.nonfinite) break;
-                if (sc.breakdown) { S.breakdown = 1; break; }
-                if (its >= d->max_iters) break;
+                enqueue_scal(c, c->ctrl, 1, c->host_scal, k & 1);
+            };
+            if (!(rho / rho0 < d->tol)) {
+                run_step(0);
+                for (int k = 0; k < m; ++k) {
+                    const bool next = k + 1 < m && its + 1 < d->max_iters;
+                    if (next) run_step(k + 1);  // ahead of the test on step k
+                    wait_scal(c, 1, c->host_scal, k & 1, &sc);
+                    rho = sc.rho;
+                    kk = k + 1;
+                    ++its;
+                    if (d->res_hist_host && its - 1 < d->res_hist_len) d->res_hist_host[its - 1] = rho / rho0;
+                    S.est_rel_res = rho / rho0;
+                    if (sc.nonfinite) break;
+                    if (sc.breakdown) { S.breakdown = 1; break; }
+                    if (its >= d->max_iters) break;
+                    if (rho / rho0 < d->tol) break;
+                    if (!next) break;
+                }
             }
             if (sc.nonfinite) { status = HPGMX_ENONFINITE; c->err = "Krylov vector is not finite"; break; }
             {
@@ -682,7 +728,7 @@ Batch &ensure_batch(hpgmx_ctx *c, int K)
     hip_check(hipMemsetAsync(B.ctrl, 0, K * sizeof(Ctrl), c->stream), "hipMemsetAsync");
     B.partials = (double *)c->dalloc((size_t)kMaxRedBlocks * kMaxBasis * K * 8);
     if (!B.host_scal)
-        hip_check(hipHostMalloc((void **)&B.host_scal, (size_t)K * 64, hipHostMallocDefault), "hipHostMalloc");
+        hip_check(hipHostMalloc((void **)&B.host_scal, (size_t)2 * K * 64, hipHostMallocDefault), "hipHostMalloc");
     B.K = K;
     return B;
 }
@@ -962,15 +1008,11 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
             bool cyc[kMaxBatch];
             for (int j = 0; j < K; ++j) cyc[j] = !done[j];
             bool nonfin = false;
-            for (int k = 0; k < m; ++k) {
-                bool act = false;
-                for (int j = 0; j < K; ++j) {
-                    if (cyc[j] && rho[j] / rho0[j] < d->tol) cyc[j] = false;
-                    act = act || cyc[j];
-                }
-                if (!act) break;
-                // one inner step for every right-hand side: z = M^{-1} q_k,
-                // w = A z, CGS2, Givens, q_{k+1}
+            ensure_scal_events(c);
+            // one inner step for every right-hand side: z = M^{-1} q_k, w = A z,
+            // CGS2, Givens, q_{k+1}, then the copy of the scalars (pipelined one
+            // deep as in solve(); see enqueue_scal)
+            auto run_step = [&](int k) {
                 auto step = [&]() {
                     bvcycle(c, B, 0, p, col(k), Kr.z);
                     {
@@ -993,20 +1035,41 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
                 };
                 if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, K), step);
                 else step();
-                read_scal_batch(c, B, sc);
+                enqueue_scal(c, B.ctrl, K, B.host_scal, k & 1);
+            };
+            // right-hand sides still taking steps in this cycle (the test at
+            // the top of Alg. 3's inner loop)
+            auto any_active = [&]() {
+                bool act = false;
                 for (int j = 0; j < K; ++j) {
-                    if (!cyc[j]) continue;
-                    rho[j] = sc[j].rho;
-                    kk[j] = k + 1;
-                    ++its[j];
-                    if (d->res_hist_host && j < nrhs && its[j] - 1 < d->res_hist_len)
-                        d->res_hist_host[(size_t)j * d->res_hist_len + its[j] - 1] = rho[j] / rho0[j];
-                    S[j].est_rel_res = rho[j] / rho0[j];
-                    if (sc[j].nonfinite) { nonfin = true; cyc[j] = false; continue; }
-                    if (sc[j].breakdown) { S[j].breakdown = 1; cyc[j] = false; continue; }
-                    if (its[j] >= d->max_iters) cyc[j] = false;
+                    if (cyc[j] && rho[j] / rho0[j] < d->tol) cyc[j] = false;
+                    act = act || cyc[j];
                 }
-                if (nonfin) break;
+                return act;
+            };
+            if (any_active()) {
+                run_step(0);
+                for (int k = 0; k < m; ++k) {
+                    bool more = false;  // some right-hand side may take step k + 1
+                    for (int j = 0; j < K; ++j) more = more || (cyc[j] && its[j] + 1 < d->max_iters);
+                    const bool next = k + 1 < m && more;
+                    if (next) run_step(k + 1);  // ahead of the tests on step k
+                    wait_scal(c, K, B.host_scal, k & 1, sc);
+                    for (int j = 0; j < K; ++j) {
+                        if (!cyc[j]) continue;
+                        rho[j] = sc[j].rho;
+                        kk[j] = k + 1;
+                        ++its[j];
+                        if (d->res_hist_host && j < nrhs && its[j] - 1 < d->res_hist_len)
+                            d->res_hist_host[(size_t)j * d->res_hist_len + its[j] - 1] = rho[j] / rho0[j];
+                        S[j].est_rel_res = rho[j] / rho0[j];
+                        if (sc[j].nonfinite) { nonfin = true; cyc[j] = false; continue; }
+                        if (sc[j].breakdown) { S[j].breakdown = 1; cyc[j] = false; continue; }
+                        if (its[j] >= d->max_iters) cyc[j] = false;
+                    }
+                    if (nonfin) break;
+                    if (!any_active() || !next) break;
+                }
             }
             if (nonfin) { status = HPGMX_ENONFINITE; c->err = "Krylov vector is not finite"; break; }
             KCount kc{};
@@ -1646,6 +1709,8 @@ hpgmx_status hpgmx_destroy(hpgmx_handle h)
     }
     for (void *p : h->owned) (void)hipFree(p);
     if (h->host_scal) (void)hipHostFree(h->host_scal);
+    for (auto &e : h->ev_scal)
+        if (e) (void)hipEventDestroy(e);
     for (auto &kv : h->batches)
         if (kv.second.host_scal) (void)hipHostFree(kv.second.host_scal);
     delete h;
