@@ -51,7 +51,7 @@ def parse():
     ap.add_argument("--levels", type=int, default=4)
     ap.add_argument("--iters", type=int, default=300, help="inner steps per timed solve")
     ap.add_argument("--restart", type=int, default=30)
-    ap.add_argument("--cpu-iters", type=int, default=20, help="inner steps of the CPU-oracle sample")
+    ap.add_argument("--cpu-iters", type=int, default=30, help="inner steps of the CPU-oracle sample (30: one restart cycle)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
     ap.add_argument("--no-validation", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the timed FP64 phase")

@@ -219,3 +219,33 @@ def test_solve_batched_192(hp, p192):
     x0, st0 = p192.solve(dev(Bh[0], 0), tol=1e-9, restart=30, precision="mxp")
     print(f"[192^3 single j=0] iters={st0.iters} time={st0.solve_ms / 1e3:.2f}s", flush=True)
     assert abs(stats[0].iters - st0.iters) <= 2
+
+
+# ---- the low-precision configuration: 256^3 with 16-bit matrices ----------------------------
+@pytest.fixture(scope="module")
+def p256(hp):
+    print("[setup] 256^3, 4 levels, forward GS (the 16-bit matrix configuration)", flush=True)
+    P = hp.Problem(256, beta=0.5, levels=4, sweep="forward")
+    yield P
+    P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_solve_256_16bit_matrices(hp, p256, precision):
+    """FP16 / BF16 matrices and hierarchy, FP32 accumulation and basis, FP64
+    residual and update: the 1e-9 residual (recomputed by the oracle), the
+    exact solution x* = 1 within the residual's amplification, and the error
+    against the FP64 solve."""
+    import torch
+    d = (256, 256, 256)
+    b = p256.rhs_from_x(torch.ones(256 ** 3, dtype=torch.float64, device="cuda"))
+    x, st = p256.solve(b, tol=1e-9, restart=30, precision=precision)
+    x64, st64 = p256.solve(b, tol=1e-9, restart=30, precision="fp64")
+    xh = host(x)
+    bh = oracle.spmv(d, np.ones(xh.size))
+    res = np.linalg.norm(bh - oracle.spmv(d, xh)) / np.linalg.norm(bh)
+    err = np.linalg.norm(xh - 1.0) / np.sqrt(xh.size)
+    e64 = np.linalg.norm(xh - host(x64)) / np.linalg.norm(host(x64))
+    print(f"[256^3 {precision}] iters={st.iters} (fp64 {st64.iters}) res={res:.3e} |x-1|/|1|={err:.3e} "
+          f"|x-x64|/|x64|={e64:.3e}", flush=True)
+    assert st.converged and res <= 1e-9 and err <= 1e-8 and e64 <= 1e-8
