@@ -413,14 +413,15 @@ def run_batched(args, hp, pm, torch, np):
         hp.rhs_from_x(P.h, U_[j], B[j])
     torch.cuda.synchronize()
     log(f"setup done in {time.time() - t:.2f}s")
+    inner_code = {"fp32": hp.F32, "fp16": hp.F16, "bf16": hp.BF16}[args.inner]
     tuning = {}
     if not args.no_autotune:
-        for name, code in (("fp32", hp.F32), ("fp64", hp.F64)):
+        for name, code in ((args.inner, inner_code), ("fp64", hp.F64)):
             tt = hp.batch_autotune(P.h, k, code)
             tuning[name] = {hp.BK_NAMES[b]: tt["rhs_per_lane"][b][:L] for b in range(hp.BK_COUNT)}
             log(f"autotuned tiles ({name}): {tuning[name]}")
 
-    PREC = {"fp64": "fp64", "mxp": "mxp"}
+    PREC = {"fp64": "fp64", "mxp": args.inner}
     val = {}
     n_d = n_ir = None
     if not args.no_validation:
@@ -462,7 +463,7 @@ def run_batched(args, hp, pm, torch, np):
 
     kernels = {}
     if not args.no_profile:
-        for prec, code in (("mxp", hp.F32),) + (() if args.no_fp64 else (("fp64", hp.F64),)):
+        for prec, code in (("mxp", inner_code),) + (() if args.no_fp64 else (("fp64", hp.F64),)):
             _, sts = P.solve_batched(B, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec],
                                      profile=True)
             profile_kernels(hp, P.h, kernel_bytes_table_batched(cfg, cycles, code, 8 if k > 4 else (4 if k > 2 else 2),
@@ -508,10 +509,11 @@ def run_batched(args, hp, pm, torch, np):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32-inner/f64-outer",
+        "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)"}[args.inner]
+                 + "-inner/f64-outer",
         "data": f"synthetic: generated 27-point stencil, b_j = A u_j, u_j ~ N(0,1) seeded 11512+j, x0 = 0",
         "config": {"workload": f"hpg-mxp batched {n}^3 27-pt nonsym beta=0.5, {k} right-hand sides, "
-                               f"GMRES({m})-IR (fp32 inner), {L}-level V-cycle fwd multicolour GS 1/1/1, "
+                               f"GMRES({m})-IR ({args.inner} inner), {L}-level V-cycle fwd multicolour GS 1/1/1, "
                                f"{args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "nrhs": k, "restart": m, "levels": L,
                    "iters_per_solve": args.iters,

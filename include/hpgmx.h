@@ -233,8 +233,9 @@ hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *to
  * passed as nrhs contiguous vectors one after the other, [nrhs][N] in the
  * natural order of the level (a row-major (nrhs, N) tensor).  Internally
  * the batch is padded to K = 2, 4 or 8 interleaved vectors; padded entries
- * are zero.  Batched calls take dtype HPGMX_F64 or HPGMX_F32 (EINVAL for the
- * 16-bit matrix types).
+ * are zero.  dtype is the matrix precision as for the single-vector calls
+ * (vectors FP64 for HPGMX_F64, FP32 otherwise; tile tables are kept per
+ * dtype).
  *
  * Tile shapes.  The batched stencil kernels run R of the K right-hand sides
  * of a row per lane (R = 1, 2, 4 or 8, R <= K; K / R lanes share a row).
@@ -267,8 +268,8 @@ hpgmx_status hpgmx_batch_get_tuning(hpgmx_handle h, int nrhs, int dtype, hpgmx_b
 
 /* Extra device bytes the batched state for nrhs right-hand sides, the
  * hierarchy `mg`, restart length `restart` and the inner dtypes in
- * dtype_mask (bits 1 << HPGMX_F64, 1 << HPGMX_F32) needs on top of
- * hpgmx_workspace_bytes (a bound workspace must hold both). */
+ * dtype_mask (bits 1 << hpgmx_dtype) needs on top of hpgmx_workspace_bytes
+ * for the same mask (a bound workspace must hold both). */
 hpgmx_status hpgmx_workspace_bytes_batched(hpgmx_handle h, const hpgmx_mg_desc *mg, int nrhs, int restart,
                                            unsigned dtype_mask, size_t *bytes);
 
@@ -286,7 +287,7 @@ hpgmx_status hpgmx_vcycle_batched(hpgmx_handle h, int dtype, int nrhs, const voi
 
 /* Alg. 3 for nrhs right-hand sides in lockstep.  B: FP64 [nrhs][N]; X: FP64
  * [nrhs][N], initial guesses on entry, solutions on exit; stats: nrhs
- * entries (may be NULL).  desc->inner_dtype is HPGMX_F64 or HPGMX_F32;
+ * entries (may be NULL).  desc->inner_dtype as for hpgmx_gmres_ir_solve;
  * desc->res_hist_host, if set, holds nrhs rows of res_hist_len entries.
  * Right-hand side j follows exactly the sequence of steps its own
  * hpgmx_gmres_ir_solve would take: it stops taking Krylov steps in a cycle

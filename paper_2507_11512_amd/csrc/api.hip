@@ -69,7 +69,7 @@ struct Batch {
     void *lr[2][kMaxLevels] = {}, *lz[2][kMaxLevels] = {};  // levels >= 1, [0] double, [1] float
     Krylov kry[2];                                           // per vector type
     void *tmp[2][3] = {};                                    // ABI staging and autotuning
-    BatchTune tune[2];
+    BatchTune tune[4];                                       // per matrix precision (Prec)
 };
 
 }  // namespace
@@ -777,7 +777,7 @@ void ensure_batch_tmp(hpgmx_ctx *c, Batch &B, int vt)
 // small ones, where parallelism is scarce).
 int tile_r(const hpgmx_ctx *c, const Batch &B, Prec p, int kind, int l)
 {
-    const int R = B.tune[vt_of(p)].R[kind][l];
+    const int R = B.tune[p].R[kind][l];
     if (R > 0) return R;
     return c->lv[l].A.g.N * B.K >= (1ll << 22) ? B.K : 1;
 }
@@ -911,7 +911,7 @@ void autotune(hpgmx_ctx *c, Batch &B, Prec p)
         for (int l = 0; l < kMaxLevels; ++l)
             if (T.ms[k][l] < 0.0) T.ms[k][l] = 0.0;
     T.set = true;
-    B.tune[vt] = T;
+    B.tune[p] = T;
     c->drop_graphs();  // captured steps hold the old tiles
 }
 
@@ -932,7 +932,7 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
     const int K = batch_width(nrhs);
     Batch &B = ensure_batch(c, K);
     ensure_batch_prec(c, B, p, m);
-    if ((d->flags & HPGMX_SOLVE_AUTOTUNE) && !B.tune[vt_of(p)].set) autotune(c, B, p);
+    if ((d->flags & HPGMX_SOLVE_AUTOTUNE) && !B.tune[p].set) autotune(c, B, p);
     Krylov &Kr = B.kry[vt_of(p)];
     const Matrix &A0 = c->lv[0].A;
     const Geom &g0 = A0.g;
@@ -1128,7 +1128,8 @@ size_t plan_batch_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, i
     add(K * sizeof(Ctrl));
     add((size_t)kMaxRedBlocks * kMaxBasis * K * 8);
     for (int vt = 0; vt < 2; ++vt) {
-        if (!((mask >> (vt == 0 ? HPGMX_F64 : HPGMX_F32)) & 1u)) continue;
+        const bool want = vt == 0 ? (mask & 1u) != 0 : (mask & 0xEu) != 0;  // FP32 vectors for F32/F16/BF16
+        if (!want) continue;
         const size_t vb = vt == 0 ? 8 : 4;
         int nx = pd.nx / 2, ny = pd.ny / 2, nz = pd.nz / 2;
         for (int l = 1; l < mg.levels; ++l) {
@@ -1172,12 +1173,7 @@ void check_ptr(const void *p, const char *name)
     if (!p) fail(HPGMX_EINVAL, std::string(name) + " is NULL");
 }
 
-Prec check_batch_dtype(int dtype)
-{
-    if (dtype != HPGMX_F64 && dtype != HPGMX_F32)
-        fail(HPGMX_EINVAL, "batched calls take dtype HPGMX_F64 or HPGMX_F32");
-    return (Prec)dtype;
-}
+Prec check_batch_dtype(int dtype) { return check_dtype(dtype); }
 
 void check_nrhs(int nrhs)
 {
@@ -1203,7 +1199,7 @@ void fill_tuning(const hpgmx_ctx *c, const Batch &B, Prec p, hpgmx_batch_tuning 
             if (k == HPGMX_BK_RESTRICT && l + 1 >= L) continue;
             if (k == HPGMX_BK_RESID64 && l > 0) continue;
             out->rhs_per_lane[k][l] = tile_r(c, B, p, k, l);
-            out->ms[k][l] = B.tune[vt_of(p)].ms[k][l];
+            out->ms[k][l] = B.tune[p].ms[k][l];
         }
 }
 
@@ -1511,7 +1507,7 @@ hpgmx_status hpgmx_workspace_bytes_batched(hpgmx_handle h, const hpgmx_mg_desc *
         check_nrhs(nrhs);
         if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
         if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
-        *bytes = plan_batch_bytes(h->prob, *mg, nrhs, restart, dtype_mask & 0x3u);
+        *bytes = plan_batch_bytes(h->prob, *mg, nrhs, restart, dtype_mask & 0xFu);
         return HPGMX_OK;
     });
 }
@@ -1551,7 +1547,7 @@ hpgmx_status hpgmx_batch_set_tuning(hpgmx_handle h, int nrhs, int dtype, const h
                 T.ms[k][l] = in->ms[k][l];
             }
         T.set = true;
-        B.tune[vt_of(p)] = T;
+        B.tune[p] = T;
         h->drop_graphs();
         return HPGMX_OK;
     });

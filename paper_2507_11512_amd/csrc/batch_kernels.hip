@@ -221,12 +221,17 @@ template <typename F> static void with_k(int K, F &&f)
     throw std::runtime_error("unsupported batch width");
 }
 
-// Matrix values of a batched call: FP64 or FP32.
+// Matrix values of a batched call (the vectors are FP64 for P64, FP32
+// otherwise).
 template <typename F> static void with_values(const Matrix &A, Prec p, F &&f)
 {
-    if (p == P64) return f(A.v64, A.d64);
-    if (p == P32) return f(A.v32, A.d32);
-    throw std::runtime_error("batched kernels take FP64 or FP32 matrices");
+    switch (p) {
+    case P64: return f(A.v64, A.d64);
+    case P32: return f(A.v32, A.d32);
+    case P16: return f(A.v16, A.d16);
+    case PB16: return f(A.vb16, A.db16);
+    }
+    throw std::runtime_error("unknown matrix precision");
 }
 
 static inline unsigned lanes_grid(i64 rows, int K, int R) { return grid_for(rows * (K / R)); }

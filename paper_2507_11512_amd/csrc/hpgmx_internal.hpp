@@ -247,8 +247,8 @@ void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 // ---- batched stencil kernels (K interleaved right-hand sides, K = 2, 4, 8) ----
 // Vectors hold N * K entries ([p * K + j]); a vector that is gathered from
 // holds (N + 1) * K with row N zero.  R right-hand sides per lane (R divides
-// K): the tile shape chosen per kernel and level by the autotuner.  p is
-// P64 or P32 (batched solves keep FP64 or FP32 matrices).
+// K): the tile shape chosen per kernel and level by the autotuner.  p is the
+// matrix precision (vectors FP64 for P64, FP32 otherwise).
 bool batch_shape_ok(int K, int R);
 // Y = A X; with ctrl, vector j is scaled by ctrl[j].colscale[k].
 void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s,

@@ -292,7 +292,7 @@ def test_batched_argument_errors(hp):
     P = problem(hp, dims, 3)
     v = torch.zeros((3, P.N), dtype=torch.float32, device="cuda")
     with pytest.raises(hp.HpgmxError) as e:
-        hp.spmv_batched(P.h, 0, 2, v, v.clone())           # 16-bit matrix type
+        hp.spmv_batched(P.h, 0, 7, v, v.clone())           # no such dtype
     assert e.value.status == -1
     with pytest.raises(hp.HpgmxError) as e:
         hp.batch_set_tuning(P.h, 3, 1, 8)                  # K = 4: R = 8 does not divide
@@ -306,7 +306,7 @@ def test_batched_argument_errors(hp):
     assert e.value.status == -1
     b = torch.zeros((2, P.N), dtype=torch.float64, device="cuda")
     with pytest.raises(hp.HpgmxError) as e:
-        hp.gmres_ir_solve_batched(P.h, b, b.clone(), inner_dtype=3)
+        hp.gmres_ir_solve_batched(P.h, b, b.clone(), inner_dtype=5)
     assert e.value.status == -1
     X, stats = P.solve_batched(b)                           # usable; b = 0 gives x = 0
     assert all(s.converged and s.iters == 0 for s in stats) and bool((X == 0).all())
@@ -353,3 +353,34 @@ def test_batched_bound_workspace(hp):
     assert all(s.converged for s in stats) and all(s.converged for s in stats2)
     assert [s.iters for s in stats] == [s.iters for s in str_]
     assert torch.equal(X, Xr)
+
+
+@pytest.mark.parametrize("dtype16,name", [(2, "fp16"), (3, "bf16")])
+def test_batched_16bit_matrices_equal_fp32(hp, dtype16, name):
+    """With beta = 0.5 every stencil entry (26, -1, -1.5, -0.5) is exact in
+    FP16 and BF16, and the 16-bit values are widened exactly before the FP32
+    arithmetic: batched SpMV, V-cycle and solve equal the FP32-matrix ones bit
+    for bit, for every tile shape."""
+    import torch
+    dims = (24, 20, 16)
+    nrhs = 6
+    P = problem(hp, dims, 3)
+    X = np.stack([rnd(inputs.uniform(dims, 5000 + j), 1) for j in range(nrhs)])
+    for R in widths(nrhs):
+        force_tiles(hp, P, nrhs, 1, R)
+        force_tiles(hp, P, nrhs, dtype16, R)
+        Y32, Y16 = dev(np.zeros(X.shape), 1), dev(np.zeros(X.shape), 1)
+        hp.spmv_batched(P.h, 0, 1, dev(X, 1), Y32)
+        hp.spmv_batched(P.h, 0, dtype16, dev(X, 1), Y16)
+        assert torch.equal(Y32, Y16), R
+        Z32, Z16 = dev(np.zeros(X.shape), 1), dev(np.zeros(X.shape), 1)
+        hp.vcycle_batched(P.h, 1, dev(X, 1), Z32)
+        hp.vcycle_batched(P.h, dtype16, dev(X, 1), Z16)
+        assert torch.equal(Z32, Z16), R
+    _, B = _batch_rhs(dims, nrhs)
+    X32, s32 = P.solve_batched(dev(B, 0), precision="mxp")
+    X16, s16 = P.solve_batched(dev(B, 0), precision=name)
+    assert [s.iters for s in s16] == [s.iters for s in s32] and all(s.converged for s in s16)
+    assert torch.equal(X16, X32)
+    force_tiles(hp, P, nrhs, 1, 0)
+    force_tiles(hp, P, nrhs, dtype16, 0)
