@@ -94,7 +94,9 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
             B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.gs_colour_bytes(rows // 8, pm.SLOTS, dtype)
             if not coarsest:
                 rc = pm.nrows(L[l + 1])
-                B[(hp.K_RESTRICT, l)] += pm.restrict_bytes(rc, dtype)
+                # one forward pre-sweep from zero: the restriction reads 8 slots
+                B[(hp.K_RESTRICT, l)] += (pm.restrict_after_sweep_bytes(rc, dtype) if cfg.pre == 1 and cfg.sweep == 0
+                                          else pm.restrict_bytes(rc, dtype))
                 B[(hp.K_PROLONG, l)] += pm.prolong_bytes(rc, dtype)
 
     N = pm.nrows(cfg.dims)
@@ -134,7 +136,8 @@ def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
             B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.bgs_colour_bytes(rows // 8, pm.SLOTS, dtype, K)
             if not coarsest:
                 rc = pm.nrows(L[l + 1])
-                B[(hp.K_RESTRICT, l)] += pm.brestrict_bytes(rc, dtype, K)
+                B[(hp.K_RESTRICT, l)] += (pm.restrict_after_sweep_bytes(rc, dtype, 8, K)
+                                          if cfg.pre == 1 and cfg.sweep == 0 else pm.brestrict_bytes(rc, dtype, K))
                 B[(hp.K_PROLONG, l)] += pm.bprolong_bytes(rc, dtype, K)
 
     N = pm.nrows(cfg.dims)

@@ -418,6 +418,13 @@ void smooth_level(hpgmx_ctx *c, int l, Prec p, int kind, const void *r, void *z,
     }
 }
 
+// The pre-smoother is one forward or backward sweep from z = 0, so the fused
+// restriction can use the shortcut of k_restrict_after_sweep.
+bool restrict_after_single_sweep(const hpgmx_mg_desc &mg)
+{
+    return mg.pre_sweeps == 1 && (mg.sweep == HPGMX_GS_FORWARD || mg.sweep == HPGMX_GS_BACKWARD);
+}
+
 // z = M^{-1} r on level l (z is overwritten; the cycle starts from zero).
 void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z)
 {
@@ -431,7 +438,10 @@ void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z)
     smooth_level(c, l, p, mg.sweep, r, z, true, mg.pre_sweeps);
     {
         ProfScope ps(c, HPGMX_K_RESTRICT, l);
-        launch_restrict(c->lv[l].A, C.A.g, p, r, z, C.r[vt], c->stream);
+        if (restrict_after_single_sweep(mg))
+            launch_restrict_after_sweep(c->lv[l].A, C.A.g, p, mg.sweep == HPGMX_GS_FORWARD, z, C.r[vt], c->stream);
+        else
+            launch_restrict(c->lv[l].A, C.A.g, p, r, z, C.r[vt], c->stream);
     }
     vcycle(c, l + 1, p, C.r[vt], C.z[vt]);
     {
@@ -831,8 +841,12 @@ void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z)
     bsmooth_level(c, B, l, p, mg.sweep, r, z, true, mg.pre_sweeps);
     {
         ProfScope ps(c, HPGMX_K_RESTRICT, l);
-        launch_brestrict(c->lv[l].A, gc, p, B.K, tile_r(c, B, p, HPGMX_BK_RESTRICT, l), r, z, B.lr[vt][l + 1],
-                         c->stream);
+        const int R = tile_r(c, B, p, HPGMX_BK_RESTRICT, l);
+        if (restrict_after_single_sweep(mg))
+            launch_brestrict_after_sweep(c->lv[l].A, gc, p, B.K, R, mg.sweep == HPGMX_GS_FORWARD, z,
+                                         B.lr[vt][l + 1], c->stream);
+        else
+            launch_brestrict(c->lv[l].A, gc, p, B.K, R, r, z, B.lr[vt][l + 1], c->stream);
     }
     bvcycle(c, B, l + 1, p, B.lr[vt][l + 1], B.lz[vt][l + 1]);
     {
@@ -889,8 +903,13 @@ void autotune(hpgmx_ctx *c, Batch &B, Prec p)
                     launch_bgs_colour(A, p, K, R, col, kGsZeroForward, t0, t1, c->stream);
             });
             if (l + 1 < L)
-                t[HPGMX_BK_RESTRICT] = time_it(
-                    [&] { launch_brestrict(A, c->lv[l + 1].A.g, p, K, R, t0, t1, t2, c->stream); });
+                t[HPGMX_BK_RESTRICT] = time_it([&] {  // the variant the V-cycle uses
+                    if (restrict_after_single_sweep(c->mg))
+                        launch_brestrict_after_sweep(A, c->lv[l + 1].A.g, p, K, R, c->mg.sweep == HPGMX_GS_FORWARD,
+                                                     t1, t2, c->stream);
+                    else
+                        launch_brestrict(A, c->lv[l + 1].A.g, p, K, R, t0, t1, t2, c->stream);
+                });
             if (l == 0)
                 t[HPGMX_BK_RESID64] = time_it([&] {
                     launch_bresid64(A, K, R, (const double *)B.tmp[0][0], (const double *)B.tmp[0][1],

@@ -120,6 +120,33 @@ __global__ __launch_bounds__(kBlock) void k_brestrict(Geom gf, Geom gc, int clog
     stp<T, R>(rc + to_internal(gc, I, J, Kc) * K + g * R, out);
 }
 
+// ---- the fused restriction right after a single sweep from zero (see
+// k_restrict_after_sweep in stencil_kernels.hip): minus the couplings of the
+// injection rows to the colours relaxed after colour 4 ----
+template <typename V, int K, int R, unsigned MASK>
+__global__ __launch_bounds__(kBlock) void k_brestrict_after_sweep(Geom gf, Geom gc, int clog2, int remap,
+                                                                  const V *__restrict__ offv,
+                                                                  const int *__restrict__ offc,
+                                                                  const typename VecT<V>::T *__restrict__ z,
+                                                                  typename VecT<V>::T *__restrict__ rc)
+{
+    using T = typename VecT<V>::T;
+    constexpr int L = K / R;
+    const i64 t = gtid_xcd(remap);
+    const i64 q = t / L;
+    if (q >= gc.N) return;
+    const int g = (int)(t % L);
+    const i64 N = gf.N, p = gf.off[4] + q;
+    const EllRow er = ell_row(p, N, clog2);
+    T acc[R];
+    ell_row_dot_b<T, V, K, R, MASK>(offv, offc, z + g * R, er, acc);
+    const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), Kc = (int)(q / ((i64)gc.nx * gc.ny));
+    Pack<T, R> out;
+#pragma unroll
+    for (int i = 0; i < R; ++i) out.v[i] = -acc[i];
+    stp<T, R>(rc + to_internal(gc, I, J, Kc) * K + g * R, out);
+}
+
 // ---- prolongation-correction z += P zc (one lane per element) -------------------------------
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_bprolong(Geom gf, Geom gc, const T *__restrict__ zc,
@@ -308,6 +335,29 @@ void launch_brestrict(const Matrix &Af, const Geom &gc, Prec p, int K, int R, co
             hipLaunchKernelGGL((k_brestrict<V, KK, RR>), dim3(lanes_grid(gc.N, KK, RR)), dim3(kBlock), 0, s,
                                Af.g, gc, Af.clog2, xcd_remap_enabled(), v, Af.col, d, (const T *)r,
                                (const T *)z, (T *)rc);
+        });
+    });
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_brestrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, int K, int R, bool forward,
+                                  const void *z, void *rc, hipStream_t s)
+{
+    constexpr unsigned kFwd = kAllSlots & ~zero_guess_mask(4, true);
+    constexpr unsigned kBwd = kAllSlots & ~zero_guess_mask(4, false);
+    with_values(Af, p, [&](auto *v, auto *d) {
+        (void)d;
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using T = typename VecT<V>::T;
+        with_kr(K, R, [&](auto kc, auto rcn) {
+            constexpr int KK = decltype(kc)::value, RR = decltype(rcn)::value;
+            const dim3 gr(lanes_grid(gc.N, KK, RR)), bl(kBlock);
+            if (forward)
+                hipLaunchKernelGGL((k_brestrict_after_sweep<V, KK, RR, kFwd>), gr, bl, 0, s, Af.g, gc, Af.clog2,
+                                   xcd_remap_enabled(), v, Af.col, (const T *)z, (T *)rc);
+            else
+                hipLaunchKernelGGL((k_brestrict_after_sweep<V, KK, RR, kBwd>), gr, bl, 0, s, Af.g, gc, Af.clog2,
+                                   xcd_remap_enabled(), v, Af.col, (const T *)z, (T *)rc);
         });
     });
     HPGMX_LAUNCH_CHECK();

@@ -203,6 +203,11 @@ void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, v
                       hipStream_t s);
 void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
                      void *rc, hipStream_t s);
+// The same result when z is the outcome of a single Gauss-Seidel sweep from
+// z = 0 in direction `forward` (see k_restrict_after_sweep): reads only the
+// slots of the injection rows that couple to colours relaxed after colour 4.
+void launch_restrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, bool forward, const void *z,
+                                 void *rc, hipStream_t s);
 void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void *z,
                     hipStream_t s);
 
@@ -257,6 +262,8 @@ void launch_bgs_colour(const Matrix &A, Prec p, int K, int R, int c, int mode, c
                        void *z, hipStream_t s);
 void launch_brestrict(const Matrix &Af, const Geom &gc, Prec p, int K, int R, const void *r,
                       const void *z, void *rc, hipStream_t s);
+void launch_brestrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, int K, int R, bool forward,
+                                  const void *z, void *rc, hipStream_t s);
 void launch_bprolong(const Geom &gf, const Geom &gc, Prec p, int K, const void *zc, void *z,
                      hipStream_t s);
 // r = b - A x in FP64 for K right-hand sides, then rho_j = ||r_j|| into

@@ -297,6 +297,61 @@ void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, co
     }
 }
 
+// ---- the fused restriction right after a single sweep from zero -----------------------------------
+// When z is the outcome of one Gauss-Seidel sweep from z = 0 (the
+// pre-smoother of a V-cycle level with one sweep), the relaxation of colour
+// 4 made r - A z vanish at the colour-4 rows while the colours relaxed after
+// colour 4 were still zero.  Those colours are the only ones that changed
+// since, so at an injection point
+//     r - A z = - sum over the slots to colours relaxed after 4 of a z,
+// which is eq. (6) evaluated with 8 of the 26 slots (forward sweep; 18
+// backward) and without r or the diagonal.  Exact in exact arithmetic; the
+// rounding differs from the full formula by the rounding of the colour-4
+// relaxation.
+template <typename V, unsigned MASK>
+__global__ __launch_bounds__(kBlock) void k_restrict_after_sweep(Geom gf, Geom gc, int clog2, int remap,
+                                                                 const V *__restrict__ offv,
+                                                                 const int *__restrict__ offc,
+                                                                 const typename VecT<V>::T *__restrict__ z,
+                                                                 typename VecT<V>::T *__restrict__ rc)
+{
+    using T = typename VecT<V>::T;
+    const i64 q = gtid_xcd(remap);
+    if (q >= gc.N) return;
+    const i64 N = gf.N, p = gf.off[4] + q;
+    const EllRow er = ell_row(p, N, clog2);
+    const T acc = ell_row_dot<T, V, MASK>(offv, offc, z, er);
+    const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
+    rc[to_internal(gc, I, J, K)] = -acc;
+}
+
+template <typename V>
+static void restrict_after_t(const Matrix &A, const Geom &gc, const V *v, bool forward, const void *z, void *rc,
+                             hipStream_t s)
+{
+    using T = typename VecT<V>::T;
+    constexpr unsigned kFwd = kAllSlots & ~zero_guess_mask(4, true);
+    constexpr unsigned kBwd = kAllSlots & ~zero_guess_mask(4, false);
+    if (forward)
+        hipLaunchKernelGGL((k_restrict_after_sweep<V, kFwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc,
+                           A.clog2, xcd_remap_enabled(), v, A.col, (const T *)z, (T *)rc);
+    else
+        hipLaunchKernelGGL((k_restrict_after_sweep<V, kBwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc,
+                           A.clog2, xcd_remap_enabled(), v, A.col, (const T *)z, (T *)rc);
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_restrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, bool forward, const void *z, void *rc,
+                                 hipStream_t s)
+{
+    switch (p) {
+    case P64: restrict_after_t(Af, gc, Af.v64, forward, z, rc, s); break;
+    case P32: restrict_after_t(Af, gc, Af.v32, forward, z, rc, s); break;
+    case P16: restrict_after_t(Af, gc, Af.v16, forward, z, rc, s); break;
+    case PB16: restrict_after_t(Af, gc, Af.vb16, forward, z, rc, s); break;
+    }
+}
+
 // ---- prolongation-correction: z += P zc, P = R^T -------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T *__restrict__ zc, T *__restrict__ z)

@@ -155,6 +155,14 @@ def restrict_bytes(coarse_rows, dtype):
     return coarse_rows * (SLOTS * (v + 4) + v + 3 * w)
 
 
+def restrict_after_sweep_bytes(coarse_rows, dtype, slots=8, K=1):
+    """The fused restriction after a single sweep from zero: `slots` matrix
+    slots of each injection row (8 after a forward sweep), z read once and
+    r_c written (K vectors)."""
+    v, w = vb(dtype), wb(dtype)
+    return coarse_rows * (slots * (v + 4) + 2 * K * w)
+
+
 def prolong_bytes(coarse_rows, dtype):
     return coarse_rows * 3 * wb(dtype)
 

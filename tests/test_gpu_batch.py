@@ -140,6 +140,7 @@ def test_smooth_batched(hp, dims, levels, dtype, sweep, zero):
 
 @pytest.mark.parametrize("dims,levels,sweep", [((16, 16, 16), 3, "symmetric"),
                                                ((24, 20, 16), 3, "forward"),
+                                               ((24, 20, 16), 3, "backward"),
                                                ((32, 32, 32), 4, "forward"),
                                                ((8, 8, 8), 1, "forward")])
 @pytest.mark.parametrize("dtype", [0, 1])
@@ -147,7 +148,7 @@ def test_vcycle_batched(hp, dims, levels, sweep, dtype):
     nrhs = 4
     P = problem(hp, dims, levels, sweep)
     Rh = np.stack([rnd(inputs.uniform(dims, 4000 + j), dtype) for j in range(nrhs)])
-    sw = {"forward": 0, "symmetric": 2}[sweep]
+    sw = {"forward": 0, "backward": 1, "symmetric": 2}[sweep]
     for R in widths(nrhs):
         force_tiles(hp, P, nrhs, dtype, R)
         Z = dev(np.zeros(Rh.shape), dtype)

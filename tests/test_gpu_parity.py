@@ -138,6 +138,7 @@ def test_restrict_and_prolong_every_level(hp, dims, levels, dtype):
 @pytest.mark.parametrize("dims,levels,sweep", [((16, 16, 16), 3, "symmetric"),
                                                ((16, 16, 16), 3, "forward"),
                                                ((24, 20, 16), 3, "forward"),
+                                               ((24, 20, 16), 3, "backward"),
                                                ((64, 64, 64), 4, "forward"),
                                                ((8, 8, 8), 1, "forward")])
 @pytest.mark.parametrize("dtype", [0, 1])
@@ -146,7 +147,7 @@ def test_vcycle(hp, dims, levels, sweep, dtype):
     r = rnd(inputs.uniform(dims, 700), dtype)
     z = dev(np.zeros(r.size), dtype)
     hp.vcycle(P.h, dtype, dev(r, dtype), z)
-    ref = oracle.vcycle(dims, r, levels, 1, 1, 1, {"forward": 0, "symmetric": 2}[sweep])
+    ref = oracle.vcycle(dims, r, levels, 1, 1, 1, {"forward": 0, "backward": 1, "symmetric": 2}[sweep])
     err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
     assert err <= (1e-12 if dtype == 0 else 1e-4), err
 
