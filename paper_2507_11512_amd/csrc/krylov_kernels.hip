@@ -280,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(i64 M, const T *__restrict__ Q,
     if (e >= M) return;
     double v = 0.0;
 #pragma unroll 8
-    for (int j = 0; j < kk; ++j) v += cj[j * K] * (double)Q[(i64)j * ldq + e];
+    for (int j = 0; j < kk; ++j) v += cj[j * K] * (double)ld_stream(Q + (i64)j * ldq + e);
     u[e] = (T)v;
 }
 
