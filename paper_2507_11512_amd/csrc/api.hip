@@ -197,7 +197,7 @@ i64 krylov_ldq(i64 N)
     const char *e = std::getenv("HPGMX_LDQ_PAD");
     if (e && *e) {
         const long v = std::atol(e);
-        if (v >= 0 && v <= (1 << 20)) pad = v;
+        if (v >= 0 && v <= (1 << 20)) pad = (v + 1) & ~1L;  // even: columns stay 8-byte aligned
     }
     return (N + 63) / 64 * 64 + pad;
 }

@@ -333,10 +333,20 @@ template <typename F> static void with_k(int K, F &&f)
     }
 }
 
+// The FP32 single-solve passes load element pairs (pair_lanes): columns must
+// start on 8-byte boundaries.
+static void check_pair_layout(Prec p, const void *Q, i64 ldq, const void *w)
+{
+    if (p == P64) return;
+    if ((ldq & 1) || ((uintptr_t)Q & 7) || ((uintptr_t)w & 7))
+        throw std::runtime_error("Krylov basis columns must start on 8-byte boundaries");
+}
+
 void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
                 Ctrl *ctrl, hipStream_t s)
 {
     if (K > 1) return batch_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
+    check_pair_layout(p, Q, ldq, w);
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
@@ -357,6 +367,7 @@ void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *
                     Ctrl *ctrl, hipStream_t s)
 {
     if (K > 1) return batch_cgs_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
+    check_pair_layout(p, Q, ldq, w);
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
@@ -377,6 +388,7 @@ void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void 
                      Ctrl *ctrl, int k, int m, hipStream_t s)
 {
     if (K > 1) return batch_cgs_norm(M, K, p, Q, ldq, kb, w, partials, ctrl, k, m, s);
+    check_pair_layout(p, Q, ldq, w);
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
