@@ -54,17 +54,36 @@ __device__ __forceinline__ void stage_coefs(double *c, const Ctrl *ctrl, int kb,
 // a streaming read run about 11 % faster on MI355X.
 __device__ __forceinline__ i64 col_off(int j, int kb, i64 ldq) { return (i64)(j < kb ? j : kb - 1) * ldq; }
 
-// The single FP32 solve (K = 1) runs the passes with two consecutive elements
-// per lane (8-byte loads, about 5 % faster than 4-byte ones on a 30-column
-// pass); the basis columns start at even offsets (even leading dimension),
-// and an odd length leaves its last element to lane 0 of workgroup 0.
-// Batches keep one element per lane, so that a lane stays on one
-// right-hand side.
+// FP32 passes take two consecutive elements per lane (8-byte loads, about
+// 5 % faster than 4-byte ones on a 30-column pass).  For K = 1 both belong
+// to the one right-hand side; for K >= 2 (K even, entries interleaved) they
+// are right-hand sides 2g and 2g + 1 with g = lane % (K / 2), so a lane keeps
+// two sets of accumulators.  The update pass (one accumulator per
+// right-hand side) does so for every K; the two GEMVT passes (kb
+// accumulators per right-hand side) only for K = 1: twice kb FP64
+// accumulators leave one or two wavefronts per SIMD, and the batched passes
+// gained nothing.  Basis columns start at even offsets (even leading
+// dimension); an odd length (K = 1 only) leaves its last element to lane 0
+// of workgroup 0.  FP64 passes keep one element per lane.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-template <typename T, int K> constexpr bool pair_lanes() { return K == 1 && sizeof(T) == 4; }
+template <typename T, int K, bool PER_COLUMN> constexpr bool pair_lanes()
+{
+    return sizeof(T) == 4 && (K == 1 || !PER_COLUMN);
+}
+template <int K> constexpr int rhs_per_lane() { return K == 1 ? 1 : 2; }
+// First right-hand side of the lane's pair.
+template <int K> __device__ __forceinline__ int pair_rhs0() { return K == 1 ? 0 : 2 * (int)(threadIdx.x % (K / 2)); }
 template <typename T> __device__ __forceinline__ f32x2 ld_pair(const T *col, i64 pe)
 {
     return __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(col) + pe);
+}
+// Partial sums of a pair-lane pass: accumulator a = NR i + r holds
+// coefficient i of right-hand side pair_rhs0 + r (column i K + j).
+template <int NA, int K>
+__device__ __forceinline__ void store_pair_partials(const double (&acc)[NA], int na, double *partials)
+{
+    if constexpr (K == 1) store_partials_g<NA, 1, 1>(acc, na, partials);
+    else store_partials_g<NA, K / 2, 2>(acc, na, partials);
 }
 
 // ---- h1 = Q_{1:kb}^T w per right-hand side (the first GEMVT of a batch, whose
@@ -73,12 +92,12 @@ template <typename T, int KB, int K>
 __global__ __launch_bounds__(kBlock) void k_dot(i64 M, const T *__restrict__ Q, i64 ldq, int kb,
                                                 const T *__restrict__ w, double *partials)
 {
-    double acc[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
     const i64 stride = (i64)gridDim.x * kBlock;
     i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if constexpr (pair_lanes<T, K>()) {
+    if constexpr (pair_lanes<T, K, true>()) {  // K = 1
+        double acc[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = 0.0;
         for (; e < M / 2; e += stride) {
             f32x2 q[KB];
 #pragma unroll
@@ -88,18 +107,27 @@ __global__ __launch_bounds__(kBlock) void k_dot(i64 M, const T *__restrict__ Q, 
 #pragma unroll
             for (int j = 0; j < KB; ++j) acc[j] += (double)q[j].x * (double)x.x + (double)q[j].y * (double)x.y;
         }
-        e = (M & 1) && blockIdx.x == 0 && threadIdx.x == 0 ? M - 1 : M;
-    }
-    for (; e < M; e += stride) {
-        T q[KB];
+        if ((M & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            const double x = (double)w[M - 1];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
-        const double vd = (double)ld_stream(w + e);
-        sched_fence();
+            for (int j = 0; j < KB; ++j) acc[j] += (double)Q[col_off(j, kb, ldq) + M - 1] * x;
+        }
+        store_partials_g<KB, 1, 1>(acc, kb, partials);
+    } else {
+        double acc[KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
+        for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+        for (; e < M; e += stride) {
+            T q[KB];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
+            const double vd = (double)ld_stream(w + e);
+            sched_fence();
+#pragma unroll
+            for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * vd;
+        }
+        store_partials_g<KB, K, 1>(acc, kb, partials);
     }
-    store_partials_g<KB, K, 1>(acc, kb, partials);
 }
 
 // ---- h2 = Q^T (w - Q h1) (the reorthogonalisation GEMV and GEMVT) ----
@@ -114,13 +142,12 @@ __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 M, const T *__restrict__
 {
     __shared__ double c[KB * K];
     stage_coefs<KB, K>(c, ctrl, kb, kCoefH1);
-    const double *cj = c + rhs_of_thread<K>();
-    double acc[KB];
-#pragma unroll
-    for (int j = 0; j < KB; ++j) acc[j] = 0.0;
     const i64 stride = (i64)gridDim.x * kBlock;
     i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if constexpr (pair_lanes<T, K>()) {
+    if constexpr (pair_lanes<T, K, true>()) {  // K = 1
+        double acc[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = 0.0;
         for (; e < M / 2; e += stride) {
             f32x2 q[KB];
 #pragma unroll
@@ -130,26 +157,38 @@ __global__ __launch_bounds__(kBlock) void k_cgs_dot(i64 M, const T *__restrict__
             double v0 = (double)x.x, v1 = (double)x.y;
 #pragma unroll
             for (int j = 0; j < KB; ++j) {
-                v0 -= cj[j * K] * (double)q[j].x;
-                v1 -= cj[j * K] * (double)q[j].y;
+                v0 -= c[j] * (double)q[j].x;
+                v1 -= c[j] * (double)q[j].y;
             }
 #pragma unroll
             for (int j = 0; j < KB; ++j) acc[j] += (double)q[j].x * v0 + (double)q[j].y * v1;
         }
-        e = (M & 1) && blockIdx.x == 0 && threadIdx.x == 0 ? M - 1 : M;
+        if ((M & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            double v = (double)w[M - 1];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) v -= c[j] * (double)Q[col_off(j, kb, ldq) + M - 1];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) acc[j] += (double)Q[col_off(j, kb, ldq) + M - 1] * v;
+        }
+        store_partials_g<KB, 1, 1>(acc, kb, partials);
+    } else {
+        const double *cj = c + rhs_of_thread<K>();
+        double acc[KB];
+#pragma unroll
+        for (int j = 0; j < KB; ++j) acc[j] = 0.0;
+        for (; e < M; e += stride) {
+            T q[KB];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
+            double v = (double)ld_stream(w + e);
+            sched_fence();
+#pragma unroll
+            for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
+#pragma unroll
+            for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * v;
+        }
+        store_partials_g<KB, K, 1>(acc, kb, partials);
     }
-    for (; e < M; e += stride) {
-        T q[KB];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
-        double v = (double)ld_stream(w + e);
-        sched_fence();
-#pragma unroll
-        for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
-#pragma unroll
-        for (int j = 0; j < KB; ++j) acc[j] += (double)q[j] * v;
-    }
-    store_partials_g<KB, K, 1>(acc, kb, partials);
 }
 
 // ---- w -= Q (h1 + h2) fused with ||w||^2, then the Givens step ----------------------------
@@ -160,11 +199,14 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict_
 {
     __shared__ double c[KB * K];
     stage_coefs<KB, K>(c, ctrl, kb, kCoefH12);
-    const double *cj = c + rhs_of_thread<K>();
-    double acc[1] = {0.0};
     const i64 stride = (i64)gridDim.x * kBlock;
     i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if constexpr (pair_lanes<T, K>()) {
+    if constexpr (pair_lanes<T, K, false>()) {
+        constexpr int NR = rhs_per_lane<K>();
+        const double *c0 = c + pair_rhs0<K>(), *c1 = c0 + (NR - 1);
+        double acc[NR];
+#pragma unroll
+        for (int a = 0; a < NR; ++a) acc[a] = 0.0;
         for (; e < M / 2; e += stride) {
             f32x2 q[KB];
 #pragma unroll
@@ -174,30 +216,42 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict_
             double v0 = (double)x.x, v1 = (double)x.y;
 #pragma unroll
             for (int j = 0; j < KB; ++j) {
-                v0 -= cj[j * K] * (double)q[j].x;
-                v1 -= cj[j * K] * (double)q[j].y;
+                v0 -= c0[j * K] * (double)q[j].x;
+                v1 -= c1[j * K] * (double)q[j].y;
             }
             f32x2 o;
             o.x = (float)v0;
             o.y = (float)v1;
             __builtin_nontemporal_store(o, reinterpret_cast<f32x2 *>(w) + e);
-            acc[0] += (double)o.x * (double)o.x + (double)o.y * (double)o.y;
+            acc[0] += (double)o.x * (double)o.x;
+            acc[NR - 1] += (double)o.y * (double)o.y;
         }
-        e = (M & 1) && blockIdx.x == 0 && threadIdx.x == 0 ? M - 1 : M;
-    }
-    for (; e < M; e += stride) {
-        T q[KB];
+        if (K == 1 && (M & 1) && blockIdx.x == 0 && threadIdx.x == 0) {
+            double v = (double)w[M - 1];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
-        double v = (double)ld_stream(w + e);
-        sched_fence();
+            for (int j = 0; j < KB; ++j) v -= c0[j * K] * (double)Q[col_off(j, kb, ldq) + M - 1];
+            const T vt = (T)v;
+            w[M - 1] = vt;
+            acc[0] += (double)vt * (double)vt;
+        }
+        store_pair_partials<NR, K>(acc, NR, partials);
+    } else {
+        const double *cj = c + rhs_of_thread<K>();
+        double acc[1] = {0.0};
+        for (; e < M; e += stride) {
+            T q[KB];
 #pragma unroll
-        for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
-        const T vt = (T)v;
-        w[e] = vt;
-        acc[0] += (double)vt * (double)vt;
+            for (int j = 0; j < KB; ++j) q[j] = ld_stream(Q + col_off(j, kb, ldq) + e);
+            double v = (double)ld_stream(w + e);
+            sched_fence();
+#pragma unroll
+            for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
+            const T vt = (T)v;
+            w[e] = vt;
+            acc[0] += (double)vt * (double)vt;
+        }
+        store_partials_g<1, K, 1>(acc, 1, partials);
     }
-    store_partials_g<1, K, 1>(acc, 1, partials);
 }
 
 // Batched instances (K = 2, 4, 8) of the Krylov passes, compiled in

@@ -333,8 +333,8 @@ template <typename F> static void with_k(int K, F &&f)
     }
 }
 
-// The FP32 single-solve passes load element pairs (pair_lanes): columns must
-// start on 8-byte boundaries.
+// The FP32 passes load element pairs (pair_lanes): columns must start on
+// 8-byte boundaries.
 static void check_pair_layout(Prec p, const void *Q, i64 ldq, const void *w)
 {
     if (p == P64) return;
@@ -345,8 +345,8 @@ static void check_pair_layout(Prec p, const void *Q, i64 ldq, const void *w)
 void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
                 Ctrl *ctrl, hipStream_t s)
 {
-    if (K > 1) return batch_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
     check_pair_layout(p, Q, ldq, w);
+    if (K > 1) return batch_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
@@ -366,8 +366,8 @@ void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void
 void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                     Ctrl *ctrl, hipStream_t s)
 {
-    if (K > 1) return batch_cgs_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
     check_pair_layout(p, Q, ldq, w);
+    if (K > 1) return batch_cgs_dot(M, K, p, Q, ldq, kb, w, partials, ctrl, s);
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
@@ -387,8 +387,8 @@ void launch_cgs_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *
 void launch_cgs_norm(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, void *w, double *partials,
                      Ctrl *ctrl, int k, int m, hipStream_t s)
 {
-    if (K > 1) return batch_cgs_norm(M, K, p, Q, ldq, kb, w, partials, ctrl, k, m, s);
     check_pair_layout(p, Q, ldq, w);
+    if (K > 1) return batch_cgs_norm(M, K, p, Q, ldq, kb, w, partials, ctrl, k, m, s);
     const dim3 gr(red_blocks(M)), bl(kBlock);
     if (p == P64) {
 #define HPGMX_KB_BODY \
