@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=320, help="grid edge (the workload is n^3)")
     ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--beta", type=float, default=0.5,
+                    help="nonsymmetry of the stencil's x-neighbour entries (0: the symmetric member)")
     ap.add_argument("--iters", type=int, default=300, help="inner steps per timed solve")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--cpu-iters", type=int, default=30, help="inner steps of the CPU-oracle sample (30: one restart cycle)")
@@ -210,7 +212,7 @@ def main():
     N = n ** 3
     log(f"setup {n}^3 levels={L} (device: {torch.cuda.get_device_name(0)})")
     t = time.time()
-    P = hp.Problem(n, beta=0.5, levels=L, sweep="forward")
+    P = hp.Problem(n, beta=args.beta, levels=L, sweep="forward")
     b = P.rhs_from_x(torch.ones(N, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     log(f"setup done in {time.time() - t:.2f}s")
@@ -291,9 +293,10 @@ def main():
     cpu = None
     if not args.no_cpu:
         import oracle
-        bh = oracle.spmv(n, np.ones(N))
+        bh = oracle.spmv(n, np.ones(N), beta=args.beta)
         t0 = time.perf_counter()
-        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0)
+        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0,
+                                 beta=args.beta)
         dt = time.perf_counter() - t0
         cflops = pm.solve_flops(cfg, [args.cpu_iters])
         cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
@@ -307,7 +310,7 @@ def main():
     if args.report:
         write_report(args.report, driver,
                      {"grid": f"{n} x {n} x {n} ({N} unknowns)",
-                      "operator": "27-point nonsymmetric stencil, beta = 0.5, Dirichlet-truncated",
+                      "operator": f"27-point stencil, beta = {args.beta:g}, Dirichlet-truncated",
                       "solver": f"GMRES({m})-IR, {args.inner} inner / fp64 outer; {L}-level V-cycle, "
                                 "forward multicolour Gauss-Seidel 1/1/1",
                       "inner steps per timed solve": args.iters,
@@ -328,7 +331,7 @@ def main():
         "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)"}[args.inner]
                  + "-inner/f64-outer",
         "data": "synthetic: generated 27-point stencil, b = A*1, x0 = 0",
-        "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta=0.5, GMRES({m})-IR ({args.inner} inner), {L}-level "
+        "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta={args.beta:g}, GMRES({m})-IR ({args.inner} inner), {L}-level "
                                f"V-cycle fwd multicolour GS 1/1/1, {args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L,
                    "iters_per_solve": args.iters,
@@ -409,7 +412,7 @@ def run_batched(args, hp, pm, torch, np):
     from paper_2507_11512_amd import inputs
     log(f"setup {n}^3 levels={L}, {k} right-hand sides (device: {torch.cuda.get_device_name(0)})")
     t = time.time()
-    P = hp.Problem(n, beta=0.5, levels=L, sweep="forward")
+    P = hp.Problem(n, beta=args.beta, levels=L, sweep="forward")
     U_ = torch.stack([torch.from_numpy(inputs.batch_u((n, n, n), j)) for j in range(k)]).cuda()
     B = torch.empty_like(U_)
     for j in range(k):
@@ -491,7 +494,8 @@ def run_batched(args, hp, pm, torch, np):
         import oracle
         bh = B[0].cpu().numpy()
         t0 = time.perf_counter()
-        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0)
+        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0,
+                                 beta=args.beta)
         dt = time.perf_counter() - t0
         cflops = pm.solve_flops(cfg, [args.cpu_iters])
         cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
@@ -515,7 +519,7 @@ def run_batched(args, hp, pm, torch, np):
         "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)"}[args.inner]
                  + "-inner/f64-outer",
         "data": f"synthetic: generated 27-point stencil, b_j = A u_j, u_j ~ N(0,1) seeded 11512+j, x0 = 0",
-        "config": {"workload": f"hpg-mxp batched {n}^3 27-pt nonsym beta=0.5, {k} right-hand sides, "
+        "config": {"workload": f"hpg-mxp batched {n}^3 27-pt nonsym beta={args.beta:g}, {k} right-hand sides, "
                                f"GMRES({m})-IR ({args.inner} inner), {L}-level V-cycle fwd multicolour GS 1/1/1, "
                                f"{args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "nrhs": k, "restart": m, "levels": L,

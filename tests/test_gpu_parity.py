@@ -343,3 +343,59 @@ def test_graph_replay_matches_eager(hp, precision, restart):
         assert torch.equal(x_g, x_e), rep
         hp.spmv(P.h, 0, 1, x_g.float(), y)      # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3])
+@pytest.mark.parametrize("dtype", [0, 1])
+def test_kernels_other_beta(hp, beta, dtype):
+    """beta = 0 is the symmetric member of the stencil family, beta = 0.3 a
+    nonsymmetric one whose entries (-1.3, -0.7) are not exact in FP32 (the
+    FP32 matrix holds their rounding; the bound allows one more rounding per
+    product).  SpMV, one sweep of each kind and a V-cycle against the oracle
+    with the same beta."""
+    dims, levels = (16, 12, 20), 3
+    print(f"[beta] beta={beta} dtype={dtype}", flush=True)
+    P = hp.Problem(dims, beta=beta, levels=levels, sweep="forward")
+    x = rnd(inputs.uniform(dims, 61), dtype)
+    y = dev(np.zeros(x.size), dtype)
+    hp.spmv(P.h, 0, dtype, dev(x, dtype), y)
+    tol = 3 * gamma(28, U[dtype]) * oracle.absrow(dims, x, beta=beta) + 1e-300
+    assert np.all(np.abs(host(y) - oracle.spmv(dims, x, beta=beta)) <= tol)
+    for sweep in (0, 1, 2):
+        r = rnd(inputs.uniform(dims, 62), dtype)
+        z0 = rnd(inputs.uniform(dims, 63), dtype)
+        zt = dev(z0, dtype)
+        hp.smooth(P.h, 0, dtype, sweep, dev(r, dtype), zt)
+        ref = oracle.gs(dims, r, z0, sweep, beta=beta)
+        zmax = np.maximum(np.abs(z0), np.abs(ref))
+        S = (np.abs(r) + oracle.absrow(dims, zmax, beta=beta) - 26.0 * zmax) / 26.0
+        assert np.max(np.abs(host(zt) - ref)) <= 3 * (16 if sweep == 2 else 8) * gamma(28, U[dtype]) * S.max()
+    r = rnd(inputs.uniform(dims, 64), dtype)
+    z = dev(np.zeros(r.size), dtype)
+    hp.vcycle(P.h, dtype, dev(r, dtype), z)
+    ref = oracle.vcycle(dims, r, levels, 1, 1, 1, 0, beta=beta)
+    assert np.linalg.norm(host(z) - ref) / np.linalg.norm(ref) <= (1e-12 if dtype == 0 else 1e-4)
+    P.close()
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.3])
+@pytest.mark.parametrize("precision", ["fp64", "mxp"])
+def test_solve_other_beta(hp, beta, precision):
+    """The solve bar for b = A 1 with other members of the stencil family:
+    residual <= 1e-9 against the oracle's matrix, x within 1e-8 of the
+    oracle's solution, FP64 iteration counts within 2 of the oracle's."""
+    dims, levels = (24, 24, 24), 3
+    P = hp.Problem(dims, beta=beta, levels=levels, sweep="forward")
+    b = oracle.spmv(dims, inputs.ones(dims), beta=beta)
+    x, st = P.solve(dev(b, 0), tol=1e-9, precision=precision)
+    xh = host(x)
+    xo, sto = oracle.gmres_ir(dims, b, levels=levels, sweep=0, tol=1e-9, beta=beta,
+                              f32=(precision != "fp64"))
+    res = np.linalg.norm(b - oracle.spmv(dims, xh, beta=beta)) / np.linalg.norm(b)
+    dx = np.linalg.norm(xh - xo) / np.linalg.norm(xo)
+    print(f"[beta solve] beta={beta} {precision} iters={st.iters} oracle={sto.iters} res={res:.2e} dx={dx:.2e}",
+          flush=True)
+    assert st.converged and res <= 1e-9 and dx <= 1e-8
+    if precision == "fp64":
+        assert abs(st.iters - sto.iters) <= 2
+    P.close()
