@@ -147,6 +147,28 @@ def test_fused_restriction_equals_unfused(oracle_mod, d):
     assert np.allclose(fused, refimpl.injection_matrix(d) @ (r - K @ z), rtol=0, atol=1e-13)
 
 
+@pytest.mark.parametrize("forward", [True, False])
+def test_restriction_after_a_zero_guess_sweep(oracle_mod, forward):
+    """The identity behind the GPU's restriction after the pre-smoother: once
+    one sweep from z = 0 has relaxed every colour, the residual at an
+    injection point (colour 4) is minus its couplings to the colours relaxed
+    after colour 4 (5, 6, 7 forward; 0..3 backward), since relaxing colour 4
+    zeroed the residual there while those colours were still zero."""
+    d = (16, 12, 8)
+    r = inputs.uniform(d, 36)
+    z = oracle_mod.gs(d, r, np.zeros(r.size), 0 if forward else 1)
+    nx, ny, nz = d
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    col = np.vectorize(oracle_mod.color)(i, j, k).ravel()
+    later = col > 4 if forward else col < 4
+    w = np.where(later, z, 0.0)
+    fused = oracle_mod.restrict_fused(d, r, z)
+    short = -oracle_mod.inject(d, oracle_mod.spmv(d, w))
+    scale = oracle_mod.inject(d, np.abs(r) + oracle_mod.absrow(d, z))
+    assert np.all(np.abs(fused - short) <= 1e-14 * scale)
+    assert np.max(np.abs(fused)) > 1e-3 * np.max(scale)   # not the trivial identity 0 = 0
+
+
 # ------------------------------------------------------------------ V-cycle --
 @pytest.mark.parametrize("d,levels", [((8, 8, 8), 1), ((8, 8, 8), 2), ((16, 16, 16), 3),
                                       ((8, 12, 16), 3), ((16, 16, 16), 4)])
