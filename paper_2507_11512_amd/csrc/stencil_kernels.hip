@@ -9,16 +9,32 @@
 
 #include <cstdlib>
 #include <stdexcept>
+#include <type_traits>
 
 namespace hpgmx {
 
-int xcd_remap_enabled()
+// HPGMX_XCD_REMAP (layout studies): 0 = no remapping, 1 = XCD-contiguous
+// tiles only, 2 (default) = also the slab order where it is used.
+static int xcd_remap_mode()
 {
-    static const int on = [] {
+    static const int mode = [] {
         const char *e = std::getenv("HPGMX_XCD_REMAP");
-        return (e && *e) ? (std::atoi(e) != 0) : 1;
+        if (!(e && *e)) return 2;
+        const int v = std::atoi(e);
+        return v < 0 ? 0 : v > 2 ? 2 : v;
     }();
-    return on;
+    return mode;
+}
+
+int xcd_remap_enabled() { return xcd_remap_mode() != 0 ? 1 : 0; }
+
+int full_grid_order(const Geom &g, int lanes)
+{
+    if (xcd_remap_mode() < 2) return xcd_remap_enabled();
+    const i64 lanes_total = g.N * lanes;
+    const bool even = g.nx % 2 == 0 && g.ny % 2 == 0 && g.nz % 2 == 0;
+    const bool whole = lanes_total % ((i64)kBlock * kXcds * kXcds) == 0;
+    return even && whole ? kRemapSlab : 1;
 }
 
 // ---- geometry -----------------------------------------------------------------
@@ -162,7 +178,7 @@ static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void 
 {
     using T = typename VecT<V>::T;
     hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2,
-                       xcd_remap_enabled(), v, A.col, d,
+                       std::is_same<V, double>::value ? xcd_remap_enabled() : full_grid_order(A.g, 1), v, A.col, d,
                        (const T *)x, (T *)y, scale);
     HPGMX_LAUNCH_CHECK();
 }
