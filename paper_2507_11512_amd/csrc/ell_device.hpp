@@ -88,18 +88,18 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int remap)
 // Slab order for the SpMV over all rows of every colour (remap ==
 // kRemapSlab).  In the XCD-contiguous order XCD x owns tiles
 // [x T/8, (x+1) T/8), which is colour block x when the eight blocks are
-// equal, so every XCD gathers neighbours from all of the vector.  In the slab
-// order XCD x owns the x-th eighth of every colour block instead (a slab of
-// k-planes), and the neighbours its rows gather lie in the same slab of the
-// other blocks: each XCD's L2 fetches about 1/8 of the vector instead of all
-// of it.  slab_perm maps a tile of the XCD-contiguous order to its tile in
-// the slab order; it is a permutation of [0, T) when T is a multiple of 64
-// and each colour block holds T/8 tiles, which the host checks
-// (full_grid_order).  Measured on the single-vector SpMV at 320^3 with
-// FP32 and 16-bit values: 6030 -> 6260 GB/s; the FP64 SpMV, the batched
-// SpMV and the FP64 residuals ran 1-4 % slower in this order (their gathers
-// are wider), so they keep the XCD-contiguous order; the per-colour kernels
-// are slab-local already.
+// equal: at any moment all eight XCDs work at the same spatial position of
+// their blocks and gather the same neighbourhood of the vector.  In the slab
+// order XCD x owns the x-th eighth of every colour block (a slab of
+// k-planes), so the XCDs work on eight different slabs and spread their
+// gathers over the vector.  The L2-to-fabric byte counters read the same in
+// both orders (a slab does not fit an XCD's L2); the time does not: the FP32
+// and 16-bit SpMV at 320^3 runs 6030 -> 6260 GB/s, while the FP64 SpMV, the
+// batched SpMV and the FP64 residuals ran 1-4 % slower and keep the
+// XCD-contiguous order; the per-colour kernels are unaffected.  slab_perm
+// maps a tile of the XCD-contiguous order to its tile in the slab order; it
+// is a permutation of [0, T) when T is a multiple of 64 and each colour block
+// holds T/8 tiles, which the host checks (full_grid_order).
 constexpr int kRemapSlab = 2;
 __device__ __forceinline__ i64 slab_perm(i64 t, i64 T)
 {
