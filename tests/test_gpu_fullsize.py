@@ -313,3 +313,51 @@ def test_largest_grid_512_sampled(hp):
         assert st.iters == 30 and 0.0 < st.final_rel_res < 1.0
     finally:
         P.close()
+
+
+def test_adjoint_192_batched(hp):
+    """The batched + adjoint configuration at its full size: 192^3, k = 8
+    right-hand sides b_j = A u_j, loss L = sum_j g_j . x_j with
+    g_j ~ N(0, 1), mixed-precision forward and adjoint solves to 1e-9.
+    Checked at full size by properties the oracle computes: each adjoint
+    solution lam_j = dL/db_j solves A^T lam_j = g_j (A^T is the stencil at
+    -beta, applied by the oracle) to the solve bar, and dL/dtheta equals
+    minus the oracle's stencil correlation of the GPU's (lam_j, x_j), summed
+    over j, within the FP64 summation bound."""
+    import time
+    import torch
+    from paper_2507_11512_amd.autograd import StencilSolver
+    d = (192, 192, 192)
+    k = 8
+    th = oracle.stencil_from_beta(0.5)
+    U_ = np.stack([inputs.batch_u(d, j) for j in range(k)])
+    G = np.stack([inputs.normal(d, 11612 + j) for j in range(k)])
+    solver = StencilSolver(d, levels=4, tol=1e-9, precision="mxp")
+    try:
+        fwd, _ = solver.problems(torch.from_numpy(th))
+        Ut = torch.from_numpy(U_).cuda()
+        B = torch.empty_like(Ut)
+        for j in range(k):
+            hp.rhs_from_x(fwd.h, Ut[j], B[j])
+        bt = B.clone().requires_grad_(True)
+        tt = torch.from_numpy(th).cuda().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X = solver(bt, tt)
+        L = (torch.from_numpy(G).cuda() * X).sum()
+        L.backward()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        Xh, lam, gt = host(X.detach()), bt.grad.cpu().numpy(), tt.grad.cpu().numpy()
+        print(f"[adjoint 192^3 x 8] forward + adjoint solves + gradient: {dt:.2f} s", flush=True)
+        corr = np.zeros(27)
+        scale = np.zeros(27)
+        for j in range(k):
+            assert np.linalg.norm(Xh[j] - U_[j]) <= 1e-7 * np.linalg.norm(U_[j])
+            resT = np.linalg.norm(G[j] - oracle.spmv(d, lam[j], beta=-0.5)) / np.linalg.norm(G[j])
+            assert resT <= 1e-9, (j, resT)
+            corr += oracle.stencil_correlation(d, lam[j], Xh[j])
+            scale += oracle.stencil_correlation(d, np.abs(lam[j]), np.abs(Xh[j]))
+        assert np.all(np.abs(gt + corr) <= 2 * 192 ** 3 * U64 * scale)
+    finally:
+        solver.close()
