@@ -13,8 +13,8 @@
  * the memory wall using mixed-precision - HPG-MxP on an exascale machine",
  * SC'25, arXiv 2507.11512).
  *
- * Readings taken where the paper is silent or garbled are listed in
- * the design doc; each is restated at the point of use below.
+ * Readings taken where the paper is silent or garbled are restated at the
+ * point of use below.
  *
  * Parity status: every exported function is pinned by a test in
  * tests/test_oracle_pins.py against an independent construction (Kronecker
