@@ -280,8 +280,12 @@ void or_restrict_fused(int nx, int ny, int nz, double beta, int fo,
 /* FP32 storage emulation.  With f32 set, every vector element that the      */
 /* mixed-precision method keeps in low precision (Alg. 3, steps in blue) is  */
 /* rounded to binary32 (round to nearest even) when stored; arithmetic stays */
-/* in binary64.  This gives an iteration-count reference for the mixed-      */
-/* precision solver; it is not used to pin anything.                        */
+/* in binary64.  Stored in binary32: q_1, the multigrid work vectors after   */
+/* every sweep, restriction and correction, z = M^{-1} q_k, w = A z, each    */
+/* Gram-Schmidt update, q_{k+1} and the end-of-cycle u = Q y.  Inner         */
+/* products, H, the rotations and x stay binary64.  Pinned by rebuilding    */
+/* each stored quantity of a cycle from independent pieces with the same     */
+/* rounding (tests/test_oracle_pins.py, "binary32 storage").                */
 /* ------------------------------------------------------------------------- */
 static inline double st(double v, int f32) { return f32 ? (double)(float)v : v; }
 

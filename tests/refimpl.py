@@ -78,24 +78,39 @@ def gs_triangular(A, perm, r, z, sweep):
     return out
 
 
-def vcycle_ref(d, r, levels, pre=1, post=1, coarsest=1, sweep=0, beta=0.5, faces_only=False):
+def keep(v):
+    return v
+
+
+def fl32(v):
+    """Round to the nearest binary32 (ties to even) and widen back: numpy's
+    float64 -> float32 conversion is the IEEE one."""
+    return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def vcycle_ref(d, r, levels, pre=1, post=1, coarsest=1, sweep=0, beta=0.5, faces_only=False,
+               store=keep):
+    """The V-cycle composed from the pieces above.  `store` is applied to
+    every vector the cycle keeps (after each sweep, the restricted residual,
+    the corrected z): identity for the FP64 method, fl32 for binary32
+    storage of the multigrid work vectors."""
     d = dims3(d)
     A = kron_matrix(d, beta, faces_only)
     perm = colour_perm(d)
     z = np.zeros(A.shape[0])
     if levels == 1:
         for _ in range(coarsest):
-            z = gs_triangular(A, perm, r, z, sweep)
+            z = store(gs_triangular(A, perm, r, z, sweep))
         return z
     for _ in range(pre):
-        z = gs_triangular(A, perm, r, z, sweep)
+        z = store(gs_triangular(A, perm, r, z, sweep))
     R = injection_matrix(d)
-    rc = R @ (r - A @ z)
+    rc = store(R @ (r - A @ z))
     zc = vcycle_ref((d[0] // 2, d[1] // 2, d[2] // 2), rc, levels - 1, pre, post, coarsest,
-                    sweep, beta, faces_only)
-    z = z + R.T @ zc
+                    sweep, beta, faces_only, store)
+    z = store(z + R.T @ zc)
     for _ in range(post):
-        z = gs_triangular(A, perm, r, z, sweep)
+        z = store(gs_triangular(A, perm, r, z, sweep))
     return z
 
 

@@ -181,15 +181,14 @@ def test_solve_batched_matches_oracle(hp, dims, levels, sweep, nrhs, precision):
     so the x parity pair is solved to 1e-11, where both reach FP64 accuracy."""
     P = problem(hp, dims, levels, sweep)
     sw = {"forward": 0, "symmetric": 2}[sweep]
-    f32 = precision != "fp64"
     U_, B = _batch_rhs(dims, nrhs)
     X, stats = P.solve_batched(dev(B, 0), tol=1e-9, precision=precision)
     X11, stats11 = P.solve_batched(dev(B, 0), tol=1e-11, precision=precision)
     Xh, X11h = host(X), host(X11)
     for j in range(nrhs):
         st = stats[j]
-        xo, sto = oracle.gmres_ir(dims, B[j], levels=levels, sweep=sw, tol=1e-9, f32=f32)
-        xo11, _ = oracle.gmres_ir(dims, B[j], levels=levels, sweep=sw, tol=1e-11, f32=f32)
+        xo, sto = oracle.gmres_ir(dims, B[j], levels=levels, sweep=sw, tol=1e-9)
+        xo11, _ = oracle.gmres_ir(dims, B[j], levels=levels, sweep=sw, tol=1e-11)
         res = np.linalg.norm(B[j] - oracle.spmv(dims, Xh[j])) / np.linalg.norm(B[j])
         dx9 = np.linalg.norm(Xh[j] - xo) / np.linalg.norm(xo)
         dx = np.linalg.norm(X11h[j] - xo11) / np.linalg.norm(xo11)

@@ -289,6 +289,98 @@ def test_restarts_and_fp32_emulation(oracle_mod):
     assert np.linalg.norm(x32 - 1) / np.sqrt(x32.size) < 1e-8
 
 
+# ------------------------------------------ binary32 storage (the f32 mode) --
+# The mixed-precision method keeps the low-precision quantities of Alg. 3 (the
+# multigrid work vectors, the preconditioned vector, the SpMV output, the
+# Gram-Schmidt updates and the basis) in binary32 while every inner product,
+# the Hessenberg matrix and the rotations stay binary64.  The oracle's f32
+# mode emulates that by rounding each stored vector to binary32.  These pins
+# rebuild every stored quantity of a cycle from independent pieces (the
+# Kronecker operator, triangular-solve Gauss-Seidel, explicit injection,
+# numpy inner products) with the same binary32 storage, and compare.  Two
+# binary64 evaluations in different summation orders can still round a value
+# that lies within ~1e-16 of a binary32 rounding boundary to different
+# neighbours, so the element-wise checks allow a few one-ulp differences;
+# a missing or misplaced rounding changes a large fraction of the elements.
+
+def _ulp32(v):
+    return np.spacing(np.abs(v).astype(np.float32)).astype(np.float64)
+
+
+def _assert_same_binary32(got, ref, max_frac=0.01):
+    assert np.array_equal(got, refimpl.fl32(got)), "not binary32-representable"
+    diff = np.abs(got - ref)
+    assert np.all(diff <= 2 * _ulp32(ref) + 1e-300), np.max(diff / (_ulp32(ref) + 1e-300))
+    assert np.count_nonzero(diff) <= max(2, max_frac * got.size), np.count_nonzero(diff)
+
+
+@pytest.mark.parametrize("d,levels,sweep", [((8, 8, 8), 3, 0), ((8, 12, 16), 3, 2), ((16, 16, 16), 4, 0)])
+def test_fp32_storage_vcycle_equals_composed_reference(oracle_mod, d, levels, sweep):
+    r = refimpl.fl32(inputs.uniform(d, 45))
+    got = oracle_mod.vcycle(d, r, levels, 1, 1, 1, sweep, f32=True)
+    ref = refimpl.vcycle_ref(d, r, levels, 1, 1, 1, sweep, store=refimpl.fl32)
+    _assert_same_binary32(got, ref)
+    # the storage rounding is visible: the FP64 cycle differs at the binary32 level
+    full = oracle_mod.vcycle(d, r, levels, 1, 1, 1, sweep)
+    assert np.count_nonzero(got != refimpl.fl32(full)) > 0.05 * got.size
+
+
+@pytest.mark.parametrize("d,levels,sweep", [((8, 8, 8), 3, 0), ((6, 8, 10), 2, 2)])
+def test_fp32_storage_arnoldi_steps(oracle_mod, d, levels, sweep):
+    """Every step of the first cycle in f32 mode, rebuilt from the oracle's own
+    basis: z = M^-1 q_k (binary32 storage), w = fl32(A z), two classical
+    Gram-Schmidt passes each stored in binary32, beta = ||w||,
+    q_{k+1} = fl32(w / beta); and the Arnoldi relation holds only to the
+    binary32 level."""
+    m = 6
+    b = inputs.uniform(d, 55)
+    _, st, cyc = oracle_mod.gmres_ir(d, b, levels=levels, sweep=sweep, restart=m, max_iters=m, tol=0.0,
+                                     f32=True, want_first_cycle=True)
+    k, Q, Hbar = cyc["k"], cyc["Q"], cyc["Hbar"]
+    assert k == m
+    K = refimpl.kron_matrix(d, 0.5)
+    fl = refimpl.fl32
+    _assert_same_binary32(Q[:, 0], fl(b / np.linalg.norm(b)), max_frac=0.0)
+    for j in range(k):
+        Qj = Q[:, :j + 1]
+        z = refimpl.vcycle_ref(d, Q[:, j], levels, 1, 1, 1, sweep, store=fl)
+        w = fl(K @ z)
+        h1 = Qj.T @ w
+        w1 = fl(w - Qj @ h1)
+        h2 = Qj.T @ w1
+        w2 = fl(w1 - Qj @ h2)
+        beta = np.linalg.norm(w2)
+        h = h1 + h2
+        assert np.linalg.norm(Hbar[:j + 1, j] - h) <= 1e-10 * np.linalg.norm(h), j
+        assert abs(Hbar[j + 1, j] - beta) <= 1e-10 * beta, j
+        assert np.all(Hbar[j + 2:, j] == 0.0)
+        _assert_same_binary32(Q[:, j + 1], fl(w2 / beta))
+    MQ = np.column_stack([refimpl.vcycle_ref(d, Q[:, j], levels, 1, 1, 1, sweep, store=fl) for j in range(k)])
+    rel = np.linalg.norm(K @ MQ - Q @ Hbar) / np.linalg.norm(Hbar)
+    assert 1e-12 < rel <= 1e-5, rel
+    orth = np.linalg.norm(Q.T @ Q - np.eye(k + 1))
+    assert 1e-12 < orth <= 1e-5, orth
+
+
+def test_fp32_storage_end_of_cycle_update(oracle_mod):
+    """After one cycle from x0 = 0: x = fl32(M^-1 fl32(Q_k y)) with y the
+    least-squares solution of the cycle (binary32 storage of u and z, the
+    update itself in binary64)."""
+    d, levels, m = (8, 8, 8), 3, 5
+    b = inputs.uniform(d, 56)
+    x, st, cyc = oracle_mod.gmres_ir(d, b, levels=levels, restart=m, max_iters=m, tol=0.0, f32=True,
+                                     want_first_cycle=True)
+    assert st.iters == m and st.restarts == 1
+    k, Q, Hbar, y = cyc["k"], cyc["Q"], cyc["Hbar"], cyc["y"]
+    rhs = np.zeros(k + 1)
+    rhs[0] = np.linalg.norm(b)
+    ys, *_ = np.linalg.lstsq(Hbar, rhs, rcond=None)
+    assert np.linalg.norm(y - ys) <= 1e-10 * np.linalg.norm(ys)
+    u = refimpl.fl32(Q[:, :k] @ y)
+    ref = refimpl.vcycle_ref(d, u, levels, store=refimpl.fl32)
+    _assert_same_binary32(x, ref)
+
+
 def test_edge_cases(oracle_mod):
     d = (8, 8, 8)
     x, st = oracle_mod.gmres_ir(d, np.zeros(512), levels=3)
