@@ -185,6 +185,33 @@ hpgmx_status hpgmx_vcycle(hpgmx_handle h, int dtype, const void *r, void *z);
 hpgmx_status hpgmx_restrict_residual(hpgmx_handle h, int level, int dtype, const void *r,
                                      const void *z, void *r_coarse);
 
+/* The first half of one V-cycle level exactly as the V-cycle runs it
+ * (Sec. 2 Fig. 1, Sec. 3.2): z <- nsweeps Gauss-Seidel sweeps of kind
+ * `sweep` from z = 0 on `level`, then r_coarse = R (r - A_level z), the fused
+ * residual-restriction of eq. (6).  After a single forward or backward sweep
+ * the restriction takes the V-cycle's shortcut: relaxing the injection
+ * colour (colour 4) left r - A z = 0 on its rows while the colours relaxed
+ * after it were still zero, so r - A z at an injection point is minus its
+ * couplings to those colours (8 slots forward, 18 backward; equal to eq. (6)
+ * in exact arithmetic).  Otherwise eq. (6) is evaluated in full.  r: input on
+ * `level`; z: output on `level`; r_coarse: output on level + 1 (level <
+ * levels - 1); 0 <= nsweeps <= 16.  Stream-ordered. */
+hpgmx_status hpgmx_presmooth_restrict(hpgmx_handle h, int level, int dtype, int sweep, int nsweeps,
+                                      const void *r, void *z, void *r_coarse);
+
+/* Test export of the Krylov state of Alg. 3: the last restart cycle of the
+ * last hpgmx_gmres_ir_solve run with inner dtype `dtype`.  *k = inner steps
+ * that cycle took.  Q (device, FP64, (k+1) vectors of N entries one after
+ * the other, natural order): the stored basis columns; basis vector
+ * q_j = scale[j] * Q[j] (the library stores the columns unnormalised, with
+ * their scale).  scale (host, k+1 doubles).  Hbar (host, FP64, (k+1) x k
+ * column-major, leading dimension k+1): the Hessenberg matrix before the
+ * Givens rotations, in the basis q_j.  y (host, k doubles): the projected
+ * solution of the cycle, y = H^{-1} t.  Any of Q, scale, Hbar, y may be NULL.
+ * Blocks.  ESTATE if no such solve has run. */
+hpgmx_status hpgmx_krylov_cycle_get(hpgmx_handle h, int dtype, int *k, double *Q, double *scale, double *Hbar,
+                                    double *y);
+
 /* z += P z_coarse with P = R^T (eq. (3)): z on `level`, z_coarse on
  * level + 1. */
 hpgmx_status hpgmx_prolong_add(hpgmx_handle h, int level, int dtype, const void *z_coarse,
@@ -280,6 +307,11 @@ hpgmx_status hpgmx_spmv_batched(hpgmx_handle h, int level, int dtype, int nrhs, 
  * (as hpgmx_smooth; R, Z: [nrhs][N_level], Z updated in place). */
 hpgmx_status hpgmx_smooth_batched(hpgmx_handle h, int level, int dtype, int sweep, int nrhs,
                                   const void *R, void *Z, int zero_guess);
+
+/* hpgmx_presmooth_restrict for every right-hand side (R: [nrhs][N_level]
+ * input, Z: [nrhs][N_level] output, R_coarse: [nrhs][N_{level+1}] output). */
+hpgmx_status hpgmx_presmooth_restrict_batched(hpgmx_handle h, int level, int dtype, int sweep, int nsweeps,
+                                              int nrhs, const void *R, void *Z, void *R_coarse);
 
 /* Z[j] = M^{-1} R[j]: one batched V-cycle per right-hand side (as
  * hpgmx_vcycle; R, Z: [nrhs][N]). */

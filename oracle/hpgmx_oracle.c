@@ -353,6 +353,14 @@ void or_vcycle(int nx, int ny, int nz, double beta, int fo, int levels, int pre,
     mg_apply(&p, 0, nx, ny, nz, r, z);
 }
 
+/* The V-cycle for any stencil table (every level uses the same table). */
+void or_vcycle_c(int nx, int ny, int nz, const double *c27, int levels, int pre, int post,
+                 int coarsest, int sweep, int f32, const double *r, double *z)
+{
+    mgparam p = {levels, pre, post, coarsest, sweep, c27, f32};
+    mg_apply(&p, 0, nx, ny, nz, r, z);
+}
+
 /* ------------------------------------------------------------------------- */
 /* GMRES-IR with CGS2 and Givens rotations (Alg. 3).                         */
 /* ------------------------------------------------------------------------- */

@@ -71,6 +71,7 @@ def load():
     lib.or_stencil_from_beta.argtypes = [d, i, _dp]
     lib.or_spmv_c.argtypes = [i, i, i, _dp, _dp, _dp]
     lib.or_gs_c.argtypes = [i, i, i, _dp, i, _dp, _dp]
+    lib.or_vcycle_c.argtypes = [i, i, i, _dp, i, i, i, i, i, i, _dp, _dp]
     lib.or_gmres_ir_c.argtypes = [i, i, i, _dp, i, i, i, i, i, i, i, i, d, _dp, _dp,
                                   C.POINTER(_CStats), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(C.c_int), C.c_void_p, i]
@@ -217,6 +218,14 @@ def gs_c(dims, coef27, r, z, sweep=0):
     nx, ny, nz = _dims(dims)
     z = _f64(z).copy()
     load().or_gs_c(nx, ny, nz, _f64(coef27), int(sweep), _f64(r), z)
+    return z
+
+
+def vcycle_c(dims, coef27, r, levels, pre=1, post=1, coarsest=1, sweep=0, f32=False):
+    nx, ny, nz = _dims(dims)
+    z = np.empty(nx * ny * nz)
+    load().or_vcycle_c(nx, ny, nz, _f64(coef27), int(levels), int(pre), int(post), int(coarsest),
+                       int(sweep), int(f32), _f64(r), z)
     return z
 
 

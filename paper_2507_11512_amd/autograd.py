@@ -16,6 +16,8 @@ Krylov process) and dL/dtheta sums the correlations of the k pairs
 Both solves and the gradient reduction run in the HIP library; this module
 only wires them into torch.autograd.
 """
+from collections import OrderedDict
+
 import torch
 
 from . import hpgmx
@@ -26,24 +28,41 @@ def _key(theta):
 
 
 class StencilSolver:
-    """Caches the forward and the adjoint problem for each stencil it sees."""
+    """Keeps the forward and the adjoint problem (each a full multigrid
+    hierarchy on the device) for the `max_cached` stencils used most
+    recently; older pairs are closed, so a loop that updates theta holds a
+    bounded amount of device memory.  A backward pass whose stencil was
+    evicted sets its pair up again."""
 
     def __init__(self, dims, levels=3, sweep="forward", restart=30, tol=1e-10,
-                 precision="mxp", max_iters=10000):
+                 precision="mxp", max_iters=10000, max_cached=2):
         self.dims = (dims, dims, dims) if isinstance(dims, int) else tuple(dims)
         self.levels, self.sweep = levels, sweep
         self.restart, self.tol, self.precision, self.max_iters = restart, tol, precision, max_iters
-        self._cache = {}
+        if max_cached < 1:
+            raise ValueError("max_cached must be at least 1")
+        self.max_cached = int(max_cached)
+        self._cache = OrderedDict()
         self.last_stats = None
 
     def problems(self, theta):
         k = _key(theta)
-        if k not in self._cache:
-            coef = list(k)
-            fwd = hpgmx.Problem(self.dims, levels=self.levels, sweep=self.sweep, coef=coef)
+        if k in self._cache:
+            self._cache.move_to_end(k)
+            return self._cache[k]
+        while len(self._cache) >= self.max_cached:
+            _, (fwd, adj) = self._cache.popitem(last=False)
+            fwd.close()
+            adj.close()
+        coef = list(k)
+        fwd = hpgmx.Problem(self.dims, levels=self.levels, sweep=self.sweep, coef=coef)
+        try:
             adj = hpgmx.Problem(self.dims, levels=self.levels, sweep=self.sweep, coef=coef[::-1])
-            self._cache[k] = (fwd, adj)
-        return self._cache[k]
+        except Exception:
+            fwd.close()
+            raise
+        self._cache[k] = (fwd, adj)
+        return fwd, adj
 
     def solve(self, problem, rhs):
         rhs = rhs.contiguous()

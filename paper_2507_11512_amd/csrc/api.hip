@@ -106,6 +106,11 @@ struct hpgmx_ctx {
     // batched solves, by interleave width K
     std::map<int, Batch> batches;
 
+    // the last restart cycle of the last single solve, per inner dtype:
+    // steps taken and restart length (hpgmx_krylov_cycle_get)
+    int last_k[4] = {-1, -1, -1, -1};
+    int last_m[4] = {0, 0, 0, 0};
+
     void drop_graphs()
     {
         for (auto &g : graphs) (void)hipGraphExecDestroy(g.second);
@@ -418,11 +423,24 @@ void smooth_level(hpgmx_ctx *c, int l, Prec p, int kind, const void *r, void *z,
     }
 }
 
-// The pre-smoother is one forward or backward sweep from z = 0, so the fused
-// restriction can use the shortcut of k_restrict_after_sweep.
-bool restrict_after_single_sweep(const hpgmx_mg_desc &mg)
+// A pre-smoother of one forward or backward sweep from z = 0 lets the fused
+// restriction use the shortcut of k_restrict_after_sweep.
+bool restrict_after_single_sweep(int kind, int nsweeps)
 {
-    return mg.pre_sweeps == 1 && (mg.sweep == HPGMX_GS_FORWARD || mg.sweep == HPGMX_GS_BACKWARD);
+    return nsweeps == 1 && (kind == HPGMX_GS_FORWARD || kind == HPGMX_GS_BACKWARD);
+}
+
+// The first half of a V-cycle level: z <- nsweeps sweeps of kind `kind` from
+// z = 0 on level l, then rc = R (r - A z) on level l + 1 (eq. (6)).
+void presmooth_restrict(hpgmx_ctx *c, int l, Prec p, int kind, int nsweeps, const void *r, void *z, void *rc)
+{
+    smooth_level(c, l, p, kind, r, z, true, nsweeps);
+    ProfScope ps(c, HPGMX_K_RESTRICT, l);
+    const Geom &gc = c->lv[l + 1].A.g;
+    if (restrict_after_single_sweep(kind, nsweeps))
+        launch_restrict_after_sweep(c->lv[l].A, gc, p, kind == HPGMX_GS_FORWARD, z, rc, c->stream);
+    else
+        launch_restrict(c->lv[l].A, gc, p, r, z, rc, c->stream);
 }
 
 // z = M^{-1} r on level l (z is overwritten; the cycle starts from zero).
@@ -435,14 +453,7 @@ void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z)
         return;
     }
     Level &C = c->lv[l + 1];
-    smooth_level(c, l, p, mg.sweep, r, z, true, mg.pre_sweeps);
-    {
-        ProfScope ps(c, HPGMX_K_RESTRICT, l);
-        if (restrict_after_single_sweep(mg))
-            launch_restrict_after_sweep(c->lv[l].A, C.A.g, p, mg.sweep == HPGMX_GS_FORWARD, z, C.r[vt], c->stream);
-        else
-            launch_restrict(c->lv[l].A, C.A.g, p, r, z, C.r[vt], c->stream);
-    }
+    presmooth_restrict(c, l, p, mg.sweep, mg.pre_sweeps, r, z, C.r[vt]);
     vcycle(c, l + 1, p, C.r[vt], C.z[vt]);
     {
         ProfScope ps(c, HPGMX_K_PROLONG, l);
@@ -678,6 +689,8 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                 ProfScope ps(c, HPGMX_K_TRSM, 0);
                 launch_trsm(c->ctrl, KCount{{kk}}, 1, m, c->stream);
             }
+            c->last_k[p] = kk;
+            c->last_m[p] = m;
             {
                 ProfScope ps(c, HPGMX_K_GEMV, 0);
                 launch_gemv(N, 1, p, K.Q, ldq, kk, c->ctrl, K.u, c->stream);
@@ -828,6 +841,20 @@ void bsmooth_level(hpgmx_ctx *c, Batch &B, int l, Prec p, int kind, const void *
     }
 }
 
+// presmooth_restrict() for K right-hand sides at once.
+void bpresmooth_restrict(hpgmx_ctx *c, Batch &B, int l, Prec p, int kind, int nsweeps, const void *r, void *z,
+                         void *rc)
+{
+    bsmooth_level(c, B, l, p, kind, r, z, true, nsweeps);
+    ProfScope ps(c, HPGMX_K_RESTRICT, l);
+    const Geom &gc = c->lv[l + 1].A.g;
+    const int R = tile_r(c, B, p, HPGMX_BK_RESTRICT, l);
+    if (restrict_after_single_sweep(kind, nsweeps))
+        launch_brestrict_after_sweep(c->lv[l].A, gc, p, B.K, R, kind == HPGMX_GS_FORWARD, z, rc, c->stream);
+    else
+        launch_brestrict(c->lv[l].A, gc, p, B.K, R, r, z, rc, c->stream);
+}
+
 // The V-cycle of vcycle() for K right-hand sides at once.
 void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z)
 {
@@ -838,16 +865,7 @@ void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z)
         return;
     }
     const Geom &gc = c->lv[l + 1].A.g;
-    bsmooth_level(c, B, l, p, mg.sweep, r, z, true, mg.pre_sweeps);
-    {
-        ProfScope ps(c, HPGMX_K_RESTRICT, l);
-        const int R = tile_r(c, B, p, HPGMX_BK_RESTRICT, l);
-        if (restrict_after_single_sweep(mg))
-            launch_brestrict_after_sweep(c->lv[l].A, gc, p, B.K, R, mg.sweep == HPGMX_GS_FORWARD, z,
-                                         B.lr[vt][l + 1], c->stream);
-        else
-            launch_brestrict(c->lv[l].A, gc, p, B.K, R, r, z, B.lr[vt][l + 1], c->stream);
-    }
+    bpresmooth_restrict(c, B, l, p, mg.sweep, mg.pre_sweeps, r, z, B.lr[vt][l + 1]);
     bvcycle(c, B, l + 1, p, B.lr[vt][l + 1], B.lz[vt][l + 1]);
     {
         ProfScope ps(c, HPGMX_K_PROLONG, l);
@@ -904,7 +922,7 @@ void autotune(hpgmx_ctx *c, Batch &B, Prec p)
             });
             if (l + 1 < L)
                 t[HPGMX_BK_RESTRICT] = time_it([&] {  // the variant the V-cycle uses
-                    if (restrict_after_single_sweep(c->mg))
+                    if (restrict_after_single_sweep(c->mg.sweep, c->mg.pre_sweeps))
                         launch_brestrict_after_sweep(A, c->lv[l + 1].A.g, p, K, R, c->mg.sweep == HPGMX_GS_FORWARD,
                                                      t1, t2, c->stream);
                     else
@@ -1460,6 +1478,66 @@ hpgmx_status hpgmx_restrict_residual(hpgmx_handle h, int level, int dtype, const
     });
 }
 
+hpgmx_status hpgmx_presmooth_restrict(hpgmx_handle h, int level, int dtype, int sweep, int nsweeps,
+                                      const void *r, void *z, void *r_coarse)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, true);
+        const Prec p = check_dtype(dtype);
+        if (sweep < HPGMX_GS_FORWARD || sweep > HPGMX_GS_SYMMETRIC) fail(HPGMX_EINVAL, "unknown sweep kind");
+        if (nsweeps < 0 || nsweeps > 16) fail(HPGMX_EINVAL, "nsweeps must be 0..16");
+        check_ptr(r, "r");
+        check_ptr(z, "z");
+        check_ptr(r_coarse, "r_coarse");
+        ensure_prec(h, p);
+        ensure_tmp(h, p);
+        const int vt = vt_of(p);
+        const Matrix &A = h->lv[level].A;
+        const Geom &gc = h->lv[level + 1].A.g;
+        const Prec pv = p == P64 ? P64 : P32;
+        zero_entry(h, h->tmp[vt][1], A.g.N, pv);
+        launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
+        presmooth_restrict(h, level, p, sweep, nsweeps, h->tmp[vt][0], h->tmp[vt][1], h->tmp[vt][2]);
+        launch_int2nat(A.g, pv, h->tmp[vt][1], pv, z, h->stream);
+        launch_int2nat(gc, pv, h->tmp[vt][2], pv, r_coarse, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_krylov_cycle_get(hpgmx_handle h, int dtype, int *k, double *Q, double *scale, double *Hbar,
+                                    double *y)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        const Prec p = check_dtype(dtype);
+        check_ptr(k, "k");
+        const int kk = h->last_k[p], m = h->last_m[p];
+        if (kk < 0 || !h->ctrl) fail(HPGMX_ESTATE, "no single solve with this inner dtype has run");
+        *k = kk;
+        const Krylov &K = h->kry[p];
+        const Geom &g0 = h->lv[0].A.g;
+        const size_t vb = vec_bytes(p);
+        if (Q)
+            for (int j = 0; j <= kk; ++j)
+                launch_int2nat(g0, p == P64 ? P64 : P32, (const char *)K.Q + (size_t)j * K.ldq * vb, P64,
+                               Q + (size_t)j * g0.N, h->stream);
+        if (scale)
+            hip_check(hipMemcpyAsync(scale, h->ctrl->colscale, (size_t)(kk + 1) * 8, hipMemcpyDeviceToHost,
+                                     h->stream), "hipMemcpyAsync");
+        if (Hbar)
+            for (int j = 0; j < kk; ++j)
+                hip_check(hipMemcpyAsync(Hbar + (size_t)j * (kk + 1), h->ctrl->Hbar + (size_t)j * (m + 1),
+                                         (size_t)(kk + 1) * 8, hipMemcpyDeviceToHost, h->stream),
+                          "hipMemcpyAsync");
+        if (y)
+            hip_check(hipMemcpyAsync(y, h->ctrl->y, (size_t)kk * 8, hipMemcpyDeviceToHost, h->stream),
+                      "hipMemcpyAsync");
+        hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        return HPGMX_OK;
+    });
+}
+
 hpgmx_status hpgmx_prolong_add(hpgmx_handle h, int level, int dtype, const void *z_coarse, void *z)
 {
     return guarded(h, [&]() -> hpgmx_status {
@@ -1628,6 +1706,34 @@ hpgmx_status hpgmx_smooth_batched(hpgmx_handle h, int level, int dtype, int swee
         if (!zero_guess) launch_bnat2int(A.g, p, p, K, nrhs, Z, B.tmp[vt][1], h->stream);
         bsmooth_level(h, B, level, p, sweep, B.tmp[vt][0], B.tmp[vt][1], zero_guess != 0, 1);
         launch_bint2nat(A.g, p, p, K, nrhs, B.tmp[vt][1], Z, h->stream);
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_presmooth_restrict_batched(hpgmx_handle h, int level, int dtype, int sweep, int nsweeps,
+                                              int nrhs, const void *R, void *Z, void *R_coarse)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_level(h, level, true);
+        check_nrhs(nrhs);
+        const Prec p = check_batch_dtype(dtype);
+        if (sweep < HPGMX_GS_FORWARD || sweep > HPGMX_GS_SYMMETRIC) fail(HPGMX_EINVAL, "unknown sweep kind");
+        if (nsweeps < 0 || nsweeps > 16) fail(HPGMX_EINVAL, "nsweeps must be 0..16");
+        check_ptr(R, "R");
+        check_ptr(Z, "Z");
+        check_ptr(R_coarse, "R_coarse");
+        const int K = batch_width(nrhs), vt = vt_of(p);
+        Batch &B = ensure_batch(h, K);
+        ensure_batch_prec(h, B, p, 0);
+        ensure_batch_tmp(h, B, vt);
+        const Matrix &A = h->lv[level].A;
+        const Geom &gc = h->lv[level + 1].A.g;
+        zero_batch_row(h, B.tmp[vt][1], A.g.N, K, p);
+        launch_bnat2int(A.g, p, p, K, nrhs, R, B.tmp[vt][0], h->stream);
+        bpresmooth_restrict(h, B, level, p, sweep, nsweeps, B.tmp[vt][0], B.tmp[vt][1], B.tmp[vt][2]);
+        launch_bint2nat(A.g, p, p, K, nrhs, B.tmp[vt][1], Z, h->stream);
+        launch_bint2nat(gc, p, p, K, nrhs, B.tmp[vt][2], R_coarse, h->stream);
         return HPGMX_OK;
     });
 }

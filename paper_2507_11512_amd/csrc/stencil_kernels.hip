@@ -73,6 +73,30 @@ Stencil stencil_from_beta(double beta)
     return st;
 }
 
+// IEEE round-to-nearest-even of x to a binary format with p significand bits
+// (the leading one included), smallest normal exponent emin and largest
+// finite value maxv, in one step from FP64: the value is scaled so that the
+// format's last significand bit (fixed at 2^(emin-p+1) below the normal
+// range) becomes the unit, rounded to an integer with ties to even, and
+// scaled back; a value that rounds above maxv overflows to infinity.  The
+// result is exactly representable in the format (and in FP32), so the
+// conversions that store it are exact and the entry is rounded once.
+__device__ double round_to_format(double x, int p, int emin, double maxv)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    (void)frexp(x, &e);  // |x| = f 2^e with f in [0.5, 1): leading bit 2^(e-1)
+    const int lead = e - 1 < emin ? emin : e - 1;
+    const int q = lead - (p - 1);
+    const double r = ldexp(rint(ldexp(x, -q)), q);
+    return fabs(r) > maxv ? copysign(INFINITY, x) : r;
+}
+__device__ __half to_half_rne(double x) { return __float2half((float)round_to_format(x, 11, -14, 65504.0)); }
+__device__ bf16 to_bf16_rne(double x)
+{
+    return __float2bfloat16((float)round_to_format(x, 8, -126, 3.3895313892515355e38));
+}
+
 __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil st, int *col, double *v64,
                                                      double *d64, float *v32, float *d32,
                                                      __half *v16, __half *d16, bf16 *vb16,
@@ -94,14 +118,14 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil 
         if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)N;
         if (v64) v64[e] = a;
         if (v32) v32[e] = (float)a;
-        if (v16) v16[e] = __float2half((float)a);
-        if (vb16) vb16[e] = __float2bfloat16((float)a);
+        if (v16) v16[e] = to_half_rne(a);
+        if (vb16) vb16[e] = to_bf16_rne(a);
     }
     const double dg = st.c[13];
     if (d64) d64[p] = dg;
     if (d32) d32[p] = (float)dg;
-    if (d16) d16[p] = __float2half((float)dg);
-    if (db16) db16[p] = __float2bfloat16((float)dg);
+    if (d16) d16[p] = to_half_rne(dg);
+    if (db16) db16[p] = to_bf16_rne(dg);
 }
 
 void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s)

@@ -40,7 +40,8 @@ EXPORTS = ["hpgmx_setup_problem", "hpgmx_setup_problem_stencil", "hpgmx_stencil_
            "hpgmx_rhs_from_x", "hpgmx_profile_get", "hpgmx_stream_copy", "hpgmx_destroy",
            "hpgmx_last_error", "hpgmx_batch_autotune", "hpgmx_batch_set_tuning",
            "hpgmx_batch_get_tuning", "hpgmx_workspace_bytes_batched", "hpgmx_spmv_batched",
-           "hpgmx_smooth_batched", "hpgmx_vcycle_batched", "hpgmx_gmres_ir_solve_batched"]
+           "hpgmx_smooth_batched", "hpgmx_vcycle_batched", "hpgmx_gmres_ir_solve_batched",
+           "hpgmx_presmooth_restrict", "hpgmx_presmooth_restrict_batched", "hpgmx_krylov_cycle_get"]
 
 
 class ProblemDesc(C.Structure):
@@ -104,6 +105,9 @@ def _load():
         "hpgmx_smooth_batched": [H, i, i, i, i, vp, vp, i],
         "hpgmx_vcycle_batched": [H, i, i, vp, vp],
         "hpgmx_gmres_ir_solve_batched": [H, i, vp, vp, C.POINTER(SolveDesc), C.POINTER(SolveStats)],
+        "hpgmx_presmooth_restrict": [H, i, i, i, i, vp, vp, vp],
+        "hpgmx_presmooth_restrict_batched": [H, i, i, i, i, i, vp, vp, vp],
+        "hpgmx_krylov_cycle_get": [H, i, C.POINTER(i), vp, vp, vp, vp],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -237,6 +241,30 @@ def restrict_residual(h, level, dtype, r, z, r_coarse):
                                           _ptr(r_coarse)))
 
 
+def presmooth_restrict(h, level, dtype, sweep, nsweeps, r, z, r_coarse):
+    _check(h, lib.hpgmx_presmooth_restrict(h, int(level), int(dtype), int(sweep), int(nsweeps), _ptr(r),
+                                           _ptr(z), _ptr(r_coarse)))
+
+
+def krylov_cycle_get(h, dtype, N, restart):
+    """The last cycle of the last single solve with this inner dtype:
+    (k, Q (k+1, N) float64 GPU tensor of stored columns, scale (k+1,),
+    Hbar (k+1, k), y (k,)) -- numpy arrays except Q."""
+    import numpy as np
+    import torch
+    m = int(restart)
+    Q = torch.empty((m + 1, int(N)), dtype=torch.float64, device="cuda")
+    scale = np.zeros(m + 1)
+    Hb = np.zeros(m * (m + 1))
+    y = np.zeros(m)
+    k = C.c_int(0)
+    _check(h, lib.hpgmx_krylov_cycle_get(h, int(dtype), C.byref(k), _ptr(Q), scale.ctypes.data_as(C.c_void_p),
+                                         Hb.ctypes.data_as(C.c_void_p), y.ctypes.data_as(C.c_void_p)))
+    k = k.value
+    Hbar = Hb[:k * (k + 1)].reshape(k, k + 1).T.copy()
+    return k, Q[:k + 1], scale[:k + 1].copy(), Hbar, y[:k].copy()
+
+
 def prolong_add(h, level, dtype, z_coarse, z):
     _check(h, lib.hpgmx_prolong_add(h, int(level), int(dtype), _ptr(z_coarse), _ptr(z)))
 
@@ -291,6 +319,11 @@ def spmv_batched(h, level, dtype, X, Y):
 def smooth_batched(h, level, dtype, sweep, R, Z, zero_guess=False):
     _check(h, lib.hpgmx_smooth_batched(h, int(level), int(dtype), int(sweep), int(R.shape[0]), _ptr(R),
                                        _ptr(Z), int(bool(zero_guess))))
+
+
+def presmooth_restrict_batched(h, level, dtype, sweep, nsweeps, R, Z, R_coarse):
+    _check(h, lib.hpgmx_presmooth_restrict_batched(h, int(level), int(dtype), int(sweep), int(nsweeps),
+                                                   int(R.shape[0]), _ptr(R), _ptr(Z), _ptr(R_coarse)))
 
 
 def vcycle_batched(h, dtype, R, Z):

@@ -88,14 +88,40 @@ def fl32(v):
     return np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
+def round_format(v, p, emin, maxv):
+    """Round to the nearest value (ties to even) of a binary format with p
+    significand bits (the leading one included), smallest normal exponent
+    emin and largest finite value maxv, straight from float64 (IEEE 754
+    round-to-nearest-even; the quantum is fixed at 2^(emin-p+1) below the
+    normal range, and values rounding above maxv overflow)."""
+    v = np.asarray(v, dtype=np.float64)
+    _, e = np.frexp(v)
+    lead = np.maximum(e - 1, emin)
+    q = lead - (p - 1)
+    r = np.ldexp(np.rint(np.ldexp(v, -q)), q)
+    r = np.where(np.abs(r) > maxv, np.copysign(np.inf, v), r)
+    return np.where(v == 0.0, v, r)
+
+
+def fl16(v):
+    """IEEE binary16 rounding (ties to even), widened back to float64."""
+    return round_format(v, 11, -14, 65504.0)
+
+
+def flbf16(v):
+    """bfloat16 rounding (8-bit significand, binary32's exponent range)."""
+    return round_format(v, 8, -126, float.fromhex("0x1.fep127"))
+
+
 def vcycle_ref(d, r, levels, pre=1, post=1, coarsest=1, sweep=0, beta=0.5, faces_only=False,
-               store=keep):
+               store=keep, coef=None):
     """The V-cycle composed from the pieces above.  `store` is applied to
     every vector the cycle keeps (after each sweep, the restricted residual,
     the corrected z): identity for the FP64 method, fl32 for binary32
-    storage of the multigrid work vectors."""
+    storage of the multigrid work vectors.  With `coef` every level uses
+    that 27-entry stencil table instead of the beta family."""
     d = dims3(d)
-    A = kron_matrix(d, beta, faces_only)
+    A = kron_matrix(d, beta, faces_only) if coef is None else stencil_matrix(d, coef)
     perm = colour_perm(d)
     z = np.zeros(A.shape[0])
     if levels == 1:
@@ -107,7 +133,7 @@ def vcycle_ref(d, r, levels, pre=1, post=1, coarsest=1, sweep=0, beta=0.5, faces
     R = injection_matrix(d)
     rc = store(R @ (r - A @ z))
     zc = vcycle_ref((d[0] // 2, d[1] // 2, d[2] // 2), rc, levels - 1, pre, post, coarsest,
-                    sweep, beta, faces_only, store)
+                    sweep, beta, faces_only, store, coef)
     z = store(z + R.T @ zc)
     for _ in range(post):
         z = store(gs_triangular(A, perm, r, z, sweep))

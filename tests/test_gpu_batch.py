@@ -164,6 +164,39 @@ def test_vcycle_batched(hp, dims, levels, sweep, dtype):
     force_tiles(hp, P, nrhs, dtype, 0)
 
 
+@pytest.mark.parametrize("dtype", [0, 1, 3])
+@pytest.mark.parametrize("sweep", [0, 1])
+def test_presmooth_restrict_batched(hp, dtype, sweep):
+    """The batched pre-smoother and restriction of the V-cycle: per right-hand
+    side bit-identical to the single-vector export for every tile shape, and
+    within the single export's bounds against the oracle."""
+    dims, levels, nrhs = (24, 20, 16), 3, 5
+    P = problem(hp, dims, levels)
+    for lvl in range(levels - 1):
+        d = tuple(v >> lvl for v in dims)
+        dc = tuple(v >> (lvl + 1) for v in dims)
+        N, Nc = int(np.prod(d)), int(np.prod(dc))
+        Rh = np.stack([inputs.uniform(d, 1400 + 10 * lvl + j) for j in range(nrhs)])
+        if dtype != 0:
+            Rh = Rh.astype(np.float32).astype(np.float64)
+        for R in (1, 2, 4, 8):
+            force_tiles(hp, P, nrhs, dtype, R)
+            Z = dev(np.zeros((nrhs, N)), dtype)
+            RC = dev(np.zeros((nrhs, Nc)), dtype)
+            hp.presmooth_restrict_batched(P.h, lvl, dtype, sweep, 1, dev(Rh, dtype), Z, RC)
+            Zg, RCg = host(Z), host(RC)
+            for j in range(nrhs):
+                z1 = dev(np.zeros(N), dtype)
+                rc1 = dev(np.zeros(Nc), dtype)
+                hp.presmooth_restrict(P.h, lvl, dtype, sweep, 1, dev(Rh[j], dtype), z1, rc1)
+                assert np.array_equal(Zg[j], host(z1)) and np.array_equal(RCg[j], host(rc1)), (lvl, R, j)
+            j = nrhs - 1
+            ref = oracle.restrict_fused(d, Rh[j], Zg[j])
+            scale = oracle.inject(d, np.abs(Rh[j]) + oracle.absrow(d, Zg[j]))
+            assert np.all(np.abs(RCg[j] - ref) <= 3 * gamma(28, U[0 if dtype == 0 else 1]) * scale + 1e-300)
+    force_tiles(hp, P, nrhs, dtype, 0)
+
+
 def _batch_rhs(dims, nrhs):
     U_ = np.stack([inputs.batch_u(dims, j) for j in range(nrhs)])
     B = np.stack([oracle.spmv(dims, U_[j]) for j in range(nrhs)])

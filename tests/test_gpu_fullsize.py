@@ -133,6 +133,37 @@ def test_restrict_320_sampled(hp, p320):
     assert np.all(np.abs(got[cs] - ref) <= 2 * gamma(28, U32) * scale)
 
 
+def test_presmooth_restrict_320_sampled(hp, p320):
+    """The level-0 pre-sweep from zero and the restriction the 320^3 V-cycle
+    runs (the shortcut from the couplings to colours 5-7), sampled: each
+    relaxed row satisfies its relaxation identity given the GPU's own
+    neighbour values (later colours still zero), and each sampled coarse
+    entry equals eq. (6) on the GPU's z within 3 gamma_28 of its scale."""
+    d, dc = (320, 320, 320), (160, 160, 160)
+    r = inputs.uniform(d, 36).astype(np.float32).astype(np.float64)
+    z = dev(np.zeros(r.size), 1)
+    rc = dev(np.zeros(160 ** 3), 1)
+    hp.presmooth_restrict(p320.h, 0, 1, 0, 1, dev(r, 1), z, rc)
+    z1, got = host(z), host(rc)
+    col = colours(d)
+    rows = sample_rows(d, 16000, 4)
+    for c in range(8):
+        rcs = rows[col[rows] == c]
+        w = np.where(col < c, z1, 0.0)
+        off = oracle.spmv_rows(d, w, rcs) - 26.0 * w[rcs]
+        expect = (r[rcs] - off) / 26.0
+        S = (np.abs(r[rcs]) + abs_offdiag_rows(d, w, rcs)) / 26.0
+        assert np.all(np.abs(z1[rcs] - expect) <= 2 * gamma(28, U32) * S + 1e-300), c
+    del w
+    cs = sample_rows(dc, 8000, 5)
+    I, J, K = cs % 160, (cs // 160) % 160, cs // (160 * 160)
+    fine = 2 * I + 320 * (2 * J + 320 * 2 * K)
+    ref = r[fine] - oracle.spmv_rows(d, z1, fine)
+    scale = np.abs(r[fine]) + 26.0 * np.abs(z1[fine]) + abs_offdiag_rows(d, z1, fine)
+    assert np.all(np.abs(got[cs] - ref) <= 3 * gamma(28, U32) * scale)
+    assert np.max(np.abs(ref)) > 1e-2
+
+
 @pytest.mark.parametrize("precision", ["mxp", "fp64"])
 def test_solve_320(hp, p320, precision):
     import torch
@@ -201,9 +232,12 @@ def test_spmv_batched_192_sampled(hp, p192):
 
 
 def test_solve_batched_192(hp, p192):
-    """b_j = A u_j: every right-hand side reaches the 1e-9 residual, its
-    solution is u_j up to the residual's amplification, and right-hand side 0
-    takes the iterations of its own single solve."""
+    """b_j = A u_j: at tol 1e-9 every right-hand side reaches the residual
+    bar and right-hand side 0 takes the iterations of its own single solve.
+    A 1e-9 residual bounds ||x_j - u_j|| / ||u_j|| only up to the grid's
+    amplification (about 1e-7 here), so the x bar is checked on the pair
+    solved to 1e-11, where the mixed-precision refinement reaches FP64
+    accuracy: ||x_j - u_j|| / ||u_j|| <= 1e-8 against the exact solution u_j."""
     d = (192, 192, 192)
     U_ = np.stack([inputs.batch_u(d, j) for j in range(8)])
     Bh = np.stack([oracle.spmv(d, U_[j]) for j in range(8)])
@@ -215,10 +249,35 @@ def test_solve_batched_192(hp, p192):
         print(f"[192^3 batch j={j}] iters={stats[j].iters} res={res:.3e} |x-u|/|u|={err:.3e} "
               f"time={stats[j].solve_ms / 1e3:.2f}s", flush=True)
         assert stats[j].converged and res <= 1e-9
-        assert err <= 1e-7
+    del X, Xh
     x0, st0 = p192.solve(dev(Bh[0], 0), tol=1e-9, restart=30, precision="mxp")
     print(f"[192^3 single j=0] iters={st0.iters} time={st0.solve_ms / 1e3:.2f}s", flush=True)
     assert abs(stats[0].iters - st0.iters) <= 2
+    del x0
+    X, stats = p192.solve_batched(dev(Bh, 0), tol=1e-11, restart=30, precision="mxp", graph=True)
+    Xh = host(X)
+    for j in range(8):
+        err = np.linalg.norm(Xh[j] - U_[j]) / np.linalg.norm(U_[j])
+        print(f"[192^3 batch tol 1e-11 j={j}] iters={stats[j].iters} |x-u|/|u|={err:.3e}", flush=True)
+        assert stats[j].converged and err <= 1e-8, (j, err)
+
+
+def test_solve_320_symmetric_beta0_to_1e11(hp):
+    """The symmetric member of the stencil family (beta = 0) at 320^3: the
+    1e-9 residual leaves ||x - 1|| / ||1|| near 3e-7 (a smaller smallest
+    singular value than beta = 0.5), so the x bar is checked at 1e-11."""
+    import torch
+    print("[setup] 320^3, beta = 0", flush=True)
+    P = hp.Problem(320, beta=0.0, levels=4, sweep="forward")
+    try:
+        b = P.rhs_from_x(torch.ones(320 ** 3, dtype=torch.float64, device="cuda"))
+        x, st = P.solve(b, tol=1e-11, restart=30, precision="mxp")
+        err = ((x - 1.0).norm() / (320 ** 1.5)).item()
+        print(f"[320^3 beta=0 tol 1e-11] iters={st.iters} res={st.final_rel_res:.3e} |x-1|/|1|={err:.3e}",
+              flush=True)
+        assert st.converged and st.final_rel_res < 1e-11 and err <= 1e-8
+    finally:
+        P.close()
 
 
 # ---- the low-precision configuration: 256^3 with 16-bit matrices ----------------------------
@@ -318,7 +377,9 @@ def test_largest_grid_512_sampled(hp):
 def test_adjoint_192_batched(hp):
     """The batched + adjoint configuration at its full size: 192^3, k = 8
     right-hand sides b_j = A u_j, loss L = sum_j g_j . x_j with
-    g_j ~ N(0, 1), mixed-precision forward and adjoint solves to 1e-9.
+    g_j ~ N(0, 1), mixed-precision forward and adjoint solves to 1e-11 (the
+    x bar, 1e-8 against the exact u_j, needs more than a 1e-9 residual at
+    this size).
     Checked at full size by properties the oracle computes: each adjoint
     solution lam_j = dL/db_j solves A^T lam_j = g_j (A^T is the stencil at
     -beta, applied by the oracle) to the solve bar, and dL/dtheta equals
@@ -332,7 +393,7 @@ def test_adjoint_192_batched(hp):
     th = oracle.stencil_from_beta(0.5)
     U_ = np.stack([inputs.batch_u(d, j) for j in range(k)])
     G = np.stack([inputs.normal(d, 11612 + j) for j in range(k)])
-    solver = StencilSolver(d, levels=4, tol=1e-9, precision="mxp")
+    solver = StencilSolver(d, levels=4, tol=1e-11, precision="mxp")
     try:
         fwd, _ = solver.problems(torch.from_numpy(th))
         Ut = torch.from_numpy(U_).cuda()
@@ -353,9 +414,11 @@ def test_adjoint_192_batched(hp):
         corr = np.zeros(27)
         scale = np.zeros(27)
         for j in range(k):
-            assert np.linalg.norm(Xh[j] - U_[j]) <= 1e-7 * np.linalg.norm(U_[j])
+            err = np.linalg.norm(Xh[j] - U_[j]) / np.linalg.norm(U_[j])
             resT = np.linalg.norm(G[j] - oracle.spmv(d, lam[j], beta=-0.5)) / np.linalg.norm(G[j])
-            assert resT <= 1e-9, (j, resT)
+            print(f"[adjoint 192^3 j={j}] |x-u|/|u|={err:.3e} adjoint residual={resT:.3e}", flush=True)
+            assert err <= 1e-8, (j, err)
+            assert resT <= 1e-10, (j, resT)
             corr += oracle.stencil_correlation(d, lam[j], Xh[j])
             scale += oracle.stencil_correlation(d, np.abs(lam[j]), np.abs(Xh[j]))
         assert np.all(np.abs(gt + corr) <= 2 * 192 ** 3 * U64 * scale)

@@ -135,6 +135,103 @@ def test_restrict_and_prolong_every_level(hp, dims, levels, dtype):
         assert np.all(np.abs(host(zt) - ref) <= 2 * U[dtype] * np.abs(ref))
 
 
+def _restrict_scale(d, r, z):
+    return oracle.inject(d, np.abs(r) + oracle.absrow(d, z))
+
+
+@pytest.mark.parametrize("dims,levels", GRIDS)
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3])
+@pytest.mark.parametrize("sweep", [0, 1])
+def test_presmooth_restrict_every_level(hp, dims, levels, dtype, sweep):
+    """The pre-smoother and the restriction the V-cycle runs (one sweep from
+    zero, then the shortcut of eq. (6) from the couplings to the colours
+    relaxed after the injection colour), element by element.
+      * z against one oracle sweep from zero (the Gauss-Seidel bound);
+      * r_c against eq. (6) evaluated by the oracle on the GPU's own z:
+        the shortcut's 8 (forward) or 18 (backward) products add at most
+        gamma_28 of the scale |r| + |A||z| at the injection point, and it
+        drops the residual that the rounding of the injection colour's own
+        relaxation left, at most gamma_28 of the same scale: 3 gamma_28
+        with the oracle's rounding;
+      * r_c against the oracle's whole composition R(r - A gs(r, 0)), where
+        the GPU's z error enters through |A|."""
+    P = problem(hp, dims, levels)
+    for lvl in range(levels - 1):
+        d, dc = ldims(dims, lvl), ldims(dims, lvl + 1)
+        r = rnd(inputs.uniform(d, 1200 + lvl), dtype)
+        z = dev(np.full(r.size, 7.0), dtype)        # output only
+        rc = dev(np.zeros(int(np.prod(dc))), dtype)
+        hp.presmooth_restrict(P.h, lvl, dtype, sweep, 1, dev(r, dtype), z, rc)
+        zg, rcg = host(z), host(rc)
+        zo = oracle.gs(d, r, np.zeros(r.size), sweep)
+        ztol = _gs_tol(d, r, np.zeros(r.size), zo, dtype, 8)
+        assert np.max(np.abs(zg - zo)) <= ztol, (lvl, np.max(np.abs(zg - zo)), ztol)
+        u = U[dtype]
+        ref = oracle.restrict_fused(d, r, zg)
+        tol = 3 * gamma(28, u) * _restrict_scale(d, r, zg) + 1e-300
+        assert np.all(np.abs(rcg - ref) <= tol), (lvl, np.max(np.abs(rcg - ref) / tol))
+        ro = oracle.restrict_fused(d, r, zo)
+        tol2 = 3 * gamma(28, u) * _restrict_scale(d, r, zo) + oracle.inject(d, oracle.absrow(d, np.full(r.size, ztol)))
+        assert np.all(np.abs(rcg - ro) <= tol2), (lvl, np.max(np.abs(rcg - ro) / tol2))
+        # not the trivial 0 = 0: the restricted residual is of the size of r
+        assert np.max(np.abs(ro)) > 1e-2 * np.max(np.abs(r))
+
+
+@pytest.mark.parametrize("dtype", [0, 1])
+@pytest.mark.parametrize("sweep,nsweeps", [(0, 2), (2, 1), (0, 0)])
+def test_presmooth_restrict_general_form(hp, dtype, sweep, nsweeps):
+    """Symmetric or several pre-sweeps (and none) keep eq. (6) in full."""
+    dims, levels = (24, 20, 16), 3
+    P = problem(hp, dims, levels)
+    r = rnd(inputs.uniform(dims, 1250), dtype)
+    z = dev(np.zeros(r.size), dtype)
+    rc = dev(np.zeros(12 * 10 * 8), dtype)
+    hp.presmooth_restrict(P.h, 0, dtype, sweep, nsweeps, dev(r, dtype), z, rc)
+    zg = host(z)
+    zo = np.zeros(r.size)
+    for _ in range(nsweeps):
+        zo = oracle.gs(dims, r, zo, sweep)
+    passes = nsweeps * (16 if sweep == 2 else 8)
+    if passes:
+        assert np.max(np.abs(zg - zo)) <= _gs_tol(dims, r, np.zeros(r.size), zo, dtype, passes)
+    else:
+        assert np.all(zg == 0.0)
+    ref = oracle.restrict_fused(dims, r, zg)
+    assert np.all(np.abs(host(rc) - ref) <= 2 * gamma(28, U[dtype]) * _restrict_scale(dims, r, zg) + 1e-300)
+
+
+@pytest.mark.parametrize("precision,dtype", [("fp64", 0), ("mxp", 1), ("fp16", 2), ("bf16", 3)])
+def test_krylov_basis_of_a_cycle(hp, precision, dtype):
+    """One restart cycle of 12 steps: the stored basis is orthonormal to the
+    working precision of its storage (FP64: 1e-13; FP32 columns: 1e-5), the
+    Arnoldi relation A M^-1 Q_k = Q_{k+1} Hbar_k holds with the oracle's FP64
+    operator and V-cycle up to the inner precision of M^-1, and y is the
+    least-squares solution of Hbar y = rho e_1 (Alg. 3, CGS2 and Givens)."""
+    import torch
+    dims, levels, m = (16, 16, 16), 3, 12
+    P = problem(hp, dims, levels)
+    b = oracle.spmv(dims, inputs.uniform(dims, 1300))
+    x = torch.zeros(P.N, dtype=torch.float64, device="cuda")
+    st = hp.gmres_ir_solve(P.h, dev(b, 0), x, restart=m, max_iters=m, tol=0.0, inner_dtype=dtype)
+    assert st.iters == m
+    k, Qd, scale, Hbar, y = hp.krylov_cycle_get(P.h, dtype, P.N, m)
+    assert k == m
+    Q = host(Qd).T * scale[None, :]
+    orth = np.linalg.norm(Q.T @ Q - np.eye(k + 1))
+    rel = np.linalg.norm(np.column_stack([oracle.spmv(dims, oracle.vcycle(dims, Q[:, j], levels))
+                                          for j in range(k)]) - Q @ Hbar) / np.linalg.norm(Hbar)
+    rhs = np.zeros(k + 1)
+    rhs[0] = np.linalg.norm(b)
+    ys, *_ = np.linalg.lstsq(Hbar, rhs, rcond=None)
+    dy = np.linalg.norm(y - ys) / np.linalg.norm(ys)
+    print(f"[krylov {precision}] ||Q^T Q - I|| = {orth:.2e}  Arnoldi {rel:.2e}  |y - lstsq| {dy:.2e}", flush=True)
+    if dtype == 0:
+        assert orth <= 1e-13 and rel <= 1e-12 and dy <= 1e-10
+    else:
+        assert orth <= 1e-5 and rel <= 1e-4 and dy <= 1e-10
+    assert np.all(np.tril(Hbar, -2) == 0.0)
+
+
 @pytest.mark.parametrize("dims,levels,sweep", [((16, 16, 16), 3, "symmetric"),
                                                ((16, 16, 16), 3, "forward"),
                                                ((24, 20, 16), 3, "forward"),
@@ -147,9 +244,25 @@ def test_vcycle(hp, dims, levels, sweep, dtype):
     r = rnd(inputs.uniform(dims, 700), dtype)
     z = dev(np.zeros(r.size), dtype)
     hp.vcycle(P.h, dtype, dev(r, dtype), z)
-    ref = oracle.vcycle(dims, r, levels, 1, 1, 1, {"forward": 0, "backward": 1, "symmetric": 2}[sweep])
-    err = np.linalg.norm(host(z) - ref) / np.linalg.norm(ref)
+    sw = {"forward": 0, "backward": 1, "symmetric": 2}[sweep]
+    ref = oracle.vcycle(dims, r, levels, 1, 1, 1, sw)
+    got = host(z)
+    err = np.linalg.norm(got - ref) / np.linalg.norm(ref)
     assert err <= (1e-12 if dtype == 0 else 1e-4), err
+    # Entry by entry: each of the P stages of the cycle (colour passes,
+    # restrictions, prolongations) adds at most gamma_28 of its row scale;
+    # the sweeps pass earlier errors on without growth (weak diagonal
+    # dominance) and a restriction followed by the coarse cycle at most
+    # doubles them per level, so ||z - z_or||_inf <= 2 P gamma_28
+    # 2^(L-1) max S with S the level-0 row scale (|r| + sum |a_ij||z_j|) / a_ii.
+    passes = 16 if sw == 2 else 8
+    stages = (levels - 1) * (2 * passes + 2) + passes
+    S = (np.abs(r) + oracle.absrow(dims, np.abs(ref)) - 26.0 * np.abs(ref)) / 26.0
+    bound = 2 * stages * gamma(28, U[dtype]) * 2 ** (levels - 1) * S.max()
+    einf = np.max(np.abs(got - ref))
+    print(f"[vcycle {dims} L={levels} {sweep} dtype={dtype}] inf-norm error {einf:.2e} = "
+          f"{einf / bound:.1e} of the bound, normwise {err:.2e}", flush=True)
+    assert einf <= bound
 
 
 def test_rhs_from_x(hp):
@@ -379,6 +492,86 @@ def test_kernels_other_beta(hp, beta, dtype):
     hp.vcycle(P.h, dtype, dev(r, dtype), z)
     ref = oracle.vcycle(dims, r, levels, 1, 1, 1, 0, beta=beta)
     assert np.linalg.norm(host(z) - ref) / np.linalg.norm(ref) <= (1e-12 if dtype == 0 else 1e-4)
+    P.close()
+
+
+def _stored_table(coef, dtype):
+    """The stencil as the library stores it in `dtype` (one round-to-nearest-
+    even from FP64 per entry)."""
+    from tests import refimpl
+    c = np.asarray(coef, dtype=np.float64)
+    return {0: c, 1: refimpl.fl32(c), 2: refimpl.fl16(c), 3: refimpl.flbf16(c)}[dtype]
+
+
+def _random_stencil(seed):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(-1.5, 0.2, 27)
+    c[13] = 0.0
+    c[13] = np.abs(c).sum() + 0.5
+    return c
+
+
+@pytest.mark.parametrize("kind", ["beta=0.3", "general"])
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3])
+def test_kernels_inexact_entries(hp, kind, dtype):
+    """Stencils whose entries are not exact in 16 bits (beta = 0.3: -1.3 and
+    -0.7; a random diagonally dominant stencil): the SpMV, one sweep of each
+    kind and a V-cycle in every matrix precision, against the oracle run on
+    the stencil rounded once to that precision (so the products are exact
+    and the bounds of the exact case apply), and the stored entries differ
+    from the FP64 ones by no more than one rounding."""
+    dims, levels = (16, 12, 20), 3
+    coef = oracle.stencil_from_beta(0.3) if kind == "beta=0.3" else _random_stencil(1500)
+    print(f"[inexact] {kind} dtype={dtype}", flush=True)
+    P = hp.Problem(dims, levels=levels, sweep="forward", coef=coef)
+    c = _stored_table(coef, dtype)
+    if dtype >= 2:
+        assert not np.array_equal(c, coef)
+    cabs = np.abs(c)
+    x = rnd(inputs.uniform(dims, 1501), dtype)
+    y = dev(np.zeros(x.size), dtype)
+    hp.spmv(P.h, 0, dtype, dev(x, dtype), y)
+    ref = oracle.spmv_c(dims, c, x)
+    tol = 2 * gamma(28, U[dtype]) * oracle.spmv_c(dims, cabs, np.abs(x)) + 1e-300
+    assert np.all(np.abs(host(y) - ref) <= tol), np.max(np.abs(host(y) - ref) / tol)
+    for sweep in (0, 1, 2):
+        r = rnd(inputs.uniform(dims, 1502), dtype)
+        z0 = rnd(inputs.uniform(dims, 1503), dtype)
+        zt = dev(z0, dtype)
+        hp.smooth(P.h, 0, dtype, sweep, dev(r, dtype), zt)
+        ref = oracle.gs_c(dims, c, r, z0, sweep)
+        zmax = np.maximum(np.abs(z0), np.abs(ref))
+        S = (np.abs(r) + oracle.spmv_c(dims, cabs, zmax) - c[13] * zmax) / c[13]
+        assert np.max(np.abs(host(zt) - ref)) <= 2 * (16 if sweep == 2 else 8) * gamma(28, U[dtype]) * S.max()
+    r = rnd(inputs.uniform(dims, 1504), dtype)
+    z = dev(np.zeros(r.size), dtype)
+    hp.vcycle(P.h, dtype, dev(r, dtype), z)
+    ref = oracle.vcycle_c(dims, c, r, levels)
+    assert np.linalg.norm(host(z) - ref) / np.linalg.norm(ref) <= (1e-12 if dtype == 0 else 1e-4)
+    if dtype >= 2:
+        # against the unrounded FP64 stencil the 16-bit cycle differs at the 16-bit level
+        ref64 = oracle.vcycle_c(dims, coef, r, levels)
+        assert np.linalg.norm(host(z) - ref64) / np.linalg.norm(ref64) > 1e-5
+    P.close()
+
+
+@pytest.mark.parametrize("precision", ["fp16", "bf16"])
+def test_solve_inexact_entries_16bit(hp, precision):
+    """beta = 0.3 with the multigrid matrices rounded to 16 bits: the FP64
+    outer residual and update still give the FP64 solution of the exact
+    problem (the solve bar against the FP64 oracle)."""
+    dims, levels, beta = (24, 24, 24), 3, 0.3
+    P = hp.Problem(dims, beta=beta, levels=levels, sweep="forward")
+    b = oracle.spmv(dims, inputs.ones(dims), beta=beta)
+    x, st = P.solve(dev(b, 0), tol=1e-9, precision=precision)
+    xh = host(x)
+    xo, sto = oracle.gmres_ir(dims, b, levels=levels, sweep=0, tol=1e-9, beta=beta)
+    x32, st32 = P.solve(dev(b, 0), tol=1e-9, precision="mxp")
+    res = np.linalg.norm(b - oracle.spmv(dims, xh, beta=beta)) / np.linalg.norm(b)
+    dx = np.linalg.norm(xh - xo) / np.linalg.norm(xo)
+    print(f"[16-bit beta=0.3] {precision} iters={st.iters} fp32-matrix iters={st32.iters} "
+          f"oracle fp64={sto.iters} res={res:.2e} dx={dx:.2e}", flush=True)
+    assert st.converged and res <= 1e-9 and dx <= 1e-8
     P.close()
 
 

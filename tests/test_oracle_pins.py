@@ -443,6 +443,46 @@ def test_general_stencil_gs_and_solve(oracle_mod):
     assert np.linalg.norm(x - xs) <= 1e-10 * np.linalg.norm(xs)
 
 
+@pytest.mark.parametrize("sweep", [0, 2])
+def test_general_stencil_vcycle(oracle_mod, sweep):
+    d = (8, 12, 8)
+    c = random_stencil(71)
+    r = inputs.uniform(d, 72)
+    ref = refimpl.vcycle_ref(d, r, 3, 1, 1, 1, sweep, coef=c)
+    got = oracle_mod.vcycle_c(d, c, r, 3, 1, 1, 1, sweep)
+    assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+    cb = oracle_mod.stencil_from_beta(0.5)
+    assert np.array_equal(oracle_mod.vcycle_c(d, cb, r, 3, sweep=sweep), oracle_mod.vcycle(d, r, 3, sweep=sweep))
+
+
+def test_sixteen_bit_rounding_helpers():
+    """The test-side binary16 / bfloat16 rounding: binary16 against numpy's
+    own float64 -> float16 conversion; bfloat16 against the nearest of the
+    two bfloat16 neighbours taken from the binary32 bit patterns (ties to the
+    even pattern); both on random values, ties, subnormals and overflow."""
+    rng = np.random.default_rng(5)
+    v = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-9, 6, 20000),
+                        [0.0, -0.0, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, 65504.0, 65519.0, 65520.0,
+                         2.0 ** -24, 2.0 ** -25, 3 * 2.0 ** -26, -1.3, -0.7]])
+    with np.errstate(over="ignore"):
+        assert np.array_equal(refimpl.fl16(v), v.astype(np.float16).astype(np.float64))
+    w = np.concatenate([rng.standard_normal(20000) * 10.0 ** rng.integers(-30, 30, 20000),
+                        [1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, -1.3, -0.7, 2.0 ** -130]])
+    w = w.astype(np.float32).astype(np.float64)   # binary32 values, so their bits give the neighbours
+    got = refimpl.flbf16(w)
+    f = w.astype(np.float32)
+    exact = f.astype(np.float64) == w
+    bits = f.view(np.uint32)
+    lo = (bits & np.uint32(0xFFFF0000)).view(np.float32).astype(np.float64)
+    hi = ((bits & np.uint32(0xFFFF0000)) + np.uint32(0x10000)).view(np.float32).astype(np.float64)
+    dlo, dhi = np.abs(w - lo), np.abs(hi - w)
+    lo_even = ((bits >> np.uint32(16)) & np.uint32(1)) == 0
+    want = np.where(dlo < dhi, lo, np.where(dhi < dlo, hi, np.where(lo_even, lo, hi)))
+    assert np.all(exact)
+    assert np.array_equal(got, want)
+    assert refimpl.flbf16(-1.3) == -1.296875 and refimpl.fl16(-1.3) == -1.2998046875
+
+
 def test_stencil_correlation_and_adjoint_gradient(oracle_mod):
     """dL/dtheta_s = -lam^T S_s x for L = g^T x, x = A^{-1} b, A^T lam = g;
     checked against the dense products and against central differences of
