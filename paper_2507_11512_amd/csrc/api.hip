@@ -1582,6 +1582,7 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
         check_ptr(lam, "lam");
         check_ptr(x, "x");
         check_ptr(out27, "out27");
+        ensure_common(h);
         ensure_tmp(h, P64);
         const Matrix &A = h->lv[0].A;
         zero_entry(h, h->tmp[0][1], A.g.N, P64);
