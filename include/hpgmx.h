@@ -227,6 +227,18 @@ hpgmx_status hpgmx_rhs_from_x(hpgmx_handle h, const double *x, double *b);
  * 27 doubles of device memory.  Stream-ordered. */
 hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double *x, double *out27);
 
+/* For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the result of
+ * hpgmx_stencil_grad (same arguments, same meaning, FP64 sums in another
+ * order) computed without allocating anything.  Its only scratch is a fixed
+ * device array of the library (1024 x 27 partial sums, 216 KiB per GPU, held
+ * until the process ends), which serves every grid size the handle accepts;
+ * lam and x are read in the natural order, without staging copies.  All
+ * calls on one GPU share that array: calls that overlap on one GPU (other
+ * streams or host threads) race, calls on one stream are safe.  Works
+ * before any solve has run.  Stream-ordered. */
+hpgmx_status hpgmx_stencil_grad_noalloc(hpgmx_handle h, const double *lam, const double *x, double *out27);
+
 /* Per-kernel timing of the last solve run with HPGMX_SOLVE_PROFILE.
  * Kernel ids are HPGMX_K_*; `level` selects the grid for the per-level
  * kernels (ignored otherwise).  Returns the summed device time in ms and the

@@ -14,7 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhpgmx.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["stencil_kernels.hip", "krylov_kernels.hip", "krylov_batch.hip", "batch_kernels.hip", "api.hip"]
+SOURCES = ["stencil_kernels.hip", "krylov_kernels.hip", "krylov_batch.hip", "batch_kernels.hip", "noalloc.hip",
+           "api.hip"]
 HEADERS = ["hpgmx_internal.hpp", "ell_device.hpp", "krylov_device.hpp"]
 ARCH = "gfx950"
 

@@ -1278,7 +1278,7 @@ hpgmx_status create(int nx, int ny, int nz, const Stencil &st, double beta, void
     c->prob.beta = beta;
     c->stencil = st;
     c->stream = (hipStream_t)hip_stream;
-    if (hipGetDevice(&c->device) != hipSuccess) {
+    if (hipGetDevice(&c->device) != hipSuccess || noalloc_setup(c->device) != hipSuccess) {
         delete c;
         return HPGMX_EHIP;
     }
@@ -1592,6 +1592,20 @@ hpgmx_status hpgmx_stencil_grad(hpgmx_handle h, const double *lam, const double 
                                    h->partials, h->ctrl, h->stream);
         hip_check(hipMemcpyAsync(out27, h->ctrl->corr, 27 * sizeof(double), hipMemcpyDeviceToDevice,
                                  h->stream), "hipMemcpyAsync");
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_stencil_grad_noalloc(hpgmx_handle h, const double *lam, const double *x, double *out27)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        check_ready(h);
+        check_ptr(lam, "lam");
+        check_ptr(x, "x");
+        check_ptr(out27, "out27");
+        const Geom &g = h->lv[0].A.g;
+        if (red_blocks(g.N) > kMaxRedBlocks) fail(HPGMX_EINVAL, "grid needs more partial sums than the fixed scratch holds");
+        launch_stencil_correlation_noalloc(h->device, g, lam, x, out27, h->stream);
         return HPGMX_OK;
     });
 }

@@ -192,6 +192,14 @@ void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s);
 // Krylov reductions.
 void launch_stencil_correlation(const Matrix &A, const double *lam, const double *x,
                                 double *partials, Ctrl *ctrl, hipStream_t s);
+// The same correlations from lam and x in the natural order, with the
+// per-workgroup partial sums in a fixed device array of this library
+// (noalloc_scratch_bytes() bytes per device; noalloc_setup(device) must have
+// run with `device` current).  Allocates nothing.
+hipError_t noalloc_setup(int device);
+size_t noalloc_scratch_bytes();
+void launch_stencil_correlation_noalloc(int device, const Geom &g, const double *lam, const double *x,
+                                        double *out27, hipStream_t s);
 void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s);
 void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s);
 // y = A x; with ctrl, y = (A x) * ctrl->colscale[k] (the SpMV of inner step

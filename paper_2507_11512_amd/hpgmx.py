@@ -41,7 +41,8 @@ EXPORTS = ["hpgmx_setup_problem", "hpgmx_setup_problem_stencil", "hpgmx_stencil_
            "hpgmx_last_error", "hpgmx_batch_autotune", "hpgmx_batch_set_tuning",
            "hpgmx_batch_get_tuning", "hpgmx_workspace_bytes_batched", "hpgmx_spmv_batched",
            "hpgmx_smooth_batched", "hpgmx_vcycle_batched", "hpgmx_gmres_ir_solve_batched",
-           "hpgmx_presmooth_restrict", "hpgmx_presmooth_restrict_batched", "hpgmx_krylov_cycle_get"]
+           "hpgmx_presmooth_restrict", "hpgmx_presmooth_restrict_batched", "hpgmx_krylov_cycle_get",
+           "hpgmx_stencil_grad_noalloc"]
 
 
 class ProblemDesc(C.Structure):
@@ -84,6 +85,7 @@ def _load():
         "hpgmx_setup_problem": [C.POINTER(ProblemDesc), vp, C.POINTER(H)],
         "hpgmx_setup_problem_stencil": [C.POINTER(StencilDesc), vp, C.POINTER(H)],
         "hpgmx_stencil_grad": [H, vp, vp, vp],
+        "hpgmx_stencil_grad_noalloc": [H, vp, vp, vp],
         "hpgmx_workspace_bytes": [H, C.POINTER(MgDesc), i, C.c_uint, C.POINTER(C.c_size_t)],
         "hpgmx_bind_workspace": [H, vp, C.c_size_t],
         "hpgmx_mg_setup": [H, C.POINTER(MgDesc)],
@@ -187,6 +189,11 @@ def setup_problem_stencil(nx, ny, nz, coef27, stream=None):
 def stencil_grad(h, lam, x, out27):
     """out27[t] = sum_i lam_i x_{i + d_t} (device FP64 tensors; out27 has 27 entries)."""
     _check(h, lib.hpgmx_stencil_grad(h, _ptr(lam), _ptr(x), _ptr(out27)))
+
+
+def stencil_grad_noalloc(h, lam, x, out27):
+    """stencil_grad without any device allocation by the library (fixed scratch)."""
+    _check(h, lib.hpgmx_stencil_grad_noalloc(h, _ptr(lam), _ptr(x), _ptr(out27)))
 
 
 def workspace_bytes(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD, restart=30,
