@@ -58,8 +58,9 @@ def parse():
     ap.add_argument("--no-validation", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the timed FP64 phase")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel profile")
-    ap.add_argument("--inner", choices=["fp32", "fp16", "bf16"], default="fp32",
-                    help="inner precision of the mixed-precision solver (fp16/bf16: 16-bit matrices)")
+    ap.add_argument("--inner", choices=["fp32", "fp16", "bf16", "fp16-mg", "bf16-mg"], default="fp32",
+                    help="inner precision of the mixed-precision solver (fp16/bf16: 16-bit matrices; "
+                         "fp16-mg/bf16-mg: matrices and multigrid work vectors in 16 bits)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying captured inner steps")
     ap.add_argument("--nrhs", type=int, default=1,
@@ -103,18 +104,22 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
 
     N = pm.nrows(cfg.dims)
     w = pm.wb(dtype)
+    mg16 = dtype in (hp.F16_MG, hp.BF16_MG)
+    cast_mg = N * (w + pm.mgb(dtype)) if mg16 else 0   # scaled 16-bit copy of the V-cycle input
     for kk in cycles:
         B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
         B[(hp.K_CAST, 0)] += N * (8 + w)
         for k in range(kk):
+            B[(hp.K_CAST, 0)] += cast_mg
             vcyc()
             B[(hp.K_SPMV, 0)] += pm.spmv_bytes(N, dtype)
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, 1)
             B[(hp.K_CGS_DOT, 0)] += pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
         B[(hp.K_GEMV, 0)] += N * (kk + 1) * w
+        B[(hp.K_CAST, 0)] += cast_mg
         vcyc()
-        B[(hp.K_UPDATE, 0)] += N * (16 + w)
+        B[(hp.K_UPDATE, 0)] += N * (16 + pm.mgb(dtype))
     B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
     B[(hp.K_PERMUTE, 0)] += 3 * 2 * N * 8
     return B
@@ -268,7 +273,8 @@ def main():
     # ---- 4a. per-kernel profile (HIP events around each launch) ---------------------------
     kernels = {}
     dominant = None
-    inner_code = {"fp32": hp.F32, "fp16": hp.F16, "bf16": hp.BF16}[args.inner]
+    inner_code = {"fp32": hp.F32, "fp16": hp.F16, "bf16": hp.BF16, "fp16-mg": hp.F16_MG,
+                  "bf16-mg": hp.BF16_MG}[args.inner]
     prof_precs = () if args.no_profile else (("mxp", inner_code),) if args.no_fp64 else (("mxp", inner_code), ("fp64", hp.F64))
     for prec, dt_code in prof_precs:
         _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], profile=True)
@@ -328,7 +334,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)"}[args.inner]
+        "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)",
+                  "fp16-mg": "f32 (f16 matrices and multigrid vectors)",
+                  "bf16-mg": "f32 (bf16 matrices and multigrid vectors)"}[args.inner]
                  + "-inner/f64-outer",
         "data": "synthetic: generated 27-point stencil, b = A*1, x0 = 0",
         "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta={args.beta:g}, GMRES({m})-IR ({args.inner} inner), {L}-level "
@@ -402,6 +410,8 @@ def run_batched(args, hp, pm, torch, np):
     k = args.nrhs
     if k > hp.MAX_BATCH:
         raise SystemExit(f"--nrhs must be at most {hp.MAX_BATCH}")
+    if args.inner.endswith("-mg"):
+        raise SystemExit("batched runs keep FP32 multigrid vectors: --inner fp32, fp16 or bf16")
     if args.validation != "standard":
         raise SystemExit("batched runs validate in the standard mode only")
     from paper_2507_11512_amd import driver
@@ -419,7 +429,8 @@ def run_batched(args, hp, pm, torch, np):
         hp.rhs_from_x(P.h, U_[j], B[j])
     torch.cuda.synchronize()
     log(f"setup done in {time.time() - t:.2f}s")
-    inner_code = {"fp32": hp.F32, "fp16": hp.F16, "bf16": hp.BF16}[args.inner]
+    inner_code = {"fp32": hp.F32, "fp16": hp.F16, "bf16": hp.BF16, "fp16-mg": hp.F16_MG,
+                  "bf16-mg": hp.BF16_MG}[args.inner]
     tuning = {}
     if not args.no_autotune:
         for name, code in ((args.inner, inner_code), ("fp64", hp.F64)):
@@ -516,7 +527,9 @@ def run_batched(args, hp, pm, torch, np):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)"}[args.inner]
+        "dtype": {"fp32": "f32", "fp16": "f32 (f16 matrices)", "bf16": "f32 (bf16 matrices)",
+                  "fp16-mg": "f32 (f16 matrices and multigrid vectors)",
+                  "bf16-mg": "f32 (bf16 matrices and multigrid vectors)"}[args.inner]
                  + "-inner/f64-outer",
         "data": f"synthetic: generated 27-point stencil, b_j = A u_j, u_j ~ N(0,1) seeded 11512+j, x0 = 0",
         "config": {"workload": f"hpg-mxp batched {n}^3 27-pt nonsym beta={args.beta:g}, {k} right-hand sides, "

@@ -16,7 +16,10 @@
  *    ordering is never visible through the ABI.
  *  - Vectors are float64 for HPGMX_F64 and float32 for HPGMX_F32, HPGMX_F16
  *    and HPGMX_BF16 (the 16-bit types describe how the matrix is stored; the
- *    vectors stay float32).
+ *    vectors stay float32), and binary16 / bfloat16 for HPGMX_F16_MG /
+ *    HPGMX_BF16_MG, except the output of hpgmx_spmv, which is float32 (the
+ *    SpMV of the solver feeds the FP32 Krylov basis).  The batched entry
+ *    points accept HPGMX_F64 .. HPGMX_BF16 only.
  *  - The caller owns every pointer it passes.  The library owns its
  *    matrices, hierarchy and Krylov workspace: they live in memory the caller
  *    bound with hpgmx_bind_workspace, or else in memory the library
@@ -55,7 +58,17 @@ typedef enum {
     HPGMX_ENONFINITE = -5  /* NaN or Inf in the right-hand side or residual  */
 } hpgmx_status;
 
-typedef enum { HPGMX_F64 = 0, HPGMX_F32 = 1, HPGMX_F16 = 2, HPGMX_BF16 = 3 } hpgmx_dtype;
+/* Precisions.  HPGMX_F64: everything in FP64.  HPGMX_F32: FP32 matrices,
+ * multigrid vectors and Krylov basis.  HPGMX_F16 / HPGMX_BF16: the multigrid
+ * matrices stored in binary16 / bfloat16, everything else as HPGMX_F32.
+ * HPGMX_F16_MG / HPGMX_BF16_MG: the whole multigrid hierarchy in 16 bits --
+ * the matrices and the work vectors of every level (the residuals r_l and
+ * corrections z_l) -- with FP32 arithmetic and an FP32 Krylov basis (the
+ * low-precision preconditioner the paper leaves as future work, Sec. 5). */
+typedef enum {
+    HPGMX_F64 = 0, HPGMX_F32 = 1, HPGMX_F16 = 2, HPGMX_BF16 = 3,
+    HPGMX_F16_MG = 4, HPGMX_BF16_MG = 5
+} hpgmx_dtype;
 
 typedef enum {
     HPGMX_GS_FORWARD = 0,   /* colours 0..7: the smoother of Sec. 3           */
@@ -106,7 +119,10 @@ typedef struct {
  * (strict "<").  inner_dtype selects the precision of the steps Alg. 3
  * allows in low precision: HPGMX_F64 gives the plain FP64 GMRES-MG,
  * HPGMX_F32 the FP32-inner GMRES-IR, HPGMX_F16 / HPGMX_BF16 the FP32-inner
- * solver with the multigrid matrices stored in 16 bits.  The outer residual
+ * solver with the multigrid matrices stored in 16 bits, HPGMX_F16_MG /
+ * HPGMX_BF16_MG with the whole multigrid hierarchy in 16 bits (the V-cycle's
+ * input is the Krylov vector times a power of two that brings its entries
+ * near 1, inside binary16's range; the SpMV and the update undo it).  The outer residual
  * and the solution update are always FP64.  If res_hist_host is not NULL the
  * estimated relative residual after each inner step is written there (host
  * memory, res_hist_len entries at most). */

@@ -277,23 +277,73 @@ void or_restrict_fused(int nx, int ny, int nz, double beta, int fo,
 }
 
 /* ------------------------------------------------------------------------- */
-/* FP32 storage emulation.  With f32 set, every vector element that the      */
-/* mixed-precision method keeps in low precision (Alg. 3, steps in blue) is  */
-/* rounded to binary32 (round to nearest even) when stored; arithmetic stays */
-/* in binary64.  Stored in binary32: q_1, the multigrid work vectors after   */
-/* every sweep, restriction and correction, z = M^{-1} q_k, w = A z, each    */
-/* Gram-Schmidt update, q_{k+1} and the end-of-cycle u = Q y.  Inner         */
-/* products, H, the rotations and x stay binary64.  Pinned by rebuilding    */
-/* each stored quantity of a cycle from independent pieces with the same     */
-/* rounding (tests/test_oracle_pins.py, "binary32 storage").                */
+/* Low-precision storage emulation (the argument `f32`, a storage mode).     */
+/*   0: everything binary64 (the plain method);                               */
+/*   1: every vector element that the mixed-precision method keeps in low    */
+/*      precision (Alg. 3, steps in blue) is rounded to binary32 (round to   */
+/*      nearest even) when stored; arithmetic stays in binary64.  Stored in  */
+/*      binary32: q_1, the multigrid work vectors after every sweep,         */
+/*      restriction and correction, z = M^{-1} q_k, w = A z, each            */
+/*      Gram-Schmidt update, q_{k+1} and the end-of-cycle u = Q y.  Inner    */
+/*      products, H, the rotations and x stay binary64;                      */
+/*   2, 3: as 1, but the multigrid work vectors of every level (the V-cycle's */
+/*      input, each sweep, restriction and correction, and its output z) are  */
+/*      rounded to binary16 (2) or bfloat16 (3) instead: the whole multigrid  */
+/*      hierarchy in 16 bits.  The V-cycle is applied to sigma q (q a unit    */
+/*      vector, sigma the power of two nearest sqrt(N), so that the entries  */
+/*      are of order one, inside binary16's range) and its result divided by */
+/*      sigma: w = A z / sigma; at the end of a cycle to sigma u with sigma  */
+/*      the power of two nearest sqrt(N) / ||y||, and x += z / sigma.  The    */
+/*      powers of two make the scalings exact.                                */
+/* Pinned by rebuilding each stored quantity of a cycle from independent     */
+/* pieces with the same rounding (tests/test_oracle_pins.py, "storage").     */
 /* ------------------------------------------------------------------------- */
-static inline double st(double v, int f32) { return f32 ? (double)(float)v : v; }
+
+/* Round to nearest (ties to even) in a binary format with p significand bits
+ * (leading one included), smallest normal exponent emin and largest finite
+ * value maxv (IEEE 754): the quantum of x is 2^(e - p + 1) with 2^e the
+ * leading bit of |x| (fixed at 2^(emin - p + 1) below the normal range). */
+static double round_format(double x, int p, int emin, double maxv)
+{
+    if (x == 0.0 || !isfinite(x)) return x;
+    int e;
+    (void)frexp(x, &e); /* |x| = f 2^e, f in [0.5, 1): leading bit 2^(e-1) */
+    int lead = e - 1 < emin ? emin : e - 1;
+    double r = ldexp(nearbyint(ldexp(x, -(lead - (p - 1)))), lead - (p - 1));
+    return fabs(r) > maxv ? copysign(INFINITY, x) : r;
+}
+
+static inline double fl32(double v) { return (double)(float)v; }
+static inline double fl16(double v) { return round_format(v, 11, -14, 65504.0); }
+static inline double flbf16(double v) { return round_format(v, 8, -126, 0x1.fep127); }
+
+/* a stored Krylov quantity (binary32 in every low-precision mode) */
+static inline double st(double v, int f32) { return f32 ? fl32(v) : v; }
 
 static void round_vec(double *v, idx_t n, int f32)
 {
     if (!f32) return;
 #pragma omp parallel for schedule(static)
-    for (idx_t i = 0; i < n; ++i) v[i] = (double)(float)v[i];
+    for (idx_t i = 0; i < n; ++i) v[i] = fl32(v[i]);
+}
+
+/* a stored multigrid work vector */
+static inline double st_mg(double v, int mode)
+{
+    return mode == 1 ? fl32(v) : mode == 2 ? fl16(v) : mode == 3 ? flbf16(v) : v;
+}
+
+static void round_mg(double *v, idx_t n, int mode)
+{
+    if (!mode) return;
+#pragma omp parallel for schedule(static)
+    for (idx_t i = 0; i < n; ++i) v[i] = st_mg(v[i], mode);
+}
+
+static double pow2_near(double v)
+{
+    if (!(v > 0.0) || !isfinite(v)) return 1.0;
+    return ldexp(1.0, (int)nearbyint(log2(v)));
 }
 
 /* ------------------------------------------------------------------------- */
@@ -319,26 +369,26 @@ static void mg_apply(const mgparam *p, int l, int nx, int ny, int nz,
     if (l == p->levels - 1) {
         for (int s = 0; s < p->coarsest; ++s) {
             or_gs_c(nx, ny, nz, p->c27, p->sweep, r, z);
-            round_vec(z, n, p->f32);
+            round_mg(z, n, p->f32);
         }
         return;
     }
     for (int s = 0; s < p->pre; ++s) {
         or_gs_c(nx, ny, nz, p->c27, p->sweep, r, z);
-        round_vec(z, n, p->f32);
+        round_mg(z, n, p->f32);
     }
     int cx = nx / 2, cy = ny / 2, cz = nz / 2;
     idx_t nc = (idx_t)cx * cy * cz;
     double *rc = (double *)malloc((size_t)nc * sizeof(double));
     double *zc = (double *)malloc((size_t)nc * sizeof(double));
     restrict_fused_c(nx, ny, nz, p->c27, r, z, rc);
-    round_vec(rc, nc, p->f32);
+    round_mg(rc, nc, p->f32);
     mg_apply(p, l + 1, cx, cy, cz, rc, zc);
     or_prolong_add(nx, ny, nz, zc, z);
-    round_vec(z, n, p->f32);
+    round_mg(z, n, p->f32);
     for (int s = 0; s < p->post; ++s) {
         or_gs_c(nx, ny, nz, p->c27, p->sweep, r, z);
-        round_vec(z, n, p->f32);
+        round_mg(z, n, p->f32);
     }
     free(rc);
     free(zc);
@@ -381,7 +431,10 @@ typedef struct {
  * Solves A x = b.  x holds the initial guess on entry and the result on exit.
  *   levels >= 1 : right preconditioner M^{-1} = one V-cycle (levels deep);
  *   levels == 0 : no preconditioner (M = I), used by the finite-termination pin.
- *   f32         : round the low-precision quantities of Alg. 3 to binary32.
+ *   f32         : storage mode 0..3 (see "Low-precision storage emulation"):
+ *                 1 rounds the low-precision quantities of Alg. 3 to
+ *                 binary32, 2 / 3 in addition keep the multigrid hierarchy's
+ *                 vectors in binary16 / bfloat16.
  * Readings (Alg. 3): rho0 = ||b||; convergence tests are strict "<"; the
  * projected system is solved over the k steps actually taken (the loop may
  * end early); the Givens rotations of earlier columns are applied through
@@ -420,6 +473,7 @@ int or_gmres_ir_c(int nx, int ny, int nz, const double *c27, int levels, int pre
     if (!Q || !H || !t || !cs || !sn || !y || !r || !z || !hc) { rc_status = -2; goto done; }
 
     double rho0 = sqrt(dot(b, b, n));
+    const double sig = pow2_near(sqrt((double)n)); /* 16-bit hierarchy: V-cycle input scale */
     stats->rho0 = rho0;
     if (rho0 == 0.0) {
         memset(x, 0, (size_t)n * sizeof(double));
@@ -447,11 +501,19 @@ int or_gmres_ir_c(int nx, int ny, int nz, const double *c27, int levels, int pre
             if (rho / rho0 < tol) break;
             double *qk = Q + (size_t)k * n, *w = Q + (size_t)(k + 1) * n;
             /* z = M^{-1} q_k ; w = A z */
-            if (levels >= 1) mg_apply(&mp, 0, nx, ny, nz, qk, z);
-            else memcpy(z, qk, (size_t)n * sizeof(double));
-            round_vec(z, n, f32);
-            or_spmv_c(nx, ny, nz, c27, z, w);
-            round_vec(w, n, f32);
+            if (f32 >= 2 && levels >= 1) {
+                /* 16-bit hierarchy: the cycle runs on sigma q_k */
+                for (idx_t i = 0; i < n; ++i) r[i] = st_mg(sig * qk[i], f32);
+                mg_apply(&mp, 0, nx, ny, nz, r, z);
+                or_spmv_c(nx, ny, nz, c27, z, w);
+                for (idx_t i = 0; i < n; ++i) w[i] = fl32(w[i] / sig);
+            } else {
+                if (levels >= 1) mg_apply(&mp, 0, nx, ny, nz, qk, z);
+                else memcpy(z, qk, (size_t)n * sizeof(double));
+                round_vec(z, n, f32);
+                or_spmv_c(nx, ny, nz, c27, z, w);
+                round_vec(w, n, f32);
+            }
             /* CGS2: two classical Gram-Schmidt passes, H(1:k,k) = h1 + h2. */
             for (int j = 0; j <= k; ++j) H[(size_t)k * (m + 1) + j] = 0.0;
             for (int pass = 0; pass < 2; ++pass) {
@@ -513,10 +575,19 @@ int or_gmres_ir_c(int nx, int ny, int nz, const double *c27, int levels, int pre
             for (int j = 0; j < kk; ++j) acc += Q[(size_t)j * n + i] * y[j];
             r[i] = st(acc, f32);
         }
-        if (levels >= 1) mg_apply(&mp, 0, nx, ny, nz, r, z);
-        else memcpy(z, r, (size_t)n * sizeof(double));
-        round_vec(z, n, f32);
-        for (idx_t i = 0; i < n; ++i) x[i] += z[i];
+        if (f32 >= 2 && levels >= 1) {
+            double y2 = 0.0;
+            for (int j = 0; j < kk; ++j) y2 += y[j] * y[j];
+            const double su = pow2_near(sqrt((double)n) / sqrt(y2));
+            for (idx_t i = 0; i < n; ++i) r[i] = st_mg(su * r[i], f32);
+            mg_apply(&mp, 0, nx, ny, nz, r, z);
+            for (idx_t i = 0; i < n; ++i) x[i] += z[i] / su;
+        } else {
+            if (levels >= 1) mg_apply(&mp, 0, nx, ny, nz, r, z);
+            else memcpy(z, r, (size_t)n * sizeof(double));
+            round_vec(z, n, f32);
+            for (idx_t i = 0; i < n; ++i) x[i] += z[i];
+        }
         stats->restarts += 1;
     }
     stats->iters = its;

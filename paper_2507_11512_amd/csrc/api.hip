@@ -35,19 +35,25 @@ inline size_t round_up(size_t b) { return (b + kAlign - 1) / kAlign * kAlign; }
 
 struct Level {
     Matrix A;
-    void *r[2] = {nullptr, nullptr};  // work vectors, [0] double, [1] float (levels >= 1)
-    void *z[2] = {nullptr, nullptr};
+    // work vectors (levels >= 1) per multigrid vector type: [0] double,
+    // [1] float, [2] __half, [3] bf16
+    void *r[4] = {nullptr, nullptr, nullptr, nullptr};
+    void *z[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 struct Krylov {
     int m = 0;
     i64 ldq = 0;        // leading dimension of Q (N rounded up, plus a skew)
     void *Q = nullptr;  // (m + 1) columns of ldq
-    void *z = nullptr;
-    void *u = nullptr;
+    void *z = nullptr;  // V-cycle output (multigrid vector type), SpMV input
+    void *u = nullptr;  // end-of-cycle Q y (Krylov type)
+    void *r0 = nullptr; // 16-bit hierarchy: the scaled V-cycle input
 };
 
-inline int vt_of(Prec p) { return p == P64 ? 0 : 1; }
+// Index of the multigrid vector type: 0 double, 1 float, 2 __half, 3 bf16.
+inline int vt_of(Prec p) { return p == P64 ? 0 : p == P16V ? 2 : p == PB16V ? 3 : 1; }
+// Element type of the multigrid vectors of p at the ABI.
+inline Prec vprec(Prec p) { return p == P64 ? P64 : mg16(p) ? p : P32; }
 
 // Tile table of the batched stencil kernels: R (right-hand sides per lane)
 // per kernel kind and level; 0 = the fixed rule.
@@ -89,13 +95,13 @@ struct hpgmx_ctx {
     size_t ws_size = 0, ws_used = 0;
     std::vector<void *> owned;
 
-    Krylov kry[4];
+    Krylov kry[kNumPrec];
     double *b_int = nullptr, *x_int = nullptr, *r64 = nullptr;
     double *partials = nullptr;
     Ctrl *ctrl = nullptr;
     double *host_scal = nullptr;   // pinned copies of the Ctrl scalar block (2 slots)
     hipEvent_t ev_scal[2] = {nullptr, nullptr};  // scalar copy of slot s has landed
-    void *tmp[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+    void *tmp[4][3] = {};  // ABI staging per multigrid vector type (vt_of)
 
     // hipGraph replay of inner steps: a private stream (default priority) that
     // can be captured, and one instantiated graph per (dtype, k, m).
@@ -108,8 +114,8 @@ struct hpgmx_ctx {
 
     // the last restart cycle of the last single solve, per inner dtype:
     // steps taken and restart length (hpgmx_krylov_cycle_get)
-    int last_k[4] = {-1, -1, -1, -1};
-    int last_m[4] = {0, 0, 0, 0};
+    int last_k[kNumPrec] = {-1, -1, -1, -1, -1, -1};
+    int last_m[kNumPrec] = {};
 
     void drop_graphs()
     {
@@ -222,6 +228,7 @@ int ell_chunk_log2()
 
 void alloc_matrix_prec(hpgmx_ctx *c, Matrix &A, Prec p)
 {
+    p = matrix_prec(p);
     const size_t N = (size_t)A.g.N, E = (size_t)ell_entries(A.g.N, A.clog2);
     switch (p) {
     case P64:
@@ -236,16 +243,18 @@ void alloc_matrix_prec(hpgmx_ctx *c, Matrix &A, Prec p)
     case PB16:
         if (!A.vb16) { A.vb16 = (bf16 *)c->dalloc(E * 2); A.db16 = (bf16 *)c->dalloc(N * 2); }
         break;
+    default: break;  // the 16-bit hierarchies use the P16 / PB16 values
     }
 }
 
 bool has_prec(const Matrix &A, Prec p)
 {
-    switch (p) {
+    switch (matrix_prec(p)) {
     case P64: return A.v64 != nullptr;
     case P32: return A.v32 != nullptr;
     case P16: return A.v16 != nullptr;
     case PB16: return A.vb16 != nullptr;
+    default: break;
     }
     return false;
 }
@@ -253,6 +262,7 @@ bool has_prec(const Matrix &A, Prec p)
 // Generates the values of precision p on every level (and the columns once).
 void ensure_prec(hpgmx_ctx *c, Prec p)
 {
+    p = matrix_prec(p);
     for (auto &L : c->lv) {
         if (has_prec(L.A, p)) continue;
         alloc_matrix_prec(c, L.A, p);
@@ -330,12 +340,13 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
                 if (*it == K.Q) { (void)hipFree(K.Q); c->owned.erase(it); break; }
         }
         K.ldq = krylov_ldq((i64)N0);
-        K.Q = c->dalloc((size_t)K.ldq * (m + 1) * vec_bytes(p));
+        K.Q = c->dalloc((size_t)K.ldq * (m + 1) * vec_bytes(basis_prec(p)));
         K.m = m;
     }
     if (!K.z) {
         K.z = gathered_vector(c, (i64)N0, p);
-        K.u = c->dalloc(N0 * vec_bytes(p));
+        K.u = c->dalloc(N0 * vec_bytes(basis_prec(p)));
+        if (mg16(p)) K.r0 = c->dalloc(N0 * vec_bytes(p));
     }
     ensure_level_vectors(c, p);
     ensure_prec(c, p);
@@ -346,40 +357,48 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
 {
     size_t tot = 0;
     auto add = [&](size_t b) { tot += round_up(b ? b : 1); };
+    static const size_t vt_bytes[4] = {8, 4, 2, 2};
+    bool mat[4] = {true, false, false, false};  // FP64 values always (outer residual)
+    bool vt_used[4] = {true, false, false, false};  // FP64 staging always
+    for (int p = 0; p < kNumPrec; ++p) {
+        if (!((mask >> p) & 1u)) continue;
+        mat[matrix_prec((Prec)p)] = true;
+        vt_used[vt_of((Prec)p)] = true;
+        if (p != P64) vt_used[1] = true;  // FP32 staging (the SpMV output of the 16-bit hierarchy)
+    }
     int nx = pd.nx, ny = pd.ny, nz = pd.nz;
     const size_t N0 = (size_t)nx * ny * nz;
     for (int l = 0; l < mg.levels; ++l) {
         const size_t N = (size_t)nx * ny * nz;
         const size_t E = (size_t)ell_entries((i64)N, ell_chunk_log2());
-        add(E * 4);                                       // columns
-        for (int p = 0; p < 4; ++p) {
-            const bool want = (mask >> p) & 1u || p == P64;  // FP64 always (outer residual)
-            if (!want) continue;
-            const size_t vb = p == P64 ? 8 : p == P32 ? 4 : 2;
+        add(E * 4);  // columns
+        for (int q = 0; q < 4; ++q) {
+            if (!mat[q]) continue;
+            const size_t vb = q == P64 ? 8 : q == P32 ? 4 : 2;
             add(E * vb);
             add(N * vb);
         }
-        if (l >= 1) {
-            for (int vt = 0; vt < 2; ++vt) {
-                const bool want = vt == 0 ? (mask & 1u) : (mask & 0xEu);
-                if (want) { add((N + 1) * (vt == 0 ? 8 : 4)); add((N + 1) * (vt == 0 ? 8 : 4)); }
+        if (l >= 1)
+            for (int vt = 0; vt < 4; ++vt) {
+                const bool want = vt == 0 ? (mask & 1u) != 0 : vt == 1 ? (mask & 0xEu) != 0
+                                                                       : (mask >> (vt + 2)) & 1u;
+                if (want) { add((N + 1) * vt_bytes[vt]); add((N + 1) * vt_bytes[vt]); }
             }
-        }
         nx /= 2; ny /= 2; nz /= 2;
     }
     add(sizeof(Ctrl));
     add((size_t)kMaxRedBlocks * kMaxBasis * 8);
-    add(N0 * 8); add((N0 + 1) * 8); add(N0 * 8);          // b, x, r in FP64
-    for (int p = 0; p < 4; ++p) {
+    add(N0 * 8); add((N0 + 1) * 8); add(N0 * 8);  // b, x, r in FP64
+    for (int p = 0; p < kNumPrec; ++p) {
         if (!((mask >> p) & 1u)) continue;
-        const size_t vb = p == P64 ? 8 : 4;
-        add((size_t)krylov_ldq((i64)N0) * (m + 1) * vb);
-        add((N0 + 1) * vb); add(N0 * vb);
+        const size_t kb = vec_bytes(basis_prec((Prec)p)), vb = vec_bytes((Prec)p);
+        add((size_t)krylov_ldq((i64)N0) * (m + 1) * kb);
+        add((N0 + 1) * vb);
+        add(N0 * kb);
+        if (mg16((Prec)p)) add(N0 * vb);
     }
-    for (int vt = 0; vt < 2; ++vt) {                       // ABI staging buffers
-        const bool want = vt == 0 ? true : (mask & 0xEu) != 0;
-        if (want) for (int i = 0; i < 3; ++i) add((N0 + 1) * (vt == 0 ? 8 : 4));
-    }
+    for (int vt = 0; vt < 4; ++vt)  // ABI staging buffers
+        if (vt_used[vt]) for (int i = 0; i < 3; ++i) add((N0 + 1) * vt_bytes[vt]);
     return tot;
 }
 
@@ -579,7 +598,9 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
     const Matrix &A0 = c->lv[0].A;
     const Geom &g0 = A0.g;
     const i64 N = g0.N;
-    const size_t vb = vec_bytes(p);
+    const Prec bp = basis_prec(p);  // Krylov vectors: FP64 or FP32
+    const bool mg = mg16(p);        // 16-bit multigrid hierarchy
+    const size_t vb = vec_bytes(bp);
     char *Q = (char *)K.Q;
     const i64 ldq = K.ldq;
     auto col = [&](int j) { return (void *)(Q + (size_t)j * ldq * vb); };
@@ -636,7 +657,7 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             if (its >= d->max_iters) break;
             {
                 ProfScope ps(c, HPGMX_K_CAST, 0);
-                launch_cast(N, 1, p, c->r64, c->ctrl, col(0), c->stream);
+                launch_cast(N, 1, bp, c->r64, c->ctrl, col(0), c->stream);
             }
             int kk = 0;
             ensure_scal_events(c);
@@ -644,22 +665,30 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             // then the copy of its scalars (see enqueue_scal)
             auto run_step = [&](int k) {
                 auto step = [&]() {
-                    vcycle(c, 0, p, col(k), K.z);
+                    if (mg) {
+                        {
+                            ProfScope ps(c, HPGMX_K_CAST, 0);
+                            launch_cast_mg(N, p, (const float *)col(k), c->ctrl, false, k, K.r0, c->stream);
+                        }
+                        vcycle(c, 0, p, K.r0, K.z);
+                    } else {
+                        vcycle(c, 0, p, col(k), K.z);
+                    }
                     {
                         ProfScope ps(c, HPGMX_K_SPMV, 0);
                         launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_DOT, 0);
-                        launch_dot(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                        launch_dot(N, 1, bp, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
-                        launch_cgs_dot(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
+                        launch_cgs_dot(N, 1, bp, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
-                        launch_cgs_norm(N, 1, p, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
+                        launch_cgs_norm(N, 1, bp, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
                     }
                 };
                 if (use_graph) replay_step(c, std::make_tuple((int)p, k, m, 1), step);
@@ -693,12 +722,20 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             c->last_m[p] = m;
             {
                 ProfScope ps(c, HPGMX_K_GEMV, 0);
-                launch_gemv(N, 1, p, K.Q, ldq, kk, c->ctrl, K.u, c->stream);
+                launch_gemv(N, 1, bp, K.Q, ldq, kk, c->ctrl, K.u, c->stream);
             }
-            vcycle(c, 0, p, K.u, K.z);
+            if (mg) {
+                {
+                    ProfScope ps(c, HPGMX_K_CAST, 0);
+                    launch_cast_mg(N, p, (const float *)K.u, c->ctrl, true, kk, K.r0, c->stream);
+                }
+                vcycle(c, 0, p, K.r0, K.z);
+            } else {
+                vcycle(c, 0, p, K.u, K.z);
+            }
             {
                 ProfScope ps(c, HPGMX_K_UPDATE, 0);
-                launch_update(N, p, K.z, c->x_int, c->stream);
+                launch_update(N, p, K.z, c->x_int, c->stream, c->ctrl);
             }
             ++S.restarts;
         }
@@ -1195,7 +1232,7 @@ void check_ready(hpgmx_ctx *c)
 
 Prec check_dtype(int dtype)
 {
-    if (dtype < HPGMX_F64 || dtype > HPGMX_BF16) fail(HPGMX_EINVAL, "dtype out of range");
+    if (dtype < HPGMX_F64 || dtype > HPGMX_BF16_MG) fail(HPGMX_EINVAL, "dtype out of range");
     return (Prec)dtype;
 }
 
@@ -1210,7 +1247,12 @@ void check_ptr(const void *p, const char *name)
     if (!p) fail(HPGMX_EINVAL, std::string(name) + " is NULL");
 }
 
-Prec check_batch_dtype(int dtype) { return check_dtype(dtype); }
+Prec check_batch_dtype(int dtype)
+{
+    const Prec p = check_dtype(dtype);
+    if (mg16(p)) fail(HPGMX_EINVAL, "the batched solver keeps FP32 multigrid vectors (dtype 0..3)");
+    return p;
+}
 
 void check_nrhs(int nrhs)
 {
@@ -1317,7 +1359,7 @@ hpgmx_status hpgmx_workspace_bytes(hpgmx_handle h, const hpgmx_mg_desc *mg, int 
         check_ptr(bytes, "bytes");
         if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
         if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
-        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0xFu);
+        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0x3Fu);
         return HPGMX_OK;
     });
 }
@@ -1399,11 +1441,13 @@ hpgmx_status hpgmx_spmv(hpgmx_handle h, int level, int dtype, const void *x, voi
         ensure_tmp(h, p);
         const int vt = vt_of(p);
         const Matrix &A = h->lv[level].A;
-        const Prec pv = p == P64 ? P64 : P32;
+        const Prec pv = vprec(p), py = basis_prec(p);  // y is a Krylov vector
+        ensure_tmp(h, py);
+        void *ty = h->tmp[vt_of(py)][1];
         zero_entry(h, h->tmp[vt][0], A.g.N, pv);
         launch_nat2int(A.g, pv, x, pv, h->tmp[vt][0], h->stream);
-        launch_spmv(A, p, h->tmp[vt][0], h->tmp[vt][1], h->stream);
-        launch_int2nat(A.g, pv, h->tmp[vt][1], pv, y, h->stream);
+        launch_spmv(A, p, h->tmp[vt][0], ty, h->stream);
+        launch_int2nat(A.g, py, ty, py, y, h->stream);
         return HPGMX_OK;
     });
 }
@@ -1422,7 +1466,7 @@ hpgmx_status hpgmx_smooth(hpgmx_handle h, int level, int dtype, int sweep, const
         ensure_tmp(h, p);
         const int vt = vt_of(p);
         const Matrix &A = h->lv[level].A;
-        const Prec pv = p == P64 ? P64 : P32;
+        const Prec pv = vprec(p);
         zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         if (!zero_guess) launch_nat2int(A.g, pv, z, pv, h->tmp[vt][1], h->stream);
@@ -1444,7 +1488,7 @@ hpgmx_status hpgmx_vcycle(hpgmx_handle h, int dtype, const void *r, void *z)
         ensure_level_vectors(h, p);
         const int vt = vt_of(p);
         const Matrix &A = h->lv[0].A;
-        const Prec pv = p == P64 ? P64 : P32;
+        const Prec pv = vprec(p);
         zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         vcycle(h, 0, p, h->tmp[vt][0], h->tmp[vt][1]);
@@ -1468,7 +1512,7 @@ hpgmx_status hpgmx_restrict_residual(hpgmx_handle h, int level, int dtype, const
         const int vt = vt_of(p);
         const Matrix &A = h->lv[level].A;
         const Geom &gc = h->lv[level + 1].A.g;
-        const Prec pv = p == P64 ? P64 : P32;
+        const Prec pv = vprec(p);
         zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         launch_nat2int(A.g, pv, z, pv, h->tmp[vt][1], h->stream);
@@ -1495,7 +1539,7 @@ hpgmx_status hpgmx_presmooth_restrict(hpgmx_handle h, int level, int dtype, int 
         const int vt = vt_of(p);
         const Matrix &A = h->lv[level].A;
         const Geom &gc = h->lv[level + 1].A.g;
-        const Prec pv = p == P64 ? P64 : P32;
+        const Prec pv = vprec(p);
         zero_entry(h, h->tmp[vt][1], A.g.N, pv);
         launch_nat2int(A.g, pv, r, pv, h->tmp[vt][0], h->stream);
         presmooth_restrict(h, level, p, sweep, nsweeps, h->tmp[vt][0], h->tmp[vt][1], h->tmp[vt][2]);
@@ -1517,11 +1561,12 @@ hpgmx_status hpgmx_krylov_cycle_get(hpgmx_handle h, int dtype, int *k, double *Q
         *k = kk;
         const Krylov &K = h->kry[p];
         const Geom &g0 = h->lv[0].A.g;
-        const size_t vb = vec_bytes(p);
+        const Prec bp = basis_prec(p);
+        const size_t vb = vec_bytes(bp);
         if (Q)
             for (int j = 0; j <= kk; ++j)
-                launch_int2nat(g0, p == P64 ? P64 : P32, (const char *)K.Q + (size_t)j * K.ldq * vb, P64,
-                               Q + (size_t)j * g0.N, h->stream);
+                launch_int2nat(g0, bp, (const char *)K.Q + (size_t)j * K.ldq * vb, P64, Q + (size_t)j * g0.N,
+                               h->stream);
         if (scale)
             hip_check(hipMemcpyAsync(scale, h->ctrl->colscale, (size_t)(kk + 1) * 8, hipMemcpyDeviceToHost,
                                      h->stream), "hipMemcpyAsync");
@@ -1550,7 +1595,7 @@ hpgmx_status hpgmx_prolong_add(hpgmx_handle h, int level, int dtype, const void 
         const int vt = vt_of(p);
         const Geom &gf = h->lv[level].A.g;
         const Geom &gc = h->lv[level + 1].A.g;
-        const Prec pv = p == P64 ? P64 : P32;
+        const Prec pv = vprec(p);
         launch_nat2int(gc, pv, z_coarse, pv, h->tmp[vt][0], h->stream);
         launch_nat2int(gf, pv, z, pv, h->tmp[vt][1], h->stream);
         launch_prolong(gf, gc, p, h->tmp[vt][0], h->tmp[vt][1], h->stream);

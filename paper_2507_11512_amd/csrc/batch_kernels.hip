@@ -257,8 +257,9 @@ template <typename F> static void with_values(const Matrix &A, Prec p, F &&f)
     case P32: return f(A.v32, A.d32);
     case P16: return f(A.v16, A.d16);
     case PB16: return f(A.vb16, A.db16);
+    default: break;  // 16-bit multigrid vectors are not batched
     }
-    throw std::runtime_error("unknown matrix precision");
+    throw std::runtime_error("unsupported matrix precision for a batched call");
 }
 
 static inline unsigned lanes_grid(i64 rows, int K, int R) { return grid_for(rows * (K / R)); }

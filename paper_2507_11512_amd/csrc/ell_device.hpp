@@ -35,12 +35,20 @@ template <typename T, typename V> __device__ __forceinline__ T to_t(V v) { retur
 template <> __device__ __forceinline__ float to_t<float, __half>(__half v) { return __half2float(v); }
 template <> __device__ __forceinline__ float to_t<float, bf16>(bf16 v) { return __bfloat162float(v); }
 
+// Storing an FP32 result in a vector of element type S rounds to nearest
+// even (IEEE) for the 16-bit types.
+template <typename S, typename T> __device__ __forceinline__ S from_t(T v) { return (S)v; }
+template <> __device__ __forceinline__ __half from_t<__half, float>(float v) { return __float2half(v); }
+template <> __device__ __forceinline__ bf16 from_t<bf16, float>(float v) { return __float2bfloat16(v); }
+
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
-// sum over the slots in MASK of a(p,s) * x[col(p,s)] (slot order).
-template <typename T, typename V, unsigned MASK>
+// sum over the slots in MASK of a(p,s) * x[col(p,s)] (slot order), in the
+// arithmetic type T; x may be stored in a narrower type X (the 16-bit
+// multigrid vectors), widened after the gathers.
+template <typename T, typename V, unsigned MASK, typename X>
 __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const int *__restrict__ offc,
-                                         const T *x, const EllRow &er)
+                                         const X *x, const EllRow &er)
 {
     V a[kSlots];
     int ci[kSlots];
@@ -53,7 +61,7 @@ __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const int *
         }
     }
     sched_fence();
-    T xv[kSlots];
+    X xv[kSlots];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
         if (MASK & (1u << s)) xv[s] = x[ci[s]];
@@ -61,7 +69,7 @@ __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const int *
     T acc = (T)0;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
-        if (MASK & (1u << s)) acc += to_t<T>(a[s]) * xv[s];
+        if (MASK & (1u << s)) acc += to_t<T>(a[s]) * to_t<T>(xv[s]);
     return acc;
 }
 

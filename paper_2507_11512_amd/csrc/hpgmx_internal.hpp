@@ -142,10 +142,23 @@ struct Matrix {
     bf16 *vb16 = nullptr, *db16 = nullptr;
 };
 
-// Precision of a call: vector type double for P64, float otherwise; matrix
-// values in the named type.
-enum Prec { P64 = HPGMX_F64, P32 = HPGMX_F32, P16 = HPGMX_F16, PB16 = HPGMX_BF16 };
-inline size_t vec_bytes(Prec p) { return p == P64 ? 8 : 4; }
+// Precision of a call.  Matrix values: double (P64), float (P32), __half
+// (P16, P16V) or bf16 (PB16, PB16V).  Multigrid vectors: double for P64,
+// float for P32, P16 and PB16, and the 16-bit type of the matrix for P16V and
+// PB16V (the whole hierarchy in 16 bits).  Arithmetic is FP64 for P64 and
+// FP32 otherwise; the Krylov basis is FP64 for P64 and FP32 otherwise.
+enum Prec {
+    P64 = HPGMX_F64, P32 = HPGMX_F32, P16 = HPGMX_F16, PB16 = HPGMX_BF16,
+    P16V = HPGMX_F16_MG, PB16V = HPGMX_BF16_MG
+};
+constexpr int kNumPrec = 6;
+inline bool mg16(Prec p) { return p == P16V || p == PB16V; }
+// Multigrid vector bytes.
+inline size_t vec_bytes(Prec p) { return p == P64 ? 8 : mg16(p) ? 2 : 4; }
+// Precision of the Krylov vectors (basis, u) and of the kernels on them.
+inline Prec basis_prec(Prec p) { return p == P64 ? P64 : P32; }
+// Which value array of the matrix a precision reads.
+inline Prec matrix_prec(Prec p) { return p == P16V ? P16 : p == PB16V ? PB16 : p; }
 
 // Device-side control block of one Krylov cycle (FP64): Hessenberg matrix
 // (rotated) and its unrotated copy, Givens rotations, right-hand side t,
@@ -169,6 +182,11 @@ struct Ctrl {
     double rho, inv_rho, beta, inv_beta, nrm2, rho0;
     int breakdown, nonfinite;
     double corr[27];  // stencil correlation of the adjoint gradient
+    // 16-bit multigrid hierarchy (P16V, PB16V): the V-cycle's input is the
+    // Krylov vector times a power of two sigma that brings its entries near
+    // 1 in magnitude (binary16's range); the consumers undo sigma.
+    double mg_post;   // SpMV output scale of the inner step: colscale[k] / sigma
+    double mg_inv;    // 1 / sigma of the end-of-cycle V-cycle (the update)
 };
 
 // What the finish kernel of a reduction does with the summed partials.
@@ -203,7 +221,9 @@ void launch_stencil_correlation_noalloc(int device, const Geom &g, const double 
 void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s);
 void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s);
 // y = A x; with ctrl, y = (A x) * ctrl->colscale[k] (the SpMV of inner step
-// k, fed with the unnormalised basis column k).
+// k, fed with the unnormalised basis column k), or for the 16-bit hierarchy
+// y = (A x) * ctrl->mg_post.  x in the multigrid vector type of p, y in the
+// Krylov type (FP32 for the 16-bit hierarchy).
 void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
                  const Ctrl *ctrl = nullptr, int k = 0);
 // One colour of a Gauss-Seidel sweep: rows of colour c, slots per `mode`.
@@ -254,7 +274,18 @@ struct KCount {
 void launch_trsm(Ctrl *ctrl, const KCount &kc, int K, int m, hipStream_t s);
 void launch_gemv(i64 M, int K, Prec p, const void *Q, i64 ldq, int kk, const Ctrl *ctrl, void *u,
                  hipStream_t s);
-void launch_update(i64 M, Prec p, const void *z, double *x, hipStream_t s);
+// x += z in FP64 (z in the multigrid vector type of p); for the 16-bit
+// hierarchy x += z * ctrl->mg_inv.
+void launch_update(i64 M, Prec p, const void *z, double *x, hipStream_t s, const Ctrl *ctrl = nullptr);
+// The V-cycle input of the 16-bit hierarchy: r0 = sigma * v rounded to the
+// 16-bit type of p, with v an FP32 Krylov vector and sigma a power of two.
+// end_of_cycle = false: v is basis column k (norm 1 / colscale[k]), sigma is
+// the power of two nearest sqrt(N) colscale[k], and ctrl->mg_post =
+// colscale[k] / sigma.  end_of_cycle = true: v = Q y (norm about ||y||,
+// y = ctrl->y[0..kk)), sigma the power of two nearest sqrt(N) / ||y||, and
+// ctrl->mg_inv = 1 / sigma.
+void launch_cast_mg(i64 N, Prec p, const float *v, Ctrl *ctrl, bool end_of_cycle, int k, void *r0,
+                    hipStream_t s);
 void launch_copy(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 // ---- batched stencil kernels (K interleaved right-hand sides, K = 2, 4, 8) ----

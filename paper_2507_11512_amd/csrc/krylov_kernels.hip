@@ -19,6 +19,7 @@
 // in krylov_batch.hip.
 #include "krylov_device.hpp"
 
+#include <cmath>
 #include <cstdlib>
 #include <stdexcept>
 #include <type_traits>
@@ -285,11 +286,51 @@ __global__ __launch_bounds__(kBlock) void k_gemv(i64 M, const T *__restrict__ Q,
 }
 
 // ---- x += z with the sum in FP64 (Alg. 3: the update must be double) ----
+// For the 16-bit hierarchy z is the correction times sigma: x += z / sigma
+// (a power of two, so the product is exact).
+template <typename T> __device__ __forceinline__ double widen(T v) { return (double)to_t<float>(v); }
+template <> __device__ __forceinline__ double widen<double>(double v) { return v; }
+
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_update(i64 M, const T *__restrict__ z, double *__restrict__ x)
+__global__ __launch_bounds__(kBlock) void k_update(i64 M, const T *__restrict__ z, double *__restrict__ x,
+                                                   const double *inv)
 {
     const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (e < M) x[e] += (double)z[e];
+    if (e >= M) return;
+    const double v = widen(z[e]);
+    x[e] += inv ? v * *inv : v;
+}
+
+// ---- the V-cycle input of the 16-bit hierarchy -----------------------------------------------
+// r0 = sigma v rounded to S, sigma = 2^e the power of two nearest
+// sqrt(N) / ||v||, so that r0's entries are of order one: binary16 has 11
+// significant bits but its normal range starts at 2^-14, below which entries
+// of a unit vector of millions of entries would lose their precision.  The
+// product sigma v is exact (a power of two), so each entry is rounded once.
+__device__ __forceinline__ double pow2_near(double v)
+{
+    if (!(v > 0.0) || !isfinite(v)) return 1.0;
+    return ldexp(1.0, (int)rint(log2(v)));
+}
+
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_cast_mg(i64 N, const float *__restrict__ v, Ctrl *ctrl, int end,
+                                                    int k, double sqrtN, S *__restrict__ r0)
+{
+    double sigma;
+    if (!end) {
+        const double cs = ctrl->colscale[k];  // ||v|| = 1 / colscale[k]
+        sigma = pow2_near(sqrtN * cs);
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->mg_post = cs / sigma;
+    } else {
+        double y2 = 0.0;  // v = Q y with orthonormal q_j: ||v|| = ||y|| up to rounding
+        for (int j = 0; j < k; ++j) y2 += ctrl->y[j] * ctrl->y[j];
+        sigma = pow2_near(sqrtN / sqrt(y2));
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl->mg_inv = 1.0 / sigma;
+    }
+    const float sg = (float)sigma;
+    const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
+    if (e < N) r0[e] = from_t<S>(v[e] * sg);
 }
 
 // ---- streaming copy (bandwidth reference) -------------------------------------------------------------
@@ -468,10 +509,30 @@ void launch_gemv(i64 M, int K, Prec p, const void *Q, i64 ldq, int kk, const Ctr
     HPGMX_LAUNCH_CHECK();
 }
 
-void launch_update(i64 M, Prec p, const void *z, double *x, hipStream_t s)
+void launch_update(i64 M, Prec p, const void *z, double *x, hipStream_t s, const Ctrl *ctrl)
 {
-    if (p == P64) hipLaunchKernelGGL(k_update<double>, dim3(grid_n(M)), dim3(kBlock), 0, s, M, (const double *)z, x);
-    else hipLaunchKernelGGL(k_update<float>, dim3(grid_n(M)), dim3(kBlock), 0, s, M, (const float *)z, x);
+    const dim3 gr(grid_n(M)), bl(kBlock);
+    const double *inv = ctrl && mg16(p) ? &ctrl->mg_inv : nullptr;
+    switch (p) {
+    case P64: hipLaunchKernelGGL(k_update<double>, gr, bl, 0, s, M, (const double *)z, x, inv); break;
+    case P16V: hipLaunchKernelGGL(k_update<__half>, gr, bl, 0, s, M, (const __half *)z, x, inv); break;
+    case PB16V: hipLaunchKernelGGL(k_update<bf16>, gr, bl, 0, s, M, (const bf16 *)z, x, inv); break;
+    default: hipLaunchKernelGGL(k_update<float>, gr, bl, 0, s, M, (const float *)z, x, inv); break;
+    }
+    HPGMX_LAUNCH_CHECK();
+}
+
+void launch_cast_mg(i64 N, Prec p, const float *v, Ctrl *ctrl, bool end_of_cycle, int k, void *r0, hipStream_t s)
+{
+    const double sqrtN = std::sqrt((double)N);
+    if (p == P16V)
+        hipLaunchKernelGGL(k_cast_mg<__half>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, v, ctrl, (int)end_of_cycle, k,
+                           sqrtN, (__half *)r0);
+    else if (p == PB16V)
+        hipLaunchKernelGGL(k_cast_mg<bf16>, dim3(grid_n(N)), dim3(kBlock), 0, s, N, v, ctrl, (int)end_of_cycle, k,
+                           sqrtN, (bf16 *)r0);
+    else
+        throw std::runtime_error("launch_cast_mg: not a 16-bit hierarchy precision");
     HPGMX_LAUNCH_CHECK();
 }
 

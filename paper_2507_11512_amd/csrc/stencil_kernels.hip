@@ -136,13 +136,23 @@ void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s)
 }
 
 // ---- natural <-> colour-blocked order ---------------------------------------------
+// Element conversions between vector types go through FP32 for the 16-bit
+// types (exact for widening; rounding to nearest even when narrowing).
+template <typename To, typename Ti> __device__ __forceinline__ To cvt(Ti v)
+{
+    if constexpr (std::is_same<To, Ti>::value) return v;
+    else if constexpr (std::is_same<Ti, double>::value) return from_t<To>((float)v);
+    else if constexpr (std::is_same<To, double>::value) return (double)to_t<float>(v);
+    else return from_t<To>(to_t<float>(v));
+}
+
 template <typename Ti, typename To>
 __global__ __launch_bounds__(kBlock) void k_nat2int(Geom g, const Ti *__restrict__ nat, To *__restrict__ in)
 {
     const i64 I = gtid();
     if (I >= g.N) return;
     const int i = (int)(I % g.nx), j = (int)((I / g.nx) % g.ny), k = (int)(I / ((i64)g.nx * g.ny));
-    in[to_internal(g, i, j, k)] = (To)nat[I];
+    in[to_internal(g, i, j, k)] = cvt<To>(nat[I]);
 }
 
 template <typename Ti, typename To>
@@ -151,39 +161,69 @@ __global__ __launch_bounds__(kBlock) void k_int2nat(Geom g, const Ti *__restrict
     const i64 I = gtid();
     if (I >= g.N) return;
     const int i = (int)(I % g.nx), j = (int)((I / g.nx) % g.ny), k = (int)(I / ((i64)g.nx * g.ny));
-    nat[I] = (To)in[to_internal(g, i, j, k)];
+    nat[I] = cvt<To>(in[to_internal(g, i, j, k)]);
+}
+
+// Calls f(tag) with a value of the multigrid vector type of p.
+template <typename F> static void with_vec(Prec p, F &&f)
+{
+    switch (p) {
+    case P64: f(double{}); break;
+    case P16V: f(__half{}); break;
+    case PB16V: f(bf16{}); break;
+    default: f(float{}); break;
+    }
 }
 
 void launch_nat2int(const Geom &g, Prec src, const void *nat, Prec dst, void *in, hipStream_t s)
 {
     const dim3 gr(grid_for(g.N)), bl(kBlock);
-    const bool s64 = src == P64, d64 = dst == P64;
-    if (s64 && d64) hipLaunchKernelGGL((k_nat2int<double, double>), gr, bl, 0, s, g, (const double *)nat, (double *)in);
-    else if (s64) hipLaunchKernelGGL((k_nat2int<double, float>), gr, bl, 0, s, g, (const double *)nat, (float *)in);
-    else if (d64) hipLaunchKernelGGL((k_nat2int<float, double>), gr, bl, 0, s, g, (const float *)nat, (double *)in);
-    else hipLaunchKernelGGL((k_nat2int<float, float>), gr, bl, 0, s, g, (const float *)nat, (float *)in);
+    with_vec(src, [&](auto ti) {
+        with_vec(dst, [&](auto to) {
+            using Ti = decltype(ti);
+            using To = decltype(to);
+            hipLaunchKernelGGL((k_nat2int<Ti, To>), gr, bl, 0, s, g, (const Ti *)nat, (To *)in);
+        });
+    });
     HPGMX_LAUNCH_CHECK();
 }
 
 void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat, hipStream_t s)
 {
     const dim3 gr(grid_for(g.N)), bl(kBlock);
-    const bool s64 = src == P64, d64 = dst == P64;
-    if (s64 && d64) hipLaunchKernelGGL((k_int2nat<double, double>), gr, bl, 0, s, g, (const double *)in, (double *)nat);
-    else if (s64) hipLaunchKernelGGL((k_int2nat<double, float>), gr, bl, 0, s, g, (const double *)in, (float *)nat);
-    else if (d64) hipLaunchKernelGGL((k_int2nat<float, double>), gr, bl, 0, s, g, (const float *)in, (double *)nat);
-    else hipLaunchKernelGGL((k_int2nat<float, float>), gr, bl, 0, s, g, (const float *)in, (float *)nat);
+    with_vec(src, [&](auto ti) {
+        with_vec(dst, [&](auto to) {
+            using Ti = decltype(ti);
+            using To = decltype(to);
+            hipLaunchKernelGGL((k_int2nat<Ti, To>), gr, bl, 0, s, g, (const Ti *)in, (To *)nat);
+        });
+    });
     HPGMX_LAUNCH_CHECK();
+}
+
+// Matrix value type V and multigrid vector type S of each precision, with the
+// value arrays of the matrix: calls f(v, d, S{}).
+template <typename F> static void with_matrix(const Matrix &A, Prec p, F &&f)
+{
+    switch (p) {
+    case P64: f(A.v64, A.d64, double{}); break;
+    case P32: f(A.v32, A.d32, float{}); break;
+    case P16: f(A.v16, A.d16, float{}); break;
+    case PB16: f(A.vb16, A.db16, float{}); break;
+    case P16V: f(A.v16, A.d16, __half{}); break;
+    case PB16V: f(A.vb16, A.db16, bf16{}); break;
+    }
 }
 
 // ---- SpMV -------------------------------------------------------------------------------
 // y = A x over all N rows (Sec. 3.2 ELL SpMV); with `scale`, y = (A x) * *scale
-// (the unnormalised-basis scale of the column x was computed from).
-template <typename V>
+// (the unnormalised-basis scale of the column x was computed from).  x is a
+// multigrid vector (type S), y a Krylov vector (type T).
+template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, int remap, const V *__restrict__ offv,
                                                  const int *__restrict__ offc,
                                                  const V *__restrict__ diag,
-                                                 const typename VecT<V>::T *__restrict__ x,
+                                                 const S *__restrict__ x,
                                                  typename VecT<V>::T *__restrict__ y,
                                                  const double *scale)
 {
@@ -191,31 +231,23 @@ __global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, int remap, co
     const i64 p = gtid_xcd(remap);
     if (p >= N) return;
     const EllRow er = ell_row(p, N, clog2);
-    const T dx = to_t<T>(ld_stream(diag + p)) * x[p];
+    const T dx = to_t<T>(ld_stream(diag + p)) * to_t<T>(x[p]);
     const T v = dx + ell_row_dot<T, V, kAllSlots>(offv, offc, x, er);
     y[p] = scale ? v * (T)*scale : v;
 }
 
-template <typename V>
-static void spmv_t(const Matrix &A, const V *v, const V *d, const void *x, void *y, hipStream_t s,
-                   const double *scale)
-{
-    using T = typename VecT<V>::T;
-    hipLaunchKernelGGL(k_spmv<V>, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2,
-                       std::is_same<V, double>::value ? xcd_remap_enabled() : full_grid_order(A.g, 1), v, A.col, d,
-                       (const T *)x, (T *)y, scale);
-    HPGMX_LAUNCH_CHECK();
-}
-
 void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s, const Ctrl *ctrl, int k)
 {
-    const double *scale = ctrl ? ctrl->colscale + k : nullptr;
-    switch (p) {
-    case P64: spmv_t(A, A.v64, A.d64, x, y, s, scale); break;
-    case P32: spmv_t(A, A.v32, A.d32, x, y, s, scale); break;
-    case P16: spmv_t(A, A.v16, A.d16, x, y, s, scale); break;
-    case PB16: spmv_t(A, A.vb16, A.db16, x, y, s, scale); break;
-    }
+    const double *scale = !ctrl ? nullptr : mg16(p) ? &ctrl->mg_post : ctrl->colscale + k;
+    with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using S = decltype(sv);
+        using T = typename VecT<V>::T;
+        hipLaunchKernelGGL((k_spmv<V, S>), dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2,
+                           std::is_same<V, double>::value ? xcd_remap_enabled() : full_grid_order(A.g, 1),
+                           (const V *)v, A.col, (const V *)d, (const S *)x, (T *)y, scale);
+    });
+    HPGMX_LAUNCH_CHECK();
 }
 
 // ---- Gauss-Seidel, one colour ---------------------------------------------------------------
@@ -226,47 +258,44 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 // unrolled loop issues every load of the row before the first use: the full
 // mask for ordinary sweeps, and for a sweep from a zero guess only the slots
 // that couple to colours relaxed earlier in the sweep (the others still hold
-// zero, and skipping them gives the same result bit for bit).
-template <typename V, unsigned MASK>
+// zero, and skipping them gives the same result bit for bit).  r and z are
+// stored in S and the row is evaluated in T.
+template <typename V, typename S, unsigned MASK>
 __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
                                                const V *__restrict__ offv,
                                                const int *__restrict__ offc,
                                                const V *__restrict__ diag,
-                                               const typename VecT<V>::T *__restrict__ r,
-                                               typename VecT<V>::T *z)
+                                               const S *__restrict__ r, S *z)
 {
     using T = typename VecT<V>::T;
     const i64 t = gtid_xcd(remap);
     if (t >= cnt) return;
     const i64 p = row0 + t;
     const EllRow er = ell_row(p, N, clog2);
-    const T rp = r[p];
+    const T rp = to_t<T>(r[p]);
     const T dg = to_t<T>(ld_stream(diag + p));
-    z[p] = (rp - ell_row_dot<T, V, MASK>(offv, offc, z, er)) / dg;
+    z[p] = from_t<S>((rp - ell_row_dot<T, V, MASK>(offv, offc, z, er)) / dg);
 }
 
-
-template <typename V, unsigned MASK>
-static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z,
-                      hipStream_t s)
+template <typename V, typename S, unsigned MASK>
+static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z, hipStream_t s)
 {
-    using T = typename VecT<V>::T;
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
-    hipLaunchKernelGGL((k_gs<V, MASK>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N,
-                       A.clog2, xcd_remap_enabled(), v, A.col, d, (const T *)r, (T *)z);
+    hipLaunchKernelGGL((k_gs<V, S, MASK>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N,
+                       A.clog2, xcd_remap_enabled(), v, A.col, d, (const S *)r, (S *)z);
     HPGMX_LAUNCH_CHECK();
 }
 
 #define HPGMX_GS_CASE(C, FWD) \
-    case C: gs_launch<V, zero_guess_mask(C, FWD)>(A, v, d, c, r, z, s); break;
+    case C: gs_launch<V, S, zero_guess_mask(C, FWD)>(A, v, d, c, r, z, s); break;
 
-template <typename V>
+template <typename V, typename S>
 static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const void *r, void *z,
                  hipStream_t s)
 {
     if (mode == kGsFull) {
-        gs_launch<V, kAllSlots>(A, v, d, c, r, z, s);
+        gs_launch<V, S, kAllSlots>(A, v, d, c, r, z, s);
     } else if (mode == kGsZeroForward) {
         switch (c) {
             HPGMX_GS_CASE(0, true) HPGMX_GS_CASE(1, true) HPGMX_GS_CASE(2, true) HPGMX_GS_CASE(3, true)
@@ -283,58 +312,47 @@ static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const
 void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
                       hipStream_t s)
 {
-    switch (p) {
-    case P64: gs_t(A, A.v64, A.d64, c, mode, r, z, s); break;
-    case P32: gs_t(A, A.v32, A.d32, c, mode, r, z, s); break;
-    case P16: gs_t(A, A.v16, A.d16, c, mode, r, z, s); break;
-    case PB16: gs_t(A, A.vb16, A.db16, c, mode, r, z, s); break;
-    }
+    with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        gs_t<V, decltype(sv)>(A, v, d, c, mode, r, z, s);
+    });
 }
 
 // ---- fused residual-restriction (eq. (6)) ------------------------------------------------------
 // The colour-4 block of the fine level holds the injection points in the
 // coarse level's natural order: row q of that block is coarse point
 // (q % cx, (q / cx) % cy, q / (cx cy)).  Only those rows are evaluated.
-template <typename V>
+template <typename V, typename S>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2, int remap,
                                                      const V *__restrict__ offv,
                                                      const int *__restrict__ offc,
                                                      const V *__restrict__ diag,
-                                                     const typename VecT<V>::T *__restrict__ r,
-                                                     const typename VecT<V>::T *__restrict__ z,
-                                                     typename VecT<V>::T *__restrict__ rc)
+                                                     const S *__restrict__ r,
+                                                     const S *__restrict__ z,
+                                                     S *__restrict__ rc)
 {
     using T = typename VecT<V>::T;
     const i64 q = gtid_xcd(remap);
     if (q >= gc.N) return;
     const i64 N = gf.N, p = gf.off[4] + q;
     const EllRow er = ell_row(p, N, clog2);
-    const T rp = r[p];
-    const T acc = to_t<T>(ld_stream(diag + p)) * z[p] + ell_row_dot<T, V, kAllSlots>(offv, offc, z, er);
+    const T rp = to_t<T>(r[p]);
+    const T acc = to_t<T>(ld_stream(diag + p)) * to_t<T>(z[p]) + ell_row_dot<T, V, kAllSlots>(offv, offc, z, er);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
-    rc[to_internal(gc, I, J, K)] = rp - acc;
-}
-
-template <typename V>
-static void restrict_t(const Matrix &A, const Geom &gc, const V *v, const V *d, const void *r,
-                       const void *z, void *rc, hipStream_t s)
-{
-    using T = typename VecT<V>::T;
-    hipLaunchKernelGGL(k_restrict<V>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc, A.clog2,
-                       xcd_remap_enabled(), v, A.col,
-                       d, (const T *)r, (const T *)z, (T *)rc);
-    HPGMX_LAUNCH_CHECK();
+    rc[to_internal(gc, I, J, K)] = from_t<S>(rp - acc);
 }
 
 void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
                      void *rc, hipStream_t s)
 {
-    switch (p) {
-    case P64: restrict_t(Af, gc, Af.v64, Af.d64, r, z, rc, s); break;
-    case P32: restrict_t(Af, gc, Af.v32, Af.d32, r, z, rc, s); break;
-    case P16: restrict_t(Af, gc, Af.v16, Af.d16, r, z, rc, s); break;
-    case PB16: restrict_t(Af, gc, Af.vb16, Af.db16, r, z, rc, s); break;
-    }
+    with_matrix(Af, p, [&](auto *v, auto *d, auto sv) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using S = decltype(sv);
+        hipLaunchKernelGGL((k_restrict<V, S>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, Af.g, gc, Af.clog2,
+                           xcd_remap_enabled(), (const V *)v, Af.col, (const V *)d, (const S *)r, (const S *)z,
+                           (S *)rc);
+    });
+    HPGMX_LAUNCH_CHECK();
 }
 
 // ---- the fused restriction right after a single sweep from zero -----------------------------------
@@ -348,12 +366,12 @@ void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, co
 // backward) and without r or the diagonal.  Exact in exact arithmetic; the
 // rounding differs from the full formula by the rounding of the colour-4
 // relaxation.
-template <typename V, unsigned MASK>
+template <typename V, typename S, unsigned MASK>
 __global__ __launch_bounds__(kBlock) void k_restrict_after_sweep(Geom gf, Geom gc, int clog2, int remap,
                                                                  const V *__restrict__ offv,
                                                                  const int *__restrict__ offc,
-                                                                 const typename VecT<V>::T *__restrict__ z,
-                                                                 typename VecT<V>::T *__restrict__ rc)
+                                                                 const S *__restrict__ z,
+                                                                 S *__restrict__ rc)
 {
     using T = typename VecT<V>::T;
     const i64 q = gtid_xcd(remap);
@@ -362,54 +380,45 @@ __global__ __launch_bounds__(kBlock) void k_restrict_after_sweep(Geom gf, Geom g
     const EllRow er = ell_row(p, N, clog2);
     const T acc = ell_row_dot<T, V, MASK>(offv, offc, z, er);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
-    rc[to_internal(gc, I, J, K)] = -acc;
-}
-
-template <typename V>
-static void restrict_after_t(const Matrix &A, const Geom &gc, const V *v, bool forward, const void *z, void *rc,
-                             hipStream_t s)
-{
-    using T = typename VecT<V>::T;
-    constexpr unsigned kFwd = kAllSlots & ~zero_guess_mask(4, true);
-    constexpr unsigned kBwd = kAllSlots & ~zero_guess_mask(4, false);
-    if (forward)
-        hipLaunchKernelGGL((k_restrict_after_sweep<V, kFwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc,
-                           A.clog2, xcd_remap_enabled(), v, A.col, (const T *)z, (T *)rc);
-    else
-        hipLaunchKernelGGL((k_restrict_after_sweep<V, kBwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, A.g, gc,
-                           A.clog2, xcd_remap_enabled(), v, A.col, (const T *)z, (T *)rc);
-    HPGMX_LAUNCH_CHECK();
+    rc[to_internal(gc, I, J, K)] = from_t<S>(-acc);
 }
 
 void launch_restrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, bool forward, const void *z, void *rc,
                                  hipStream_t s)
 {
-    switch (p) {
-    case P64: restrict_after_t(Af, gc, Af.v64, forward, z, rc, s); break;
-    case P32: restrict_after_t(Af, gc, Af.v32, forward, z, rc, s); break;
-    case P16: restrict_after_t(Af, gc, Af.v16, forward, z, rc, s); break;
-    case PB16: restrict_after_t(Af, gc, Af.vb16, forward, z, rc, s); break;
-    }
+    constexpr unsigned kFwd = kAllSlots & ~zero_guess_mask(4, true);
+    constexpr unsigned kBwd = kAllSlots & ~zero_guess_mask(4, false);
+    with_matrix(Af, p, [&](auto *v, auto *, auto sv) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using S = decltype(sv);
+        if (forward)
+            hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kFwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, Af.g,
+                               gc, Af.clog2, xcd_remap_enabled(), (const V *)v, Af.col, (const S *)z, (S *)rc);
+        else
+            hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kBwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, Af.g,
+                               gc, Af.clog2, xcd_remap_enabled(), (const V *)v, Af.col, (const S *)z, (S *)rc);
+    });
+    HPGMX_LAUNCH_CHECK();
 }
 
 // ---- prolongation-correction: z += P zc, P = R^T -------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const T *__restrict__ zc, T *__restrict__ z)
+template <typename S>
+__global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const S *__restrict__ zc, S *__restrict__ z)
 {
+    using T = typename VecT<S>::T;
     const i64 q = gtid();
     if (q >= gc.N) return;
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
-    z[gf.off[4] + q] += zc[to_internal(gc, I, J, K)];
+    const i64 p = gf.off[4] + q;
+    z[p] = from_t<S>(to_t<T>(z[p]) + to_t<T>(zc[to_internal(gc, I, J, K)]));
 }
 
 void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void *z, hipStream_t s)
 {
-    if (p == P64)
-        hipLaunchKernelGGL(k_prolong<double>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, gf, gc,
-                           (const double *)zc, (double *)z);
-    else
-        hipLaunchKernelGGL(k_prolong<float>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, gf, gc,
-                           (const float *)zc, (float *)z);
+    with_vec(p, [&](auto sv) {
+        using S = decltype(sv);
+        hipLaunchKernelGGL(k_prolong<S>, dim3(grid_for(gc.N)), dim3(kBlock), 0, s, gf, gc, (const S *)zc, (S *)z);
+    });
     HPGMX_LAUNCH_CHECK();
 }
 

@@ -13,7 +13,7 @@ from dataclasses import dataclass
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libhpgmx.so")
 
-F64, F32, F16, BF16 = 0, 1, 2, 3
+F64, F32, F16, BF16, F16_MG, BF16_MG = 0, 1, 2, 3, 4, 5
 GS_FORWARD, GS_BACKWARD, GS_SYMMETRIC = 0, 1, 2
 SOLVE_PROFILE = 1
 SOLVE_GRAPH = 2
@@ -143,8 +143,9 @@ def _ptr(t):
 
 
 def _vec_dtype(dtype):
+    """torch dtype of the multigrid vectors of a precision at the ABI."""
     import torch
-    return torch.float64 if dtype == F64 else torch.float32
+    return {F64: torch.float64, F16_MG: torch.float16, BF16_MG: torch.bfloat16}.get(dtype, torch.float32)
 
 
 @dataclass
@@ -388,7 +389,8 @@ class Problem:
     """
 
     _SWEEPS = {"forward": GS_FORWARD, "backward": GS_BACKWARD, "symmetric": GS_SYMMETRIC}
-    _PREC = {"fp64": F64, "mxp": F32, "fp32": F32, "fp16": F16, "bf16": BF16}
+    _PREC = {"fp64": F64, "mxp": F32, "fp32": F32, "fp16": F16, "bf16": BF16,
+             "fp16-mg": F16_MG, "bf16-mg": BF16_MG}
 
     def __init__(self, n, beta=0.5, levels=4, sweep="forward", pre=1, post=1, coarsest=1,
                  stream=None, workspace=None, coef=None):

@@ -120,24 +120,35 @@ def fixed_iteration_cycles(iters, restart):
 
 
 # ---- bytes --------------------------------------------------------------------------------------
+# dtype codes: 0 FP64; 1 FP32; 2 / 3 binary16 / bfloat16 matrices; 4 / 5 the
+# whole multigrid hierarchy (matrices and work vectors) in binary16 / bfloat16.
 def vb(dtype):
-    return {0: 8, 1: 4, 2: 2, 3: 2}[dtype]
+    """Matrix value bytes."""
+    return {0: 8, 1: 4, 2: 2, 3: 2, 4: 2, 5: 2}[dtype]
 
 
 def wb(dtype):
+    """Krylov vector bytes (the basis, the SpMV output)."""
     return 8 if dtype == 0 else 4
+
+
+def mgb(dtype):
+    """Multigrid work-vector bytes."""
+    return {0: 8, 4: 2, 5: 2}.get(dtype, 4)
 
 
 def gs_colour_bytes(rows, active_slots, dtype):
     """One colour launch: matrix slice for `active_slots` slots + diagonal,
     r read, z written, neighbour z counted once per row."""
-    v, w = vb(dtype), wb(dtype)
+    v, w = vb(dtype), mgb(dtype)
     return rows * (active_slots * (v + 4) + v + 3 * w)
 
 
 def spmv_bytes(rows, dtype):
-    v, w = vb(dtype), wb(dtype)
-    return rows * (SLOTS * (v + 4) + v + 2 * w)
+    """The SpMV of an inner step: x is the V-cycle's output (a multigrid
+    vector), y a Krylov vector."""
+    v = vb(dtype)
+    return rows * (SLOTS * (v + 4) + v + mgb(dtype) + wb(dtype))
 
 
 def cgs_pass_bytes(rows, kb, dtype):
@@ -151,7 +162,7 @@ def cgs_dot_bytes(rows, kb, dtype):
 
 
 def restrict_bytes(coarse_rows, dtype):
-    v, w = vb(dtype), wb(dtype)
+    v, w = vb(dtype), mgb(dtype)
     return coarse_rows * (SLOTS * (v + 4) + v + 3 * w)
 
 
@@ -159,12 +170,12 @@ def restrict_after_sweep_bytes(coarse_rows, dtype, slots=8, K=1):
     """The fused restriction after a single sweep from zero: `slots` matrix
     slots of each injection row (8 after a forward sweep), z read once and
     r_c written (K vectors)."""
-    v, w = vb(dtype), wb(dtype)
+    v, w = vb(dtype), mgb(dtype)
     return coarse_rows * (slots * (v + 4) + 2 * K * w)
 
 
 def prolong_bytes(coarse_rows, dtype):
-    return coarse_rows * 3 * wb(dtype)
+    return coarse_rows * 3 * mgb(dtype)
 
 
 def resid64_bytes(rows):

@@ -314,37 +314,75 @@ def _assert_same_binary32(got, ref, max_frac=0.01):
     assert np.count_nonzero(diff) <= max(2, max_frac * got.size), np.count_nonzero(diff)
 
 
+STORE = {1: refimpl.fl32, 2: refimpl.fl16, 3: refimpl.flbf16}
+
+
+def _ulp(v, mode):
+    """Spacing of the storage format at |v| (binary32, binary16 or bfloat16)."""
+    a = np.abs(np.asarray(v, dtype=np.float64))
+    if mode == 1:
+        return np.spacing(a.astype(np.float32)).astype(np.float64)
+    p, emin = (11, -14) if mode == 2 else (8, -126)
+    _, e = np.frexp(np.where(a > 0, a, 1.0))
+    return np.ldexp(1.0, np.maximum(e - 1, emin) - (p - 1))
+
+
+def _assert_same_stored(got, ref, mode, max_frac=0.01):
+    assert np.array_equal(got, STORE[mode](got)), "not representable in the storage format"
+    diff = np.abs(got - ref)
+    assert np.all(diff <= 2 * _ulp(ref, mode) + 1e-300), np.max(diff / (_ulp(ref, mode) + 1e-300))
+    assert np.count_nonzero(diff) <= max(2, max_frac * got.size), np.count_nonzero(diff)
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3])
 @pytest.mark.parametrize("d,levels,sweep", [((8, 8, 8), 3, 0), ((8, 12, 16), 3, 2), ((16, 16, 16), 4, 0)])
-def test_fp32_storage_vcycle_equals_composed_reference(oracle_mod, d, levels, sweep):
-    r = refimpl.fl32(inputs.uniform(d, 45))
-    got = oracle_mod.vcycle(d, r, levels, 1, 1, 1, sweep, f32=True)
-    ref = refimpl.vcycle_ref(d, r, levels, 1, 1, 1, sweep, store=refimpl.fl32)
-    _assert_same_binary32(got, ref)
-    # the storage rounding is visible: the FP64 cycle differs at the binary32 level
+def test_storage_vcycle_equals_composed_reference(oracle_mod, d, levels, sweep, mode):
+    """The V-cycle with its work vectors stored in binary32 (mode 1), binary16
+    (2) or bfloat16 (3) equals the composition of the independent pieces
+    with the same rounding after every stored vector."""
+    store = STORE[mode]
+    r = store(inputs.uniform(d, 45))
+    got = oracle_mod.vcycle(d, r, levels, 1, 1, 1, sweep, f32=mode)
+    ref = refimpl.vcycle_ref(d, r, levels, 1, 1, 1, sweep, store=store)
+    _assert_same_stored(got, ref, mode)
+    # the storage rounding is visible: the FP64 cycle differs at the format's level
     full = oracle_mod.vcycle(d, r, levels, 1, 1, 1, sweep)
-    assert np.count_nonzero(got != refimpl.fl32(full)) > 0.05 * got.size
+    assert np.count_nonzero(got != store(full)) > 0.05 * got.size
 
 
-@pytest.mark.parametrize("d,levels,sweep", [((8, 8, 8), 3, 0), ((6, 8, 10), 2, 2)])
-def test_fp32_storage_arnoldi_steps(oracle_mod, d, levels, sweep):
-    """Every step of the first cycle in f32 mode, rebuilt from the oracle's own
-    basis: z = M^-1 q_k (binary32 storage), w = fl32(A z), two classical
-    Gram-Schmidt passes each stored in binary32, beta = ||w||,
-    q_{k+1} = fl32(w / beta); and the Arnoldi relation holds only to the
-    binary32 level."""
+def _pow2_near(v):
+    return float(np.ldexp(1.0, int(np.rint(np.log2(v)))))
+
+
+@pytest.mark.parametrize("d,levels,sweep,mode", [((8, 8, 8), 3, 0, 1), ((6, 8, 10), 2, 2, 1),
+                                                 ((8, 8, 8), 3, 0, 2), ((8, 8, 8), 3, 0, 3)])
+def test_fp32_storage_arnoldi_steps(oracle_mod, d, levels, sweep, mode):
+    """Every step of the first cycle in a storage mode, rebuilt from the
+    oracle's own basis: z = M^-1 q_k with the multigrid vectors stored in
+    binary32 (mode 1) -- or, for the 16-bit hierarchies (2: binary16, 3:
+    bfloat16), z = M^-1 fl16(sigma q_k) / sigma with sigma the power of two
+    nearest sqrt(N) -- then w = fl32(A z), two classical Gram-Schmidt passes
+    each stored in binary32, beta = ||w||, q_{k+1} = fl32(w / beta); and the
+    Arnoldi relation holds only to the storage precision."""
     m = 6
     b = inputs.uniform(d, 55)
     _, st, cyc = oracle_mod.gmres_ir(d, b, levels=levels, sweep=sweep, restart=m, max_iters=m, tol=0.0,
-                                     f32=True, want_first_cycle=True)
+                                     f32=mode, want_first_cycle=True)
     k, Q, Hbar = cyc["k"], cyc["Q"], cyc["Hbar"]
     assert k == m
     K = refimpl.kron_matrix(d, 0.5)
     fl = refimpl.fl32
+    mg = STORE[mode]
+    sig = _pow2_near(np.sqrt(b.size)) if mode >= 2 else 1.0
     _assert_same_binary32(Q[:, 0], fl(b / np.linalg.norm(b)), max_frac=0.0)
+
+    def precond(q):
+        return refimpl.vcycle_ref(d, mg(sig * q), levels, 1, 1, 1, sweep, store=mg)
+
     for j in range(k):
         Qj = Q[:, :j + 1]
-        z = refimpl.vcycle_ref(d, Q[:, j], levels, 1, 1, 1, sweep, store=fl)
-        w = fl(K @ z)
+        z = precond(Q[:, j])
+        w = fl(K @ z / sig)
         h1 = Qj.T @ w
         w1 = fl(w - Qj @ h1)
         h2 = Qj.T @ w1
@@ -355,20 +393,26 @@ def test_fp32_storage_arnoldi_steps(oracle_mod, d, levels, sweep):
         assert abs(Hbar[j + 1, j] - beta) <= 1e-10 * beta, j
         assert np.all(Hbar[j + 2:, j] == 0.0)
         _assert_same_binary32(Q[:, j + 1], fl(w2 / beta))
-    MQ = np.column_stack([refimpl.vcycle_ref(d, Q[:, j], levels, 1, 1, 1, sweep, store=fl) for j in range(k)])
+    MQ = np.column_stack([precond(Q[:, j]) / sig for j in range(k)])
     rel = np.linalg.norm(K @ MQ - Q @ Hbar) / np.linalg.norm(Hbar)
     assert 1e-12 < rel <= 1e-5, rel
     orth = np.linalg.norm(Q.T @ Q - np.eye(k + 1))
     assert 1e-12 < orth <= 1e-5, orth
+    if mode >= 2:   # the 16-bit preconditioner differs from the binary32 one at the 16-bit level
+        M32 = np.column_stack([refimpl.vcycle_ref(d, Q[:, j], levels, 1, 1, 1, sweep, store=fl) for j in range(k)])
+        assert np.linalg.norm(MQ - M32) > 1e-5 * np.linalg.norm(M32)
 
 
-def test_fp32_storage_end_of_cycle_update(oracle_mod):
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_fp32_storage_end_of_cycle_update(oracle_mod, mode):
     """After one cycle from x0 = 0: x = fl32(M^-1 fl32(Q_k y)) with y the
     least-squares solution of the cycle (binary32 storage of u and z, the
-    update itself in binary64)."""
+    update itself in binary64); for the 16-bit hierarchies
+    x = M^-1 fl16(sigma fl32(Q_k y)) / sigma with sigma the power of two
+    nearest sqrt(N) / ||y||."""
     d, levels, m = (8, 8, 8), 3, 5
     b = inputs.uniform(d, 56)
-    x, st, cyc = oracle_mod.gmres_ir(d, b, levels=levels, restart=m, max_iters=m, tol=0.0, f32=True,
+    x, st, cyc = oracle_mod.gmres_ir(d, b, levels=levels, restart=m, max_iters=m, tol=0.0, f32=mode,
                                      want_first_cycle=True)
     assert st.iters == m and st.restarts == 1
     k, Q, Hbar, y = cyc["k"], cyc["Q"], cyc["Hbar"], cyc["y"]
@@ -377,8 +421,14 @@ def test_fp32_storage_end_of_cycle_update(oracle_mod):
     ys, *_ = np.linalg.lstsq(Hbar, rhs, rcond=None)
     assert np.linalg.norm(y - ys) <= 1e-10 * np.linalg.norm(ys)
     u = refimpl.fl32(Q[:, :k] @ y)
-    ref = refimpl.vcycle_ref(d, u, levels, store=refimpl.fl32)
-    _assert_same_binary32(x, ref)
+    if mode == 1:
+        ref = refimpl.vcycle_ref(d, u, levels, store=refimpl.fl32)
+        _assert_same_binary32(x, ref)
+    else:
+        mg = STORE[mode]
+        su = _pow2_near(np.sqrt(b.size) / np.linalg.norm(y))
+        zs = refimpl.vcycle_ref(d, mg(su * u), levels, store=mg)
+        _assert_same_stored(x * su, zs, mode)
 
 
 def test_edge_cases(oracle_mod):
