@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MxP vs FP64 GMRES-MG GFLOP/s at 1e-9 rel. residual; kernel HBM GB/s"
 PEAK_HBM_GBPS = 8000.0
+FINISH_PARTIALS = 1024  # workgroups of a grid-stride reduction: partial sums per coefficient
 
 
 def log(*a):
@@ -55,6 +56,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--cpu-iters", type=int, default=30, help="inner steps of the CPU-oracle sample (30: one restart cycle)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-oracle baseline")
+    ap.add_argument("--no-cpu-extra", action="store_true",
+                    help="CPU baseline: only the one-cycle sample (skip the 16^3/128^3 solves and the 1-thread run)")
     ap.add_argument("--no-validation", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip the timed FP64 phase")
     ap.add_argument("--no-profile", action="store_true", help="skip the HIP-event kernel profile")
@@ -109,6 +112,7 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
     for kk in cycles:
         B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
         B[(hp.K_CAST, 0)] += N * (8 + w)
+        B[(hp.K_FINISH, 0)] += FINISH_PARTIALS * 8                   # the residual's norm
         for k in range(kk):
             B[(hp.K_CAST, 0)] += cast_mg
             vcyc()
@@ -116,6 +120,7 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, 1)
             B[(hp.K_CGS_DOT, 0)] += pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
+            B[(hp.K_FINISH, 0)] += FINISH_PARTIALS * 8 * (2 * (k + 1) + 1)  # partial sums read
         B[(hp.K_GEMV, 0)] += N * (kk + 1) * w
         B[(hp.K_CAST, 0)] += cast_mg
         vcyc()
@@ -298,19 +303,7 @@ def main():
     # ---- 4c. CPU oracle on a bounded sample ------------------------------------------------------
     cpu = None
     if not args.no_cpu:
-        import oracle
-        bh = oracle.spmv(n, np.ones(N), beta=args.beta)
-        t0 = time.perf_counter()
-        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0,
-                                 beta=args.beta)
-        dt = time.perf_counter() - t0
-        cflops = pm.solve_flops(cfg, [args.cpu_iters])
-        cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"{n}^3 FP64 oracle, one GMRES({m}) cycle cut at {args.cpu_iters} inner steps "
-                         f"(2 outer residuals, {args.cpu_iters} V-cycle+SpMV+CGS2 steps, end-of-cycle "
-                         f"V-cycle), {dt:.1f} s wall"}
-        log(f"cpu oracle: {cpu['value']} GFLOP/s on {cpu['cores']} threads ({dt:.1f}s)")
+        cpu = cpu_baseline(args, n, N, L, m, cfg, pm, np)
 
     traffic = load_traffic(f"{n}^3", dom_name) if dominant else None
     if args.report:
@@ -352,6 +345,7 @@ def main():
         "validation": val,
         "fp64_ms_per_step": round(res["fp64"]["s_per_solve"] * 1e3, 3) if "fp64" in res else None,
         "flops_per_solve": flops,
+        "solve_bytes": solve_rates(cfg, cycles, inner_code, res, penalty, hp, pm),
         "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": dominant["GBps"] if dominant else None, "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": dominant["frac_peak"] if dominant else None,
@@ -363,6 +357,81 @@ def main():
     }
     P.close()
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_baseline(args, n, N, L, m, cfg, pm, np):
+    """The FP64 CPU oracle timed on the host: one restart cycle of the
+    workload on every host thread (the reported value), plus full solves of
+    the 16^3 and 128^3 configurations to 1e-9 and a one-thread sample."""
+    import oracle
+    threads = oracle.num_threads()
+    bh = oracle.spmv(n, np.ones(N), beta=args.beta)
+    t0 = time.perf_counter()
+    oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0, beta=args.beta)
+    dt = time.perf_counter() - t0
+    cflops = pm.solve_flops(cfg, [args.cpu_iters])
+    cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n}^3 FP64 oracle, one GMRES({m}) cycle cut at {args.cpu_iters} inner steps "
+                     f"(2 outer residuals, {args.cpu_iters} V-cycle+SpMV+CGS2 steps, end-of-cycle "
+                     f"V-cycle), {dt:.1f} s wall", "cpu_model": cpu_model()}
+    log(f"cpu oracle: {cpu['value']} GFLOP/s on {threads} threads ({dt:.1f}s)")
+    runs = []
+
+    def full(nn, levels, sweep, nthreads):
+        oracle.set_num_threads(nthreads)
+        c = pm.Config(dims=(nn, nn, nn), levels=levels, pre=1, post=1, coarsest=1, sweep=sweep, restart=m)
+        b = oracle.spmv(nn, np.ones(nn ** 3), beta=args.beta)
+        t = time.perf_counter()
+        _, st = oracle.gmres_ir(nn, b, levels=levels, sweep=sweep, restart=m, tol=1e-9, beta=args.beta)
+        t = time.perf_counter() - t
+        cyc = pm.fixed_iteration_cycles(st.iters, m)
+        runs.append({"sample": f"{nn}^3 full FP64 solve to 1e-9 ({'symmetric' if sweep == 2 else 'forward'} GS)",
+                     "threads": nthreads, "seconds": round(t, 3), "iters": st.iters,
+                     "GFLOP/s": round(pm.solve_flops(c, cyc) / t / 1e9, 3)})
+        log(f"cpu oracle: {runs[-1]}")
+
+    if not args.no_cpu_extra:
+        full(16, 3, 2, threads)
+        full(128, 4, 0, threads)
+        oracle.set_num_threads(1)
+        c = pm.Config(dims=(128, 128, 128), levels=4, pre=1, post=1, coarsest=1, sweep=0, restart=m)
+        b = oracle.spmv(128, np.ones(128 ** 3), beta=args.beta)
+        t = time.perf_counter()
+        oracle.gmres_ir(128, b, levels=4, sweep=0, restart=m, max_iters=m, tol=0.0, beta=args.beta)
+        t = time.perf_counter() - t
+        runs.append({"sample": f"128^3 FP64 oracle, one GMRES({m}) cycle", "threads": 1, "seconds": round(t, 3),
+                     "GFLOP/s": round(pm.solve_flops(c, [m]) / t / 1e9, 3)})
+        log(f"cpu oracle: {runs[-1]}")
+        full(16, 3, 2, 1)
+        oracle.set_num_threads(threads)
+    cpu["more"] = runs
+    return cpu
+
+
+def solve_rates(cfg, cycles, inner_code, res, penalty, hp, pm):
+    """Algorithmic bytes of a whole fixed-iteration solve and the rate at
+    which each solver moved them; equal_efficiency_speedup is what the byte
+    model alone predicts (both solvers at the same GB/s), times the
+    iteration penalty."""
+    out = {}
+    for prec, code in (("mxp", inner_code), ("fp64", hp.F64)):
+        nbytes = sum(v for (kid, _), v in kernel_bytes_table(cfg, cycles, code, hp, pm).items()
+                     if kid != hp.K_FINISH)
+        out[prec] = {"bytes": nbytes}
+        if prec in res:
+            out[prec]["GBps"] = round(nbytes / res[prec]["s_per_solve"] / 1e9, 1)
+    out["equal_efficiency_speedup"] = round(out["fp64"]["bytes"] / out["mxp"]["bytes"] * penalty, 4)
+    return out
 
 
 def timed(driver, once, args, torch):

@@ -275,7 +275,9 @@ hpgmx_status hpgmx_stencil_grad_noalloc(hpgmx_handle h, const double *lam, const
 #define HPGMX_K_PERMUTE 13     /* natural <-> colour-blocked order            */
 #define HPGMX_K_SPMV 14        /* w = A z                                     */
 #define HPGMX_K_DOT 15         /* h1 = Q^T w                                  */
-#define HPGMX_K_COUNT 16
+#define HPGMX_K_FINISH 16      /* one-workgroup sums of the reduction passes' partial sums
+                                  (and the Givens step after the norm pass)  */
+#define HPGMX_K_COUNT 17
 hpgmx_status hpgmx_profile_get(hpgmx_handle h, int kernel, int level, double *total_ms,
                                long long *launches);
 

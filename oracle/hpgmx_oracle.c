@@ -30,6 +30,7 @@ typedef int64_t idx_t;
 
 /* Threads the OpenMP loops of this library use. */
 int or_num_threads(void) { return omp_get_max_threads(); }
+void or_set_num_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 
 /* ------------------------------------------------------------------------- */
 /* Problem definition: the 27-point stencil (Sec. 2 "Background": 27 nonzeros */

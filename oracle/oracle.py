@@ -52,6 +52,7 @@ def load():
     i, d = C.c_int, C.c_double
     lib.or_num_threads.argtypes = []
     lib.or_num_threads.restype = i
+    lib.or_set_num_threads.argtypes = [i]
     lib.or_coef.argtypes = [d, i, i, i, i]
     lib.or_coef.restype = d
     lib.or_spmv.argtypes = [i, i, i, d, i, _dp, _dp]
@@ -117,6 +118,11 @@ def absrow(dims, x, beta=0.5, faces_only=False):
 
 def num_threads():
     return load().or_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's OpenMP loops from now on (in this process)."""
+    load().or_set_num_threads(int(n))
 
 
 def color(i, j, k):

@@ -199,6 +199,32 @@ struct ProfScope {
     ~ProfScope() { c->prof_end(); }
 };
 
+// A reduction pass and its finish kernel, timed apart: the pass under
+// `kernel`, the finish kernel under HPGMX_K_FINISH.
+struct PassScope {
+    hpgmx_ctx *c;
+    static void split(void *a)
+    {
+        hpgmx_ctx *cc = (hpgmx_ctx *)a;
+        cc->prof_end();
+        cc->prof_begin(HPGMX_K_FINISH, 0);
+    }
+    PassScope(hpgmx_ctx *c_, int kernel, int level) : c(c_)
+    {
+        c->prof_begin(kernel, level);
+        if (c->prof) {
+            finish_hook = &PassScope::split;
+            finish_hook_arg = c;
+        }
+    }
+    ~PassScope()
+    {
+        finish_hook = nullptr;
+        finish_hook_arg = nullptr;
+        c->prof_end();
+    }
+};
+
 // ---- allocation plan ---------------------------------------------------------------------
 // Leading dimension of the Krylov basis: N rounded up to 64 elements plus a
 // skew (HPGMX_LDQ_PAD overrides the default for layout studies).
@@ -646,7 +672,7 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
         int its = 0;
         for (;;) {
             {
-                ProfScope ps(c, HPGMX_K_RESID64, 0);
+                PassScope ps(c, HPGMX_K_RESID64, 0);
                 launch_resid64(A0, c->x_int, c->b_int, c->r64, c->partials, c->ctrl, m, c->stream);
             }
             sc = read_scal(c);
@@ -679,15 +705,15 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                         launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k);
                     }
                     {
-                        ProfScope ps(c, HPGMX_K_DOT, 0);
+                        PassScope ps(c, HPGMX_K_DOT, 0);
                         launch_dot(N, 1, bp, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                     }
                     {
-                        ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
+                        PassScope ps(c, HPGMX_K_CGS_DOT, 0);
                         launch_cgs_dot(N, 1, bp, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, c->stream);
                     }
                     {
-                        ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
+                        PassScope ps(c, HPGMX_K_CGS_NORM, 0);
                         launch_cgs_norm(N, 1, bp, K.Q, ldq, k + 1, col(k + 1), c->partials, c->ctrl, k, m, c->stream);
                     }
                 };
@@ -1057,7 +1083,7 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
     if (status == HPGMX_OK) {
         for (;;) {
             {
-                ProfScope ps(c, HPGMX_K_RESID64, 0);
+                PassScope ps(c, HPGMX_K_RESID64, 0);
                 launch_bresid64(A0, K, tile_r(c, B, p, HPGMX_BK_RESID64, 0), B.x, B.b, B.r64, B.partials, B.ctrl,
                                 m, c->stream);
             }
@@ -1095,15 +1121,15 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
                                      B.ctrl, k);
                     }
                     {
-                        ProfScope ps(c, HPGMX_K_DOT, 0);
+                        PassScope ps(c, HPGMX_K_DOT, 0);
                         launch_dot(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, c->stream);
                     }
                     {
-                        ProfScope ps(c, HPGMX_K_CGS_DOT, 0);
+                        PassScope ps(c, HPGMX_K_CGS_DOT, 0);
                         launch_cgs_dot(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, c->stream);
                     }
                     {
-                        ProfScope ps(c, HPGMX_K_CGS_NORM, 0);
+                        PassScope ps(c, HPGMX_K_CGS_NORM, 0);
                         launch_cgs_norm(M, K, p, Kr.Q, ldq, k + 1, col(k + 1), B.partials, B.ctrl, k, m, c->stream);
                     }
                 };

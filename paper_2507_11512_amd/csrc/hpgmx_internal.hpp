@@ -251,6 +251,11 @@ int red_blocks(i64 N);
 // i * K + j (i < kb) over nb workgroups and applies `mode` to ctrl[j].
 void launch_finish(const double *partials, int nb, int kb, int K, int mode, Ctrl *ctrl, int k, int m,
                    hipStream_t s);
+// Profiling of the reduction passes: when set (on the calling host thread),
+// launch_finish calls finish_hook(finish_hook_arg) before it enqueues the
+// finish kernel, so that a pass and its finish kernel can be timed apart.
+extern thread_local void (*finish_hook)(void *);
+extern thread_local void *finish_hook_arg;
 // h1 = Q^T w alone (the first GEMVT when the SpMV runs as its own kernel).
 void launch_dot(i64 M, int K, Prec p, const void *Q, i64 ldq, int kb, const void *w, double *partials,
                 Ctrl *ctrl, hipStream_t s);

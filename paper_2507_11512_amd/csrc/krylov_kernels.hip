@@ -194,9 +194,13 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(const double *__restr
     }
 }
 
+thread_local void (*finish_hook)(void *) = nullptr;
+thread_local void *finish_hook_arg = nullptr;
+
 void launch_finish(const double *partials, int nb, int kb, int K, int mode, Ctrl *ctrl, int k, int m,
                    hipStream_t s)
 {
+    if (finish_hook) finish_hook(finish_hook_arg);
     hipLaunchKernelGGL(k_finish, dim3(K), dim3(kFinishThreads), 0, s, partials, nb, kb, K, mode, ctrl,
                        k, m);
     HPGMX_LAUNCH_CHECK();
@@ -347,19 +351,39 @@ __global__ __launch_bounds__(kBlock) void k_copy(i64 n16, const u32x4 *__restric
 // launchers
 static inline unsigned grid_n(i64 n) { return (unsigned)((n + kBlock - 1) / kBlock); }
 
-// Basis-count buckets: kernels are compiled for KB = 4, 8, ..., 64 columns.
+// Basis counts: kernels are compiled for every KB = 1..32 columns (restart
+// lengths up to 31 never read a column they do not use) and for buckets
+// KB = 36, 40, ..., 64 above, where columns kb..KB-1 re-read column kb-1
+// from cache.  (Buckets of four throughout cost the 30-step cycle's passes
+// about 4 % of their bandwidth.)
+#define HPGMX_KB_EXACT(N_)                  \
+    case N_: {                              \
+        constexpr int KB = N_;              \
+        HPGMX_KB_BODY;                      \
+    } break;
 #define HPGMX_KB_CASE(N_)                   \
     case N_: {                              \
         constexpr int KB = 4 * N_;          \
         HPGMX_KB_BODY;                      \
     } break;
-#define HPGMX_KB_SWITCH(kb)                                                                  \
-    switch (((kb) + 3) / 4) {                                                                \
-        HPGMX_KB_CASE(1) HPGMX_KB_CASE(2) HPGMX_KB_CASE(3) HPGMX_KB_CASE(4) HPGMX_KB_CASE(5) \
-        HPGMX_KB_CASE(6) HPGMX_KB_CASE(7) HPGMX_KB_CASE(8) HPGMX_KB_CASE(9) HPGMX_KB_CASE(10) \
-        HPGMX_KB_CASE(11) HPGMX_KB_CASE(12) HPGMX_KB_CASE(13) HPGMX_KB_CASE(14)              \
-        HPGMX_KB_CASE(15) HPGMX_KB_CASE(16)                                                  \
-    default: throw std::runtime_error("basis size out of range");                            \
+#define HPGMX_KB_SWITCH(kb)                                                                       \
+    if ((kb) >= 1 && (kb) <= 32) {                                                                \
+        switch (kb) {                                                                             \
+            HPGMX_KB_EXACT(1) HPGMX_KB_EXACT(2) HPGMX_KB_EXACT(3) HPGMX_KB_EXACT(4)               \
+            HPGMX_KB_EXACT(5) HPGMX_KB_EXACT(6) HPGMX_KB_EXACT(7) HPGMX_KB_EXACT(8)               \
+            HPGMX_KB_EXACT(9) HPGMX_KB_EXACT(10) HPGMX_KB_EXACT(11) HPGMX_KB_EXACT(12)            \
+            HPGMX_KB_EXACT(13) HPGMX_KB_EXACT(14) HPGMX_KB_EXACT(15) HPGMX_KB_EXACT(16)           \
+            HPGMX_KB_EXACT(17) HPGMX_KB_EXACT(18) HPGMX_KB_EXACT(19) HPGMX_KB_EXACT(20)           \
+            HPGMX_KB_EXACT(21) HPGMX_KB_EXACT(22) HPGMX_KB_EXACT(23) HPGMX_KB_EXACT(24)           \
+            HPGMX_KB_EXACT(25) HPGMX_KB_EXACT(26) HPGMX_KB_EXACT(27) HPGMX_KB_EXACT(28)           \
+            HPGMX_KB_EXACT(29) HPGMX_KB_EXACT(30) HPGMX_KB_EXACT(31) HPGMX_KB_EXACT(32)           \
+        }                                                                                         \
+    } else {                                                                                      \
+        switch (((kb) + 3) / 4) {                                                                 \
+            HPGMX_KB_CASE(9) HPGMX_KB_CASE(10) HPGMX_KB_CASE(11) HPGMX_KB_CASE(12)                \
+            HPGMX_KB_CASE(13) HPGMX_KB_CASE(14) HPGMX_KB_CASE(15) HPGMX_KB_CASE(16)               \
+        default: throw std::runtime_error("basis size out of range");                             \
+        }                                                                                         \
     }
 
 // Interleave widths: K = 1 (single solve) and the batch widths 2, 4, 8.

@@ -34,7 +34,7 @@ MOTIFS = {
     "SpMV": ("spmv_dot", "spmv"),   # spmv_dot: the reserved fused id
     "Restr": ("restrict",),
     "Prolong": ("prolong",),
-    "Ortho": ("cgs_dot", "cgs_norm", "normalize", "dot"),
+    "Ortho": ("cgs_dot", "cgs_norm", "normalize", "dot", "finish"),
     "Outer": ("resid64", "cast", "update", "permute"),
     "Other": ("trsm", "gemv"),
 }

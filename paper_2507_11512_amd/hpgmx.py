@@ -20,10 +20,10 @@ SOLVE_GRAPH = 2
 SOLVE_AUTOTUNE = 4
 
 K_GS, K_GS_ZERO, K_RESTRICT, K_PROLONG, K_SPMV_DOT, K_CGS_DOT, K_CGS_NORM, K_NORMALIZE, \
-    K_RESID64, K_CAST, K_TRSM, K_GEMV, K_UPDATE, K_PERMUTE, K_SPMV, K_DOT = range(16)
-K_COUNT = 16
+    K_RESID64, K_CAST, K_TRSM, K_GEMV, K_UPDATE, K_PERMUTE, K_SPMV, K_DOT, K_FINISH = range(17)
+K_COUNT = 17
 KERNEL_NAMES = ["gs", "gs_zero", "restrict", "prolong", "spmv_dot", "cgs_dot", "cgs_norm",
-                "normalize", "resid64", "cast", "trsm", "gemv", "update", "permute", "spmv", "dot"]
+                "normalize", "resid64", "cast", "trsm", "gemv", "update", "permute", "spmv", "dot", "finish"]
 
 # batched kernel kinds of the tile table
 BK_SPMV, BK_GS, BK_GS_ZERO, BK_RESTRICT, BK_RESID64 = range(5)

@@ -310,13 +310,21 @@ def test_solve_256_16bit_matrices(hp, p256, precision):
     assert st.converged and res <= 1e-9 and err <= 1e-8 and e64 <= 1e-8
 
 
+BANDWIDTH_BAR = 0.70   # of the 8 TB/s HBM peak, in algorithmic bytes per HIP-event second
+
+
 def test_bandwidth_320(hp, p320):
-    """The bandwidth bar at 320^3: per-kernel HIP-event times of a profiled
-    30-step mixed-precision solve against the kernels' algorithmic bytes.
-    The level-0 Gauss-Seidel colour passes (all slots), the SpMV and the
-    three CGS2 passes taken together each reach at least 70 % of the 8 TB/s
-    HBM peak (measured: about 75 %, 75 % and 77 %; boxes differ by a few
-    per cent)."""
+    """The bandwidth bar at 320^3, kernel by kernel: per-kernel HIP-event
+    times of a profiled 30-step mixed-precision solve against each kernel's
+    algorithmic bytes.  Every level-0 SpMV, Gauss-Seidel (all slots, and
+    from the zero guess) and orthogonalisation pass (h1 = Q^T w, the
+    reorthogonalisation, the update with its norm) reaches 70 % of the HBM
+    peak; the one-workgroup finish kernels of the reductions are timed
+    apart.  Not held to the bar: the coarser levels (160^3 and below: a
+    colour pass there takes a few microseconds, latency and launch bound),
+    the restriction (eq. (6) at the 1/8 of points that are injection points:
+    8 slots per coarse row, a short launch) and the FP64 outer residual (once
+    per restart cycle)."""
     import torch
     import bench
     from paper_2507_11512_amd import perfmodel as pm
@@ -326,22 +334,15 @@ def test_bandwidth_320(hp, p320):
     assert st.iters == 30
     cfg = pm.Config(dims=(320, 320, 320), levels=4, pre=1, post=1, coarsest=1, sweep=0, restart=30)
     table = bench.kernel_bytes_table(cfg, [30], 1, hp, pm)
-
-    def rate(kids):
-        nbytes = ms = 0.0
-        for kid in kids:
-            t, n = hp.profile_get(p320.h, kid, 0)
-            assert n > 0, hp.KERNEL_NAMES[kid]
-            nbytes += table[(kid, 0)]
-            ms += t
-        return nbytes / (ms / 1e3) / 1e9
-
     peak = bench.PEAK_HBM_GBPS
-    gs, spmv = rate([hp.K_GS]), rate([hp.K_SPMV])
-    cgs = rate([hp.K_DOT, hp.K_CGS_DOT, hp.K_CGS_NORM])
-    print(f"[bandwidth 320^3] GS {gs:.0f} GB/s ({gs / peak:.3f}), SpMV {spmv:.0f} ({spmv / peak:.3f}), "
-          f"CGS2 {cgs:.0f} ({cgs / peak:.3f})", flush=True)
-    assert gs >= 0.70 * peak and spmv >= 0.70 * peak and cgs >= 0.70 * peak
+    rates = {}
+    for kid in (hp.K_GS, hp.K_GS_ZERO, hp.K_SPMV, hp.K_DOT, hp.K_CGS_DOT, hp.K_CGS_NORM):
+        t, n = hp.profile_get(p320.h, kid, 0)
+        assert n > 0, hp.KERNEL_NAMES[kid]
+        rates[hp.KERNEL_NAMES[kid]] = table[(kid, 0)] / (t / 1e3) / 1e9 / peak
+    print("[bandwidth 320^3] " + ", ".join(f"{k} {v:.3f}" for k, v in rates.items()), flush=True)
+    low = {k: v for k, v in rates.items() if v < BANDWIDTH_BAR}
+    assert not low, low
 
 
 def test_largest_grid_512_sampled(hp):
