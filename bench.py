@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--inner", choices=["fp32", "fp16", "bf16", "fp16-mg", "bf16-mg"], default="fp32",
                     help="inner precision of the mixed-precision solver (fp16/bf16: 16-bit matrices; "
                          "fp16-mg/bf16-mg: matrices and multigrid work vectors in 16 bits)")
+    ap.add_argument("--cols", choices=["int32", "offset16"], default="int32",
+                    help="storage of the ELL column indices (int32, or 16-bit offsets; single right-hand side only)")
     ap.add_argument("--eager", action="store_true",
                     help="launch every kernel from the host instead of replaying captured inner steps")
     ap.add_argument("--nrhs", type=int, default=1,
@@ -81,8 +83,9 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
-    """Algorithmic bytes per (kernel id, level) over one solve with the given cycles."""
+def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4):
+    """Algorithmic bytes per (kernel id, level) over one solve with the given
+    cycles (idx: bytes of a stored column index)."""
     from collections import defaultdict
     B = defaultdict(float)
     L = pm.level_dims(cfg.dims, cfg.levels)
@@ -95,14 +98,14 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
             for c in range(8):
                 cr = rows // 8  # even dims on every level but possibly the coarsest
                 B[(hp.K_GS_ZERO, l)] += nsweeps_zero * pm.gs_colour_bytes(
-                    cr, pm.zero_guess_active_slots(c), dtype)
+                    cr, pm.zero_guess_active_slots(c), dtype, idx)
             full = (cfg.coarsest - 1) if coarsest else (cfg.pre - 1 + cfg.post)
-            B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.gs_colour_bytes(rows // 8, pm.SLOTS, dtype)
+            B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.gs_colour_bytes(rows // 8, pm.SLOTS, dtype, idx)
             if not coarsest:
                 rc = pm.nrows(L[l + 1])
                 # one forward pre-sweep from zero: the restriction reads 8 slots
-                B[(hp.K_RESTRICT, l)] += (pm.restrict_after_sweep_bytes(rc, dtype) if cfg.pre == 1 and cfg.sweep == 0
-                                          else pm.restrict_bytes(rc, dtype))
+                B[(hp.K_RESTRICT, l)] += (pm.restrict_after_sweep_bytes(rc, dtype, idx=idx)
+                                          if cfg.pre == 1 and cfg.sweep == 0 else pm.restrict_bytes(rc, dtype, idx))
                 B[(hp.K_PROLONG, l)] += pm.prolong_bytes(rc, dtype)
 
     N = pm.nrows(cfg.dims)
@@ -110,13 +113,13 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
     mg16 = dtype in (hp.F16_MG, hp.BF16_MG)
     cast_mg = N * (w + pm.mgb(dtype)) if mg16 else 0   # scaled 16-bit copy of the V-cycle input
     for kk in cycles:
-        B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
+        B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N, idx)
         B[(hp.K_CAST, 0)] += N * (8 + w)
         B[(hp.K_FINISH, 0)] += FINISH_PARTIALS * 8                   # the residual's norm
         for k in range(kk):
             B[(hp.K_CAST, 0)] += cast_mg
             vcyc()
-            B[(hp.K_SPMV, 0)] += pm.spmv_bytes(N, dtype)
+            B[(hp.K_SPMV, 0)] += pm.spmv_bytes(N, dtype, idx)
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, 1)
             B[(hp.K_CGS_DOT, 0)] += pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)
@@ -125,7 +128,7 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm):
         B[(hp.K_CAST, 0)] += cast_mg
         vcyc()
         B[(hp.K_UPDATE, 0)] += N * (16 + pm.mgb(dtype))
-    B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N)
+    B[(hp.K_RESID64, 0)] += pm.resid64_bytes(N, idx)
     B[(hp.K_PERMUTE, 0)] += 3 * 2 * N * 8
     return B
 
@@ -222,7 +225,8 @@ def main():
     N = n ** 3
     log(f"setup {n}^3 levels={L} (device: {torch.cuda.get_device_name(0)})")
     t = time.time()
-    P = hp.Problem(n, beta=args.beta, levels=L, sweep="forward")
+    P = hp.Problem(n, beta=args.beta, levels=L, sweep="forward", cols=args.cols)
+    idx = 2 if args.cols == "offset16" else 4
     b = P.rhs_from_x(torch.ones(N, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
     log(f"setup done in {time.time() - t:.2f}s")
@@ -283,7 +287,7 @@ def main():
     prof_precs = () if args.no_profile else (("mxp", inner_code),) if args.no_fp64 else (("mxp", inner_code), ("fp64", hp.F64))
     for prec, dt_code in prof_precs:
         _, st = P.solve(b, tol=0.0, restart=m, max_iters=args.iters, precision=PREC[prec], profile=True)
-        profile_kernels(hp, P.h, kernel_bytes_table(cfg, cycles, dt_code, hp, pm), prec, kernels)
+        profile_kernels(hp, P.h, kernel_bytes_table(cfg, cycles, dt_code, hp, pm, idx), prec, kernels)
         log(f"profiled {prec} solve: {st.solve_ms:.1f} ms with events")
     mxp_k = {k: v for k, v in kernels.items() if k.endswith("_mxp")}
     dom_name = max(mxp_k, key=lambda k: mxp_k[k]["total_ms"]) if mxp_k else None
@@ -305,7 +309,7 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(args, n, N, L, m, cfg, pm, np)
 
-    traffic = load_traffic(f"{n}^3", dom_name) if dominant else None
+    traffic = load_traffic(f"{n}^3" + ("" if args.cols == "int32" else " offset16"), dom_name) if dominant else None
     if args.report:
         write_report(args.report, driver,
                      {"grid": f"{n} x {n} x {n} ({N} unknowns)",
@@ -335,7 +339,7 @@ def main():
         "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta={args.beta:g}, GMRES({m})-IR ({args.inner} inner), {L}-level "
                                f"V-cycle fwd multicolour GS 1/1/1, {args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L,
-                   "iters_per_solve": args.iters,
+                   "iters_per_solve": args.iters, "column_indices": args.cols,
                    "launch": "eager" if args.eager else "hipGraph per inner step"},
         "fp64_gflops": round(fp64_gflops, 2) if fp64_gflops else None,
         "speedup_vs_fp64": round(value / fp64_gflops, 4) if fp64_gflops else None,
@@ -345,7 +349,7 @@ def main():
         "validation": val,
         "fp64_ms_per_step": round(res["fp64"]["s_per_solve"] * 1e3, 3) if "fp64" in res else None,
         "flops_per_solve": flops,
-        "solve_bytes": solve_rates(cfg, cycles, inner_code, res, penalty, hp, pm),
+        "solve_bytes": solve_rates(cfg, cycles, inner_code, res, penalty, hp, pm, idx),
         "roofline": {"bound": "hbm", "kernel": dom_name,
                      "achieved": dominant["GBps"] if dominant else None, "peak": PEAK_HBM_GBPS,
                      "unit": "GB/s", "frac": dominant["frac_peak"] if dominant else None,
@@ -418,14 +422,14 @@ def cpu_baseline(args, n, N, L, m, cfg, pm, np):
     return cpu
 
 
-def solve_rates(cfg, cycles, inner_code, res, penalty, hp, pm):
+def solve_rates(cfg, cycles, inner_code, res, penalty, hp, pm, idx=4):
     """Algorithmic bytes of a whole fixed-iteration solve and the rate at
     which each solver moved them; equal_efficiency_speedup is what the byte
     model alone predicts (both solvers at the same GB/s), times the
     iteration penalty."""
     out = {}
     for prec, code in (("mxp", inner_code), ("fp64", hp.F64)):
-        nbytes = sum(v for (kid, _), v in kernel_bytes_table(cfg, cycles, code, hp, pm).items()
+        nbytes = sum(v for (kid, _), v in kernel_bytes_table(cfg, cycles, code, hp, pm, idx).items()
                      if kid != hp.K_FINISH)
         out[prec] = {"bytes": nbytes}
         if prec in res:
@@ -481,6 +485,8 @@ def run_batched(args, hp, pm, torch, np):
         raise SystemExit(f"--nrhs must be at most {hp.MAX_BATCH}")
     if args.inner.endswith("-mg"):
         raise SystemExit("batched runs keep FP32 multigrid vectors: --inner fp32, fp16 or bf16")
+    if args.cols != "int32":
+        raise SystemExit("batched runs read int32 column indices")
     if args.validation != "standard":
         raise SystemExit("batched runs validate in the standard mode only")
     from paper_2507_11512_amd import driver

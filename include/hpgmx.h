@@ -158,6 +158,20 @@ hpgmx_status hpgmx_setup_problem(const hpgmx_problem_desc *desc, void *hip_strea
 hpgmx_status hpgmx_setup_problem_stencil(const hpgmx_stencil_desc *desc, void *hip_stream,
                                          hpgmx_handle *out);
 
+/* Storage of the ELL column indices of every level (Sec. 3.2 "ELLPACK matrix
+ * format").  HPGMX_COLS_INT32 (the default): one int32 column index per slot.
+ * HPGMX_COLS_OFFSET16: the index of slot s of a row p of colour c stored as
+ * the 16-bit offset col - p - D[c][s], with D a table of 8 x 26 offsets taken
+ * from interior rows of the generated matrix; padded slots hold a reserved
+ * value.  It halves the index bytes every ELL pass moves (the paper notes
+ * that index fetches limit the mixed-precision gain of the smoother and the
+ * SpMV, Sec. 4); hpgmx_mg_setup fails with EINVAL if an offset does not fit
+ * 16 bits (odd level extents of a few hundred and more).  The batched entry
+ * points need int32 indices.  Must precede hpgmx_mg_setup. */
+#define HPGMX_COLS_INT32 0
+#define HPGMX_COLS_OFFSET16 1
+hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
+
 /* Device bytes the hierarchy of `mg` plus the Krylov workspace for a
  * restart length `restart` need, for every inner dtype whose bit
  * (1 << hpgmx_dtype) is set in dtype_mask. */

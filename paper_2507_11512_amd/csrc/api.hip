@@ -83,6 +83,7 @@ struct Batch {
 struct hpgmx_ctx {
     hpgmx_problem_desc prob{};  // grid size (beta is unused once `stencil` is set)
     Stencil stencil{};
+    bool cols16 = false;        // column format of the hierarchy (hpgmx_set_column_format)
     hipStream_t stream = nullptr;
     int device = 0;
     bool mg_ready = false;
@@ -298,7 +299,7 @@ void ensure_prec(hpgmx_ctx *c, Prec p)
         if (p != P32) only.v32 = nullptr, only.d32 = nullptr;
         if (p != P16) only.v16 = nullptr, only.d16 = nullptr;
         if (p != PB16) only.vb16 = nullptr, only.db16 = nullptr;
-        launch_generate(only, c->stencil, c->stream);
+        launch_generate(only, c->stencil, nullptr, c->stream);
     }
 }
 
@@ -379,7 +380,7 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
     if (p != P64) ensure_prec(c, P64);
 }
 
-size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, unsigned mask)
+size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, unsigned mask, bool cols16)
 {
     size_t tot = 0;
     auto add = [&](size_t b) { tot += round_up(b ? b : 1); };
@@ -397,7 +398,12 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
     for (int l = 0; l < mg.levels; ++l) {
         const size_t N = (size_t)nx * ny * nz;
         const size_t E = (size_t)ell_entries((i64)N, ell_chunk_log2());
-        add(E * 4);  // columns
+        if (cols16) {
+            add(E * sizeof(short));  // 16-bit column offsets and their table
+            add(sizeof(ColMap));
+        } else {
+            add(E * sizeof(int));    // int32 column indices
+        }
         for (int q = 0; q < 4; ++q) {
             if (!mat[q]) continue;
             const size_t vb = q == P64 ? 8 : q == P32 ? 4 : 2;
@@ -412,6 +418,7 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
             }
         nx /= 2; ny /= 2; nz /= 2;
     }
+    add(sizeof(int));  // the generation's overflow flag
     add(sizeof(Ctrl));
     add((size_t)kMaxRedBlocks * kMaxBasis * 8);
     add(N0 * 8); add((N0 + 1) * 8); add(N0 * 8);  // b, x, r in FP64
@@ -1280,6 +1287,12 @@ Prec check_batch_dtype(int dtype)
     return p;
 }
 
+// The batched kernels read int32 column indices.
+void check_batch_cols(hpgmx_ctx *c)
+{
+    if (c->cols16) fail(HPGMX_EINVAL, "batched calls need int32 column indices (HPGMX_COLS_INT32)");
+}
+
 void check_nrhs(int nrhs)
 {
     if (nrhs < 1 || nrhs > kMaxBatch) fail(HPGMX_EINVAL, "nrhs must be 1..8");
@@ -1385,7 +1398,7 @@ hpgmx_status hpgmx_workspace_bytes(hpgmx_handle h, const hpgmx_mg_desc *mg, int 
         check_ptr(bytes, "bytes");
         if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
         if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
-        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0x3Fu);
+        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0x3Fu, h->cols16);
         return HPGMX_OK;
     });
 }
@@ -1400,6 +1413,17 @@ hpgmx_status hpgmx_bind_workspace(hpgmx_handle h, void *dev_ptr, size_t bytes)
         h->ws_base = (char *)dev_ptr;
         h->ws_size = bytes;
         h->ws_used = 0;
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
+        if (h->mg_ready) fail(HPGMX_ESTATE, "the column format must be chosen before hpgmx_mg_setup");
+        if (format != HPGMX_COLS_INT32 && format != HPGMX_COLS_OFFSET16) fail(HPGMX_EINVAL, "unknown column format");
+        h->cols16 = format == HPGMX_COLS_OFFSET16;
         return HPGMX_OK;
     });
 }
@@ -1425,19 +1449,34 @@ hpgmx_status hpgmx_mg_setup(hpgmx_handle h, const hpgmx_mg_desc *mg)
         h->mg = *mg;
         h->lv.resize(mg->levels);
         int nx = pd.nx, ny = pd.ny, nz = pd.nz;
+        std::vector<ColMap> maps(mg->levels);
+        int *overflow = (int *)h->dalloc(sizeof(int));
+        hip_check(hipMemsetAsync(overflow, 0, sizeof(int), h->stream), "hipMemsetAsync");
         for (int l = 0; l < mg->levels; ++l) {
             Matrix &A = h->lv[l].A;
             A.g = make_geom(nx, ny, nz);
             A.clog2 = ell_chunk_log2();
-            A.col = (int *)h->dalloc((size_t)ell_entries(A.g.N, A.clog2) * 4);
+            A.c16 = h->cols16;
+            A.col = h->dalloc((size_t)ell_entries(A.g.N, A.clog2) * (A.c16 ? sizeof(short) : sizeof(int)));
+            if (A.c16) {
+                A.cmap = (int *)h->dalloc(sizeof(ColMap));
+                maps[l] = make_colmap(A.g);
+                hip_check(hipMemcpyAsync(A.cmap, &maps[l], sizeof(ColMap), hipMemcpyHostToDevice, h->stream),
+                          "hipMemcpyAsync");
+            }
             alloc_matrix_prec(h, A, P64);
             alloc_matrix_prec(h, A, P32);
-            launch_generate(A, h->stencil, h->stream);
+            launch_generate(A, h->stencil, overflow, h->stream);
             nx /= 2; ny /= 2; nz /= 2;
         }
         ensure_common(h);
         if (!h->host_scal) hip_check(hipHostMalloc((void **)&h->host_scal, 256, hipHostMallocDefault), "hipHostMalloc");
+        int over = 0;
+        hip_check(hipMemcpyAsync(&over, overflow, sizeof(int), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync");
         hip_check(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        if (over)
+            fail(HPGMX_EINVAL, "a column offset of the generated matrix does not fit 16 bits (odd level "
+                               "extents beyond a few hundred); choose even grid extents");
         h->mg_ready = true;
         return HPGMX_OK;
     });
@@ -1701,6 +1740,7 @@ hpgmx_status hpgmx_batch_autotune(hpgmx_handle h, int nrhs, int dtype, hpgmx_bat
         check_ready(h);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         Batch &B = ensure_batch(h, batch_width(nrhs));
         autotune(h, B, p);
         if (out) fill_tuning(h, B, p, out);
@@ -1714,6 +1754,7 @@ hpgmx_status hpgmx_batch_set_tuning(hpgmx_handle h, int nrhs, int dtype, const h
         check_ready(h);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         check_ptr(in, "in");
         const int K = batch_width(nrhs);
         for (int k = 0; k < HPGMX_BK_COUNT; ++k)
@@ -1742,6 +1783,7 @@ hpgmx_status hpgmx_batch_get_tuning(hpgmx_handle h, int nrhs, int dtype, hpgmx_b
         check_ready(h);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         check_ptr(out, "out");
         Batch &B = ensure_batch(h, batch_width(nrhs));
         fill_tuning(h, B, p, out);
@@ -1756,6 +1798,7 @@ hpgmx_status hpgmx_spmv_batched(hpgmx_handle h, int level, int dtype, int nrhs, 
         check_level(h, level, false);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         check_ptr(X, "X");
         check_ptr(Y, "Y");
         const int K = batch_width(nrhs), vt = vt_of(p);
@@ -1779,6 +1822,7 @@ hpgmx_status hpgmx_smooth_batched(hpgmx_handle h, int level, int dtype, int swee
         check_level(h, level, false);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         if (sweep < HPGMX_GS_FORWARD || sweep > HPGMX_GS_SYMMETRIC) fail(HPGMX_EINVAL, "unknown sweep kind");
         check_ptr(R, "R");
         check_ptr(Z, "Z");
@@ -1804,6 +1848,7 @@ hpgmx_status hpgmx_presmooth_restrict_batched(hpgmx_handle h, int level, int dty
         check_level(h, level, true);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         if (sweep < HPGMX_GS_FORWARD || sweep > HPGMX_GS_SYMMETRIC) fail(HPGMX_EINVAL, "unknown sweep kind");
         if (nsweeps < 0 || nsweeps > 16) fail(HPGMX_EINVAL, "nsweeps must be 0..16");
         check_ptr(R, "R");
@@ -1830,6 +1875,7 @@ hpgmx_status hpgmx_vcycle_batched(hpgmx_handle h, int dtype, int nrhs, const voi
         check_ready(h);
         check_nrhs(nrhs);
         const Prec p = check_batch_dtype(dtype);
+        check_batch_cols(h);
         check_ptr(R, "R");
         check_ptr(Z, "Z");
         const int K = batch_width(nrhs), vt = vt_of(p);
@@ -1855,6 +1901,7 @@ hpgmx_status hpgmx_gmres_ir_solve_batched(hpgmx_handle h, int nrhs, const double
         check_ptr(X, "X");
         check_solve_desc(desc);
         check_batch_dtype(desc->inner_dtype);
+        check_batch_cols(h);
         return bsolve(h, nrhs, B, X, desc, stats);
     });
 }

@@ -14,6 +14,7 @@
 #include "hpgmx_internal.hpp"
 
 #include <stdexcept>
+#include <type_traits>
 
 namespace hpgmx {
 
@@ -43,28 +44,77 @@ template <> __device__ __forceinline__ bf16 from_t<bf16, float>(float v) { retur
 
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// Column of a slot from its 16-bit offset d (see ColMap): p + D + d, or the
+// zero entry N for a padded slot.
+__device__ __forceinline__ int ell_col(short d, i64 p, int D, i64 N)
+{
+    return d == (short)kPadOffset ? (int)N : (int)(p + D + d);
+}
+
+// The 16-bit offset of slot s from the row's pair words.
+__device__ __forceinline__ short pair_half(unsigned w, int s)
+{
+    return (short)(unsigned short)((s & 1) ? (w >> 16) : (w & 0xffffu));
+}
+
+// Loads the pair words of the slots in MASK (a pair is loaded when either of
+// its slots is in MASK).
+template <unsigned MASK>
+__device__ __forceinline__ void load_pairs(const unsigned *__restrict__ offc, const EllRow &er, unsigned (&w)[kPairs])
+{
+#pragma unroll
+    for (int t = 0; t < kPairs; ++t)
+        if (MASK & (3u << (2 * t))) w[t] = __builtin_nontemporal_load(offc + er.pbase + (i64)t * er.pstride);
+}
+
+// Colour block of row p (the number of block starts at or below p).
+__device__ __forceinline__ int row_colour(const Geom &g, i64 p)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) c += p >= g.off[i] ? 1 : 0;
+    return c;
+}
+
+// Kernels whose rows are of any colour read the column-offset table from LDS
+// (each lane indexes it with its row's colour); call before any early exit.
+__device__ __forceinline__ void stage_colmap(int *lds, const int *__restrict__ cmap)
+{
+    for (int t = threadIdx.x; t < kColMapSize; t += blockDim.x) lds[t] = cmap[t];
+    __syncthreads();
+}
+
 // sum over the slots in MASK of a(p,s) * x[col(p,s)] (slot order), in the
 // arithmetic type T; x may be stored in a narrower type X (the 16-bit
-// multigrid vectors), widened after the gathers.
-template <typename T, typename V, unsigned MASK, typename X>
-__device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const int *__restrict__ offc,
-                                         const X *x, const EllRow &er)
+// multigrid vectors), widened after the gathers.  Columns: C16 = false,
+// int32 indices (offc: int, laid out as the values); C16 = true, 16-bit
+// offsets in pairs (offc: unsigned pair words), decoded with Dc, the column
+// offsets D[c][.] of the row's colour, and N, the zero entry.
+template <typename T, typename V, unsigned MASK, bool C16, typename X>
+__device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const void *__restrict__ offc,
+                                         const X *x, const EllRow &er, i64 p, const int *Dc, i64 N)
 {
     V a[kSlots];
     int ci[kSlots];
+    unsigned w[kPairs];
 #pragma unroll
     for (int s = 0; s < kSlots; ++s) {
         if (MASK & (1u << s)) {
             const i64 e = er.base + (i64)s * er.stride;
             a[s] = ld_stream(offv + e);
-            ci[s] = ld_stream(offc + e);
+            if constexpr (!C16) ci[s] = ld_stream(static_cast<const int *>(offc) + e);
         }
     }
+    if constexpr (C16) load_pairs<MASK>(static_cast<const unsigned *>(offc), er, w);
     sched_fence();
     X xv[kSlots];
 #pragma unroll
-    for (int s = 0; s < kSlots; ++s)
-        if (MASK & (1u << s)) xv[s] = x[ci[s]];
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) {
+            if constexpr (C16) xv[s] = x[ell_col(pair_half(w[s >> 1], s), p, Dc[s], N)];
+            else xv[s] = x[ci[s]];
+        }
+    }
     sched_fence();
     T acc = (T)0;
 #pragma unroll
@@ -74,6 +124,14 @@ __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const int *
 }
 
 constexpr unsigned kAllSlots = (1u << kSlots) - 1u;
+
+// Calls f(std::true_type) for a matrix with 16-bit column offsets, else
+// f(std::false_type) (the kernels' C16 parameter).
+template <typename F> static void with_cols(const Matrix &A, F &&f)
+{
+    if (A.c16) f(std::true_type{});
+    else f(std::false_type{});
+}
 
 // ---- XCD-aware work distribution -------------------------------------------------------
 // MI355X dispatches workgroup b to XCD b % 8, and each XCD has its own L2.

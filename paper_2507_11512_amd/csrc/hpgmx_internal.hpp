@@ -17,7 +17,8 @@
 //    kernels gather from holds N + 1 entries and keeps entry N at zero, so a
 //    padded slot contributes 0 * 0 whatever the rest of the vector holds.
 //    Column indices are shared by all value precisions (FP64, FP32, FP16,
-//    BF16).
+//    BF16): int32 (the default), or compressed to 16-bit offsets (see
+//    ColMap), chosen per handle before the hierarchy is built.
 #pragma once
 
 #include <hip/hip_bf16.h>
@@ -116,13 +117,20 @@ constexpr int kGsZeroBackward = 2;  // backward sweep from z = 0
 // the whole matrix ([s*N + p]).  clog2 > 0: rows are grouped in chunks of
 // C = 2^clog2 and each chunk is slot-major on its own (SELL-C with sigma = 1):
 // a wavefront's 26 slots then lie in one contiguous 26*C-entry region.
+// The 16-bit column offsets are stored in pairs: slots 2t and 2t + 1 of a
+// row share one 32-bit word (low half slot 2t), the 13 pair words laid out
+// as the values (pbase + t * pstride), so a row's offsets take 13 loads.
+constexpr int kPairs = kSlots / 2;
 struct EllRow {
-    i64 base, stride;
+    i64 base, stride;    // values: slot s at base + s * stride
+    i64 pbase, pstride;  // offset pairs: pair t at pbase + t * pstride (32-bit words)
 };
 __host__ __device__ inline EllRow ell_row(i64 p, i64 N, int clog2)
 {
-    if (clog2 == 0) return {p, N};
-    return {(p >> clog2) * ((i64)kSlots << clog2) + (p & ((1ll << clog2) - 1)), 1ll << clog2};
+    if (clog2 == 0) return {p, N, p, N};
+    const i64 lane = p & ((1ll << clog2) - 1), chunk = p >> clog2;
+    return {chunk * ((i64)kSlots << clog2) + lane, 1ll << clog2, chunk * ((i64)kPairs << clog2) + lane,
+            1ll << clog2};
 }
 // Entries each off-diagonal ELL array holds (the last chunk is padded).
 __host__ __device__ inline i64 ell_entries(i64 N, int clog2)
@@ -132,10 +140,26 @@ __host__ __device__ inline i64 ell_entries(i64 N, int clog2)
     return (i64)kSlots * ((N + C - 1) / C) * C;
 }
 
+// Compressed column indices (optional).  Slot s of row p, a row of colour c,
+// stores the 16-bit offset d = col - p - D[c][s] with D a per-matrix table of
+// 8 x 26 column offsets (the offsets of an interior row of that colour); a
+// padded slot stores kPadOffset and reads column N.  Any matrix whose
+// offsets all fit 16 bits is stored exactly (mg_setup checks every entry and
+// fails otherwise).  This halves the index bytes of every ELL pass, which
+// are 104 of the 224 bytes of an FP32 Gauss-Seidel row with int32 indices.
+constexpr int kPadOffset = -32768;
+constexpr int kColMapSize = 8 * kSlots;
+struct ColMap {
+    int d[8][kSlots];
+};
+ColMap make_colmap(const Geom &g);
+
 struct Matrix {
     Geom g;
-    int clog2 = 0;       // ELL chunking (see ell_row)
-    int *col = nullptr;  // [26][N]
+    int clog2 = 0;         // ELL chunking (see ell_row)
+    bool c16 = false;         // column format: int32 indices, or 16-bit offsets
+    void *col = nullptr;      // int32 [laid out as the values], or 16-bit offset pairs (see ell_row)
+    int *cmap = nullptr;      // the ColMap D[c][s] on the device (16-bit offsets)
     double *v64 = nullptr, *d64 = nullptr;
     float *v32 = nullptr, *d32 = nullptr;
     __half *v16 = nullptr, *d16 = nullptr;
@@ -204,7 +228,10 @@ struct Stencil {
     double c[27];
 };
 Stencil stencil_from_beta(double beta);
-void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s);
+// Writes the values of the precisions A has arrays for and, if A.col is set,
+// the column offsets (A.cmap must hold make_colmap(A.g)); an offset that does
+// not fit 16 bits sets *overflow (device int, may be null if A.col is null).
+void launch_generate(const Matrix &A, const Stencil &st, int *overflow, hipStream_t s);
 // out[t] = sum over rows of lam_p * x_{neighbour t of p} (x, lam in internal
 // order, x gathered with its zero entry at N); `partials` as for the
 // Krylov reductions.

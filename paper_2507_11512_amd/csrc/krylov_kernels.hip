@@ -97,20 +97,25 @@ __device__ void givens_column(Ctrl *c, int k, int m, double nrm2)
 }
 
 // ---- FP64 outer residual r = b - A x with ||r||^2 (Alg. 3, residual step) ----
-__global__ __launch_bounds__(kBlock) void k_resid64(i64 N, int clog2, int remap, const double *__restrict__ offv,
-                                                    const int *__restrict__ offc,
+template <bool C16>
+__global__ __launch_bounds__(kBlock) void k_resid64(Geom g, int clog2, int remap, const double *__restrict__ offv,
+                                                    const void *__restrict__ offc, const int *__restrict__ cmap,
                                                     const double *__restrict__ diag,
                                                     const double *__restrict__ x,
                                                     const double *__restrict__ b,
                                                     double *__restrict__ r, double *partials)
 {
+    __shared__ int cm[C16 ? kColMapSize : 1];
+    if constexpr (C16) stage_colmap(cm, cmap);
+    const i64 N = g.N;
     double acc[1] = {0.0};
     RowLoop rl = row_loop(N, remap);
     i64 p;
     while (rl.next(p)) {
         const EllRow er = ell_row(p, N, clog2);
         const double bp = b[p];
-        const double v = ld_stream(diag + p) * x[p] + ell_row_dot<double, double, kAllSlots>(offv, offc, x, er);
+        const int *Dc = C16 ? cm + row_colour(g, p) * kSlots : nullptr;
+        const double v = ld_stream(diag + p) * x[p] + ell_row_dot<double, double, kAllSlots, C16>(offv, offc, x, er, p, Dc, N);
         const double rv = bp - v;
         r[p] = rv;
         acc[0] += rv * rv;
@@ -209,11 +214,16 @@ void launch_finish(const double *partials, int nb, int kb, int K, int mode, Ctrl
 // ---- stencil correlation for the adjoint gradient -------------------------------------------
 // acc[t] = sum_p lam_p x_{col(p,t)} for the 26 off-diagonal slots and
 // acc[13] = sum_p lam_p x_p; padded slots read the zero entry x_N.
-__global__ __launch_bounds__(kBlock) void k_stencil_corr(i64 N, int clog2, const int *__restrict__ offc,
+template <bool C16>
+__global__ __launch_bounds__(kBlock) void k_stencil_corr(Geom g, int clog2, const void *__restrict__ offc,
+                                                         const int *__restrict__ cmap,
                                                          const double *__restrict__ lam,
                                                          const double *__restrict__ x,
                                                          double *partials)
 {
+    __shared__ int cm[C16 ? kColMapSize : 1];
+    if constexpr (C16) stage_colmap(cm, cmap);
+    const i64 N = g.N;
     double acc[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) acc[t] = 0.0;
@@ -222,8 +232,17 @@ __global__ __launch_bounds__(kBlock) void k_stencil_corr(i64 N, int clog2, const
         const EllRow er = ell_row(p, N, clog2);
         const double l = lam[p];
         int ci[kSlots];
+        if constexpr (C16) {
+            const int *Dc = cm + row_colour(g, p) * kSlots;
+            unsigned w[kPairs];
+            load_pairs<kAllSlots>(static_cast<const unsigned *>(offc), er, w);
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) ci[s] = ld_stream(offc + er.base + (i64)s * er.stride);
+            for (int s = 0; s < kSlots; ++s) ci[s] = ell_col(pair_half(w[s >> 1], s), p, Dc[s], N);
+        } else {
+#pragma unroll
+            for (int s = 0; s < kSlots; ++s)
+                ci[s] = ld_stream(static_cast<const int *>(offc) + er.base + (i64)s * er.stride);
+        }
         const double xp = x[p];
         sched_fence();
         double xv[kSlots];
@@ -474,8 +493,10 @@ void launch_resid64(const Matrix &A, const double *x, const double *b, double *r
                     double *partials, Ctrl *ctrl, int m, hipStream_t s)
 {
     const unsigned nb = (unsigned)red_blocks(A.g.N);
-    hipLaunchKernelGGL(k_resid64, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, xcd_remap_enabled(), A.v64, A.col,
-                       A.d64, x, b, r, partials);
+    with_cols(A, [&](auto c16) {
+        hipLaunchKernelGGL(k_resid64<decltype(c16)::value>, dim3(nb), dim3(kBlock), 0, s, A.g, A.clog2,
+                           xcd_remap_enabled(), A.v64, (const void *)A.col, A.cmap, A.d64, x, b, r, partials);
+    });
     HPGMX_LAUNCH_CHECK();
     launch_finish(partials, (int)nb, 1, 1, kFinishResid, ctrl, 0, m, s);
 }
@@ -496,8 +517,10 @@ void launch_stencil_correlation(const Matrix &A, const double *lam, const double
                                 double *partials, Ctrl *ctrl, hipStream_t s)
 {
     const unsigned nb = (unsigned)red_blocks(A.g.N);
-    hipLaunchKernelGGL(k_stencil_corr, dim3(nb), dim3(kBlock), 0, s, A.g.N, A.clog2, A.col, lam, x,
-                       partials);
+    with_cols(A, [&](auto c16) {
+        hipLaunchKernelGGL(k_stencil_corr<decltype(c16)::value>, dim3(nb), dim3(kBlock), 0, s, A.g, A.clog2,
+                           (const void *)A.col, A.cmap, lam, x, partials);
+    });
     HPGMX_LAUNCH_CHECK();
     launch_finish(partials, (int)nb, 27, 1, kFinishCorr, ctrl, 0, 0, s);
 }

@@ -97,7 +97,27 @@ __device__ bf16 to_bf16_rne(double x)
     return __float2bfloat16((float)round_to_format(x, 8, -126, 3.3895313892515355e38));
 }
 
-__global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil st, int *col, double *v64,
+// Column-offset table of a geometry (see ColMap): for each colour, the
+// offsets col - p of an interior row of that colour (every row of that colour
+// in a grid of even extents); 0 where the colour has no interior row.
+ColMap make_colmap(const Geom &g)
+{
+    ColMap m{};
+    for (int c = 0; c < 8; ++c) {
+        const int i0 = (c & 1) ? 1 : 2, j0 = ((c >> 1) & 1) ? 1 : 2, k0 = (((c >> 2) & 1) ^ 1) ? 1 : 2;
+        if (i0 + 1 >= g.nx || j0 + 1 >= g.ny || k0 + 1 >= g.nz) continue;
+        const i64 p0 = to_internal(g, i0, j0, k0);
+        for (int s = 0; s < kSlots; ++s) {
+            int di, dj, dk;
+            slot_offset(s, di, dj, dk);
+            m.d[c][s] = (int)(to_internal(g, i0 + di, j0 + dj, k0 + dk) - p0);
+        }
+    }
+    return m;
+}
+
+__global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil st, void *col, int c16,
+                                                     const int *__restrict__ cmap, int *overflow, double *v64,
                                                      double *d64, float *v32, float *d32,
                                                      __half *v16, __half *d16, bf16 *vb16,
                                                      bf16 *db16)
@@ -107,6 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil 
     int i, j, k;
     from_internal(g, p, i, j, k);
     const i64 N = g.N;
+    const int c = colour_of(i, j, k);
     const EllRow er = ell_row(p, N, clog2);
     for (int s = 0; s < kSlots; ++s) {
         int di, dj, dk;
@@ -115,7 +136,17 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil 
         const bool in = ii >= 0 && ii < g.nx && jj >= 0 && jj < g.ny && kk >= 0 && kk < g.nz;
         const double a = in ? st.c[9 * (dk + 1) + 3 * (dj + 1) + (di + 1)] : 0.0;
         const i64 e = er.base + (i64)s * er.stride;
-        if (col) col[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)N;
+        if (col && !c16) static_cast<int *>(col)[e] = in ? (int)to_internal(g, ii, jj, kk) : (int)N;
+        if (col && c16) {
+            short o = (short)kPadOffset;
+            if (in) {
+                const i64 d = to_internal(g, ii, jj, kk) - p - cmap[c * kSlots + s];
+                if (d < -32767 || d > 32767) atomicOr(overflow, 1);
+                else o = (short)d;
+            }
+            // slot s is the low (even s) or high half of pair word s / 2
+            static_cast<short *>(col)[2 * (er.pbase + (i64)(s >> 1) * er.pstride) + (s & 1)] = o;
+        }
         if (v64) v64[e] = a;
         if (v32) v32[e] = (float)a;
         if (v16) v16[e] = to_half_rne(a);
@@ -128,10 +159,12 @@ __global__ __launch_bounds__(kBlock) void k_generate(Geom g, int clog2, Stencil 
     if (db16) db16[p] = to_bf16_rne(dg);
 }
 
-void launch_generate(const Matrix &A, const Stencil &st, hipStream_t s)
+void launch_generate(const Matrix &A, const Stencil &st, int *overflow, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, A.clog2, st, A.col,
-                       A.v64, A.d64, A.v32, A.d32, A.v16, A.d16, A.vb16, A.db16);
+    if (A.col && A.c16 && (!A.cmap || !overflow))
+        throw std::runtime_error("launch_generate: column map or flag missing");
+    hipLaunchKernelGGL(k_generate, dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g, A.clog2, st, A.col, (int)A.c16,
+                       A.cmap, overflow, A.v64, A.d64, A.v32, A.d32, A.v16, A.d16, A.vb16, A.db16);
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -219,20 +252,24 @@ template <typename F> static void with_matrix(const Matrix &A, Prec p, F &&f)
 // y = A x over all N rows (Sec. 3.2 ELL SpMV); with `scale`, y = (A x) * *scale
 // (the unnormalised-basis scale of the column x was computed from).  x is a
 // multigrid vector (type S), y a Krylov vector (type T).
-template <typename V, typename S>
-__global__ __launch_bounds__(kBlock) void k_spmv(i64 N, int clog2, int remap, const V *__restrict__ offv,
-                                                 const int *__restrict__ offc,
+template <typename V, typename S, bool C16>
+__global__ __launch_bounds__(kBlock) void k_spmv(Geom g, int clog2, int remap, const V *__restrict__ offv,
+                                                 const void *__restrict__ offc, const int *__restrict__ cmap,
                                                  const V *__restrict__ diag,
                                                  const S *__restrict__ x,
                                                  typename VecT<V>::T *__restrict__ y,
                                                  const double *scale)
 {
     using T = typename VecT<V>::T;
+    __shared__ int cm[C16 ? kColMapSize : 1];
+    if constexpr (C16) stage_colmap(cm, cmap);
+    const i64 N = g.N;
     const i64 p = gtid_xcd(remap);
     if (p >= N) return;
     const EllRow er = ell_row(p, N, clog2);
     const T dx = to_t<T>(ld_stream(diag + p)) * to_t<T>(x[p]);
-    const T v = dx + ell_row_dot<T, V, kAllSlots>(offv, offc, x, er);
+    const int *Dc = C16 ? cm + row_colour(g, p) * kSlots : nullptr;
+    const T v = dx + ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N);
     y[p] = scale ? v * (T)*scale : v;
 }
 
@@ -243,9 +280,11 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
         using S = decltype(sv);
         using T = typename VecT<V>::T;
-        hipLaunchKernelGGL((k_spmv<V, S>), dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g.N, A.clog2,
-                           std::is_same<V, double>::value ? xcd_remap_enabled() : full_grid_order(A.g, 1),
-                           (const V *)v, A.col, (const V *)d, (const S *)x, (T *)y, scale);
+        with_cols(A, [&](auto c16) {
+            hipLaunchKernelGGL((k_spmv<V, S, decltype(c16)::value>), dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g,
+                               A.clog2, std::is_same<V, double>::value ? xcd_remap_enabled() : full_grid_order(A.g, 1),
+                               (const V *)v, (const void *)A.col, A.cmap, (const V *)d, (const S *)x, (T *)y, scale);
+        });
     });
     HPGMX_LAUNCH_CHECK();
 }
@@ -260,10 +299,10 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 // that couple to colours relaxed earlier in the sweep (the others still hold
 // zero, and skipping them gives the same result bit for bit).  r and z are
 // stored in S and the row is evaluated in T.
-template <typename V, typename S, unsigned MASK>
+template <typename V, typename S, unsigned MASK, bool C16>
 __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
                                                const V *__restrict__ offv,
-                                               const int *__restrict__ offc,
+                                               const void *__restrict__ offc, const int *__restrict__ cmapc,
                                                const V *__restrict__ diag,
                                                const S *__restrict__ r, S *z)
 {
@@ -274,7 +313,7 @@ __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clo
     const EllRow er = ell_row(p, N, clog2);
     const T rp = to_t<T>(r[p]);
     const T dg = to_t<T>(ld_stream(diag + p));
-    z[p] = from_t<S>((rp - ell_row_dot<T, V, MASK>(offv, offc, z, er)) / dg);
+    z[p] = from_t<S>((rp - ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmapc, N)) / dg);
 }
 
 template <typename V, typename S, unsigned MASK>
@@ -282,8 +321,11 @@ static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void
 {
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
-    hipLaunchKernelGGL((k_gs<V, S, MASK>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt, A.g.N,
-                       A.clog2, xcd_remap_enabled(), v, A.col, d, (const S *)r, (S *)z);
+    with_cols(A, [&](auto c16) {
+        hipLaunchKernelGGL((k_gs<V, S, MASK, decltype(c16)::value>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0,
+                           cnt, A.g.N, A.clog2, xcd_remap_enabled(), v, (const void *)A.col,
+                           A.c16 ? A.cmap + c * kSlots : nullptr, d, (const S *)r, (S *)z);
+    });
     HPGMX_LAUNCH_CHECK();
 }
 
@@ -322,10 +364,10 @@ void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, v
 // The colour-4 block of the fine level holds the injection points in the
 // coarse level's natural order: row q of that block is coarse point
 // (q % cx, (q / cx) % cy, q / (cx cy)).  Only those rows are evaluated.
-template <typename V, typename S>
+template <typename V, typename S, bool C16>
 __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2, int remap,
                                                      const V *__restrict__ offv,
-                                                     const int *__restrict__ offc,
+                                                     const void *__restrict__ offc, const int *__restrict__ cmap4,
                                                      const V *__restrict__ diag,
                                                      const S *__restrict__ r,
                                                      const S *__restrict__ z,
@@ -337,7 +379,8 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2
     const i64 N = gf.N, p = gf.off[4] + q;
     const EllRow er = ell_row(p, N, clog2);
     const T rp = to_t<T>(r[p]);
-    const T acc = to_t<T>(ld_stream(diag + p)) * to_t<T>(z[p]) + ell_row_dot<T, V, kAllSlots>(offv, offc, z, er);
+    const T acc = to_t<T>(ld_stream(diag + p)) * to_t<T>(z[p]) +
+                  ell_row_dot<T, V, kAllSlots, C16>(offv, offc, z, er, p, cmap4, N);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
     rc[to_internal(gc, I, J, K)] = from_t<S>(rp - acc);
 }
@@ -348,9 +391,12 @@ void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, co
     with_matrix(Af, p, [&](auto *v, auto *d, auto sv) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
         using S = decltype(sv);
-        hipLaunchKernelGGL((k_restrict<V, S>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, Af.g, gc, Af.clog2,
-                           xcd_remap_enabled(), (const V *)v, Af.col, (const V *)d, (const S *)r, (const S *)z,
-                           (S *)rc);
+        with_cols(Af, [&](auto c16) {
+            hipLaunchKernelGGL((k_restrict<V, S, decltype(c16)::value>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s,
+                               Af.g, gc, Af.clog2, xcd_remap_enabled(), (const V *)v, (const void *)Af.col,
+                               Af.c16 ? Af.cmap + 4 * kSlots : nullptr, (const V *)d, (const S *)r, (const S *)z,
+                               (S *)rc);
+        });
     });
     HPGMX_LAUNCH_CHECK();
 }
@@ -366,10 +412,11 @@ void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, co
 // backward) and without r or the diagonal.  Exact in exact arithmetic; the
 // rounding differs from the full formula by the rounding of the colour-4
 // relaxation.
-template <typename V, typename S, unsigned MASK>
+template <typename V, typename S, unsigned MASK, bool C16>
 __global__ __launch_bounds__(kBlock) void k_restrict_after_sweep(Geom gf, Geom gc, int clog2, int remap,
                                                                  const V *__restrict__ offv,
-                                                                 const int *__restrict__ offc,
+                                                                 const void *__restrict__ offc,
+                                                                 const int *__restrict__ cmap4,
                                                                  const S *__restrict__ z,
                                                                  S *__restrict__ rc)
 {
@@ -378,7 +425,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_after_sweep(Geom gf, Geom g
     if (q >= gc.N) return;
     const i64 N = gf.N, p = gf.off[4] + q;
     const EllRow er = ell_row(p, N, clog2);
-    const T acc = ell_row_dot<T, V, MASK>(offv, offc, z, er);
+    const T acc = ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmap4, N);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
     rc[to_internal(gc, I, J, K)] = from_t<S>(-acc);
 }
@@ -391,12 +438,18 @@ void launch_restrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, bool 
     with_matrix(Af, p, [&](auto *v, auto *, auto sv) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
         using S = decltype(sv);
-        if (forward)
-            hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kFwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, Af.g,
-                               gc, Af.clog2, xcd_remap_enabled(), (const V *)v, Af.col, (const S *)z, (S *)rc);
-        else
-            hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kBwd>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s, Af.g,
-                               gc, Af.clog2, xcd_remap_enabled(), (const V *)v, Af.col, (const S *)z, (S *)rc);
+        with_cols(Af, [&](auto c16) {
+            constexpr bool C = decltype(c16)::value;
+            const int *cm4 = Af.c16 ? Af.cmap + 4 * kSlots : nullptr;
+            if (forward)
+                hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kFwd, C>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s,
+                                   Af.g, gc, Af.clog2, xcd_remap_enabled(), (const V *)v, (const void *)Af.col, cm4,
+                                   (const S *)z, (S *)rc);
+            else
+                hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kBwd, C>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s,
+                                   Af.g, gc, Af.clog2, xcd_remap_enabled(), (const V *)v, (const void *)Af.col, cm4,
+                                   (const S *)z, (S *)rc);
+        });
     });
     HPGMX_LAUNCH_CHECK();
 }

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libhpgmx.so")
 
 F64, F32, F16, BF16, F16_MG, BF16_MG = 0, 1, 2, 3, 4, 5
 GS_FORWARD, GS_BACKWARD, GS_SYMMETRIC = 0, 1, 2
+COLS_INT32, COLS_OFFSET16 = 0, 1
 SOLVE_PROFILE = 1
 SOLVE_GRAPH = 2
 SOLVE_AUTOTUNE = 4
@@ -42,7 +43,7 @@ EXPORTS = ["hpgmx_setup_problem", "hpgmx_setup_problem_stencil", "hpgmx_stencil_
            "hpgmx_batch_get_tuning", "hpgmx_workspace_bytes_batched", "hpgmx_spmv_batched",
            "hpgmx_smooth_batched", "hpgmx_vcycle_batched", "hpgmx_gmres_ir_solve_batched",
            "hpgmx_presmooth_restrict", "hpgmx_presmooth_restrict_batched", "hpgmx_krylov_cycle_get",
-           "hpgmx_stencil_grad_noalloc"]
+           "hpgmx_stencil_grad_noalloc", "hpgmx_set_column_format"]
 
 
 class ProblemDesc(C.Structure):
@@ -86,6 +87,7 @@ def _load():
         "hpgmx_setup_problem_stencil": [C.POINTER(StencilDesc), vp, C.POINTER(H)],
         "hpgmx_stencil_grad": [H, vp, vp, vp],
         "hpgmx_stencil_grad_noalloc": [H, vp, vp, vp],
+        "hpgmx_set_column_format": [H, i],
         "hpgmx_workspace_bytes": [H, C.POINTER(MgDesc), i, C.c_uint, C.POINTER(C.c_size_t)],
         "hpgmx_bind_workspace": [H, vp, C.c_size_t],
         "hpgmx_mg_setup": [H, C.POINTER(MgDesc)],
@@ -207,6 +209,10 @@ def workspace_bytes(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD, re
 
 def bind_workspace(h, tensor):
     _check(h, lib.hpgmx_bind_workspace(h, _ptr(tensor), tensor.numel() * tensor.element_size()))
+
+
+def set_column_format(h, fmt):
+    _check(h, lib.hpgmx_set_column_format(h, int(fmt)))
 
 
 def mg_setup(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD):
@@ -393,7 +399,7 @@ class Problem:
              "fp16-mg": F16_MG, "bf16-mg": BF16_MG}
 
     def __init__(self, n, beta=0.5, levels=4, sweep="forward", pre=1, post=1, coarsest=1,
-                 stream=None, workspace=None, coef=None):
+                 stream=None, workspace=None, coef=None, cols="int32"):
         import torch
         self.dims = (n, n, n) if isinstance(n, int) else tuple(n)
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
@@ -405,6 +411,7 @@ class Problem:
             self.h = setup_problem_stencil(*self.dims, coef, stream=self.stream)
         sw = self._SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
         try:
+            set_column_format(self.h, {"int32": COLS_INT32, "offset16": COLS_OFFSET16}[cols])
             if workspace is not None:
                 bind_workspace(self.h, workspace)
                 self.workspace = workspace

@@ -7,13 +7,16 @@ The same model is used for the FP64 and the mixed-precision solver, so their
 ratio is the time ratio times the iteration-count penalty min(1, n_d/n_ir).
 
 Bytes are algorithmic: what each kernel must move once -- every matrix
-entry (value + int32 column for the 26 off-diagonal slots, value for the
+entry (value + column index for the 26 off-diagonal slots, value for the
 diagonal), every vector entry read or written once per launch; the repeated
-reads of neighbouring vector entries are not counted.
+reads of neighbouring vector entries are not counted.  A column index is
+`idx` bytes: 4 for int32 indices (the default format), 2 for the 16-bit
+column offsets of HPGMX_COLS_OFFSET16.
 """
 from dataclasses import dataclass
 
 SLOTS = 26
+IDX = 4   # bytes of a stored int32 column index
 
 
 def dims_of(n):
@@ -137,18 +140,18 @@ def mgb(dtype):
     return {0: 8, 4: 2, 5: 2}.get(dtype, 4)
 
 
-def gs_colour_bytes(rows, active_slots, dtype):
+def gs_colour_bytes(rows, active_slots, dtype, idx=IDX):
     """One colour launch: matrix slice for `active_slots` slots + diagonal,
     r read, z written, neighbour z counted once per row."""
     v, w = vb(dtype), mgb(dtype)
-    return rows * (active_slots * (v + 4) + v + 3 * w)
+    return rows * (active_slots * (v + idx) + v + 3 * w)
 
 
-def spmv_bytes(rows, dtype):
+def spmv_bytes(rows, dtype, idx=IDX):
     """The SpMV of an inner step: x is the V-cycle's output (a multigrid
     vector), y a Krylov vector."""
     v = vb(dtype)
-    return rows * (SLOTS * (v + 4) + v + mgb(dtype) + wb(dtype))
+    return rows * (SLOTS * (v + idx) + v + mgb(dtype) + wb(dtype))
 
 
 def cgs_pass_bytes(rows, kb, dtype):
@@ -161,43 +164,43 @@ def cgs_dot_bytes(rows, kb, dtype):
     return rows * (kb + 1) * wb(dtype)
 
 
-def restrict_bytes(coarse_rows, dtype):
+def restrict_bytes(coarse_rows, dtype, idx=IDX):
     v, w = vb(dtype), mgb(dtype)
-    return coarse_rows * (SLOTS * (v + 4) + v + 3 * w)
+    return coarse_rows * (SLOTS * (v + idx) + v + 3 * w)
 
 
-def restrict_after_sweep_bytes(coarse_rows, dtype, slots=8, K=1):
+def restrict_after_sweep_bytes(coarse_rows, dtype, slots=8, K=1, idx=IDX):
     """The fused restriction after a single sweep from zero: `slots` matrix
     slots of each injection row (8 after a forward sweep), z read once and
     r_c written (K vectors)."""
     v, w = vb(dtype), mgb(dtype)
-    return coarse_rows * (slots * (v + 4) + 2 * K * w)
+    return coarse_rows * (slots * (v + idx) + 2 * K * w)
 
 
 def prolong_bytes(coarse_rows, dtype):
     return coarse_rows * 3 * mgb(dtype)
 
 
-def resid64_bytes(rows):
-    return rows * (SLOTS * 12 + 8 + 4 * 8)
+def resid64_bytes(rows, idx=IDX):
+    return rows * (SLOTS * (8 + idx) + 8 + 4 * 8)
 
 
 # ---- bytes of the batched kernels (K interleaved right-hand sides) -------------------------------
 # The matrix is read once per launch for all K vectors; vector traffic scales
-# with K.  Per right-hand side and row the matrix share is (26 (v + 4) + v) / K.
+# with K.  Per right-hand side and row the matrix share is (26 (v + IDX) + v) / K.
 def bgs_colour_bytes(rows, active_slots, dtype, K):
     v, w = vb(dtype), wb(dtype)
-    return rows * (active_slots * (v + 4) + v + 3 * K * w)
+    return rows * (active_slots * (v + IDX) + v + 3 * K * w)
 
 
 def bspmv_bytes(rows, dtype, K):
     v, w = vb(dtype), wb(dtype)
-    return rows * (SLOTS * (v + 4) + v + 2 * K * w)
+    return rows * (SLOTS * (v + IDX) + v + 2 * K * w)
 
 
 def brestrict_bytes(coarse_rows, dtype, K):
     v, w = vb(dtype), wb(dtype)
-    return coarse_rows * (SLOTS * (v + 4) + v + 3 * K * w)
+    return coarse_rows * (SLOTS * (v + IDX) + v + 3 * K * w)
 
 
 def bprolong_bytes(coarse_rows, dtype, K):
@@ -206,7 +209,7 @@ def bprolong_bytes(coarse_rows, dtype, K):
 
 def bresid64_bytes(rows, K):
     """b - A x (b, x read, r written) plus the norm pass over r."""
-    return rows * (SLOTS * 12 + 8 + 4 * 8 * K)
+    return rows * (SLOTS * (8 + IDX) + 8 + 4 * 8 * K)
 
 
 def bdot_bytes(rows, kb, dtype, K):

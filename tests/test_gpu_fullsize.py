@@ -262,6 +262,23 @@ def test_solve_batched_192(hp, p192):
         assert stats[j].converged and err <= 1e-8, (j, err)
 
 
+def test_solve_320_offset16_columns(hp, p320):
+    """The benchmark's solve with 16-bit column offsets gives the int32
+    solve's iterates bit for bit (same matrix, same arithmetic)."""
+    import torch
+    print("[setup] 320^3 with 16-bit column offsets", flush=True)
+    P = hp.Problem(320, beta=0.5, levels=4, sweep="forward", cols="offset16")
+    try:
+        b = p320.rhs_from_x(torch.ones(320 ** 3, dtype=torch.float64, device="cuda"))
+        xa, sa = p320.solve(b, tol=1e-9, restart=30, precision="mxp", graph=True)
+        xb, sb = P.solve(b, tol=1e-9, restart=30, precision="mxp", graph=True)
+        print(f"[320^3 offset16] iters {sb.iters} (int32 {sa.iters}), {sb.solve_ms:.0f} ms (int32 {sa.solve_ms:.0f} ms)",
+              flush=True)
+        assert sb.converged and sa.iters == sb.iters and torch.equal(xa, xb)
+    finally:
+        P.close()
+
+
 def test_solve_320_symmetric_beta0_to_1e11(hp):
     """The symmetric member of the stencil family (beta = 0) at 320^3: the
     1e-9 residual leaves ||x - 1|| / ||1|| near 3e-7 (a smaller smallest

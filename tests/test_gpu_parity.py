@@ -399,6 +399,89 @@ def test_batched_calls_reject_16bit_vectors(hp):
     assert e.value.status == -1
 
 
+@pytest.mark.parametrize("dims,levels", [((16, 16, 16), 3), ((24, 20, 14), 2), ((12, 10, 9), 1), ((64, 64, 64), 4)])
+def test_offset16_columns_equal_int32(hp, dims, levels):
+    """16-bit column offsets (HPGMX_COLS_OFFSET16) store the same matrix as
+    int32 indices, and the kernels do the same arithmetic in the same order,
+    so every entry point gives bit-identical results with both formats: the
+    SpMV, every sweep, both restrictions, the V-cycle in all six precisions,
+    the FP64 right-hand side, the stencil correlation and solves."""
+    import torch
+    A = hp.Problem(dims, beta=0.5, levels=levels, sweep="forward")
+    B = hp.Problem(dims, beta=0.5, levels=levels, sweep="forward", cols="offset16")
+    try:
+        for dtype in ALL:
+            for lvl in range(levels):
+                d = ldims(dims, lvl)
+                x = dev(rnd(inputs.uniform(d, 1600 + lvl), dtype), dtype)
+                ya, yb = (dev(np.zeros(x.numel()), kdt(dtype)) for _ in range(2))
+                hp.spmv(A.h, lvl, dtype, x, ya)
+                hp.spmv(B.h, lvl, dtype, x, yb)
+                assert torch.equal(ya, yb), ("spmv", dtype, lvl)
+                for sweep in (0, 1, 2):
+                    for zero in (False, True):
+                        za, zb = x.clone(), x.clone()
+                        r = dev(rnd(inputs.uniform(d, 1610 + lvl), dtype), dtype)
+                        hp.smooth(A.h, lvl, dtype, sweep, r, za, zero_guess=zero)
+                        hp.smooth(B.h, lvl, dtype, sweep, r, zb, zero_guess=zero)
+                        assert torch.equal(za, zb), ("smooth", dtype, lvl, sweep, zero)
+                if lvl + 1 < levels:
+                    dc = ldims(dims, lvl + 1)
+                    for sweep in (0, 1):
+                        out = []
+                        for P in (A, B):
+                            z = dev(np.zeros(x.numel()), dtype)
+                            rc = dev(np.zeros(int(np.prod(dc))), dtype)
+                            hp.presmooth_restrict(P.h, lvl, dtype, sweep, 1, x, z, rc)
+                            rc2 = dev(np.zeros(int(np.prod(dc))), dtype)
+                            hp.restrict_residual(P.h, lvl, dtype, x, z, rc2)
+                            out.append((z, rc, rc2))
+                        assert all(torch.equal(a, b) for a, b in zip(*out)), ("restrict", dtype, lvl, sweep)
+            x = dev(rnd(inputs.uniform(dims, 1620), dtype), dtype)
+            za, zb = (dev(np.zeros(x.numel()), dtype) for _ in range(2))
+            hp.vcycle(A.h, dtype, x, za)
+            hp.vcycle(B.h, dtype, x, zb)
+            assert torch.equal(za, zb), ("vcycle", dtype)
+        u = dev(inputs.uniform(dims, 1630), 0)
+        assert torch.equal(A.rhs_from_x(u), B.rhs_from_x(u))
+        lam = dev(inputs.uniform(dims, 1631), 0)
+        assert torch.equal(A.stencil_grad(lam, u), B.stencil_grad(lam, u))
+        b = A.rhs_from_x(torch.ones(A.N, dtype=torch.float64, device="cuda"))
+        for precision in ("fp64", "mxp", "bf16-mg"):
+            xa, sa = A.solve(b, tol=1e-9, precision=precision)
+            xb, sb = B.solve(b, tol=1e-9, precision=precision)
+            assert sa.iters == sb.iters and torch.equal(xa, xb), precision
+    finally:
+        A.close()
+        B.close()
+
+
+def test_offset16_columns_errors(hp):
+    """Offsets that do not fit 16 bits (odd extents: the column offsets of a
+    colour drift with the row) are refused at setup; batched calls need int32
+    indices."""
+    import torch
+    with pytest.raises(hp.HpgmxError) as e:
+        hp.Problem((3, 401, 401), levels=1, cols="offset16")
+    assert e.value.status == -1
+    P = hp.Problem((16, 16, 16), levels=3, cols="offset16")
+    try:
+        B = torch.zeros((2, P.N), dtype=torch.float64, device="cuda")
+        with pytest.raises(hp.HpgmxError) as e:
+            P.solve_batched(B)
+        assert e.value.status == -1
+    finally:
+        P.close()
+    h = hp.setup_problem(8, 8, 8, beta=0.5)
+    try:
+        hp.mg_setup(h, 2)
+        with pytest.raises(hp.HpgmxError) as e:
+            hp.set_column_format(h, hp.COLS_OFFSET16)   # after the hierarchy exists
+        assert e.value.status == -4
+    finally:
+        hp.destroy(h)
+
+
 def test_solve_edge_cases(hp):
     import torch
     dims = (16, 16, 16)

@@ -54,3 +54,12 @@ def test_batched_bytes_reduce_to_single_at_k1():
     assert pm.bresid64_bytes(1000, 1) == pm.resid64_bytes(1000)
     # FP32, k = 8: the matrix (216 B/row) is shared, 8 vectors of 4 B in and out
     assert pm.bspmv_bytes(1, 1, 8) == 26 * 8 + 4 + 2 * 8 * 4
+
+
+def test_single_vector_row_bytes():
+    # FP32 SpMV: 26 (4 + 4) + 4 + 4 + 4; GS pass: 26 (4 + 4) + 4 + 3 * 4
+    assert pm.spmv_bytes(1, 1) == 220 and pm.gs_colour_bytes(1, 26, 1) == 224
+    # with 16-bit column offsets: 26 (4 + 2) + 12 and 26 (4 + 2) + 16
+    assert pm.spmv_bytes(1, 1, idx=2) == 168 and pm.gs_colour_bytes(1, 26, 1, idx=2) == 172
+    # FP64: 26 (8 + 4) + 8 + 2 * 8 and 26 (8 + 4) + 8 + 3 * 8
+    assert pm.spmv_bytes(1, 0) == 336 and pm.gs_colour_bytes(1, 26, 0) == 344
