@@ -43,13 +43,22 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def parse():
+SWEEP_CODE = {"forward": 0, "backward": 1, "symmetric": 2}
+
+
+def parse(argv=None):
+    from paper_2507_11512_amd import presets
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--preset", choices=sorted(presets.PRESETS), default=None,
+                    help="a named workload; sets the defaults of --n, --levels, --sweep, --inner, --nrhs, "
+                         "--cols and --beta (flags given explicitly still win)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=320, help="grid edge (the workload is n^3)")
     ap.add_argument("--levels", type=int, default=4)
+    ap.add_argument("--sweep", choices=["forward", "backward", "symmetric"], default="forward",
+                    help="Gauss-Seidel sweep of the smoother (one pre-, one post-sweep per level)")
     ap.add_argument("--beta", type=float, default=0.5,
                     help="nonsymmetry of the stencil's x-neighbour entries (0: the symmetric member)")
     ap.add_argument("--iters", type=int, default=300, help="inner steps per timed solve")
@@ -80,7 +89,38 @@ def parse():
                     help="fill this many seconds per timed phase with solves instead of running --steps "
                          "(the benchmark's official running time is 1800 s)")
     ap.add_argument("--report", default=None, help="write the benchmark report (text) to this path")
-    return ap.parse_args()
+    pre, _ = ap.parse_known_args(argv)
+    if pre.preset:
+        ap.set_defaults(**presets.PRESETS[pre.preset].bench_defaults())
+    return ap.parse_args(argv)
+
+
+def vcycle_bytes(cfg, B, hp, pm, colour, restrict_after, restrict_full, prolong):
+    """Adds the algorithmic bytes of one V-cycle to B[(kernel id, level)].
+    colour(rows, slots): one colour launch over `rows` rows reading `slots`
+    off-diagonal slots; restrict_after(rc, slots): the restriction after a
+    single sweep from zero; restrict_full(rc), prolong(rc): the general
+    restriction and the prolongation onto rc coarse rows."""
+    L = pm.level_dims(cfg.dims, cfg.levels)
+    fwd, sym = cfg.sweep != 1, cfg.sweep == 2
+    per_sweep = 15 if sym else 8   # the backward half of a symmetric sweep skips its first colour
+    for l, d in enumerate(L):
+        cr = pm.nrows(d) // 8      # even dims on every level but possibly the coarsest
+        coarsest = l == cfg.levels - 1
+        nsw = cfg.coarsest if coarsest else cfg.pre
+        if nsw > 0:                # the first sweep starts from zero
+            for c in range(8):
+                B[(hp.K_GS_ZERO, l)] += colour(cr, pm.zero_guess_active_slots(c, fwd))
+            if sym:
+                B[(hp.K_GS, l)] += 7 * colour(cr, pm.SLOTS)
+        full = max(nsw - 1, 0) + (0 if coarsest else cfg.post)
+        B[(hp.K_GS, l)] += full * per_sweep * colour(cr, pm.SLOTS)
+        if not coarsest:
+            rc = pm.nrows(L[l + 1])
+            # one forward (backward) sweep from zero: the restriction reads 8 (18) slots
+            B[(hp.K_RESTRICT, l)] += (restrict_after(rc, 8 if fwd else 18) if cfg.pre == 1 and not sym
+                                      else restrict_full(rc))
+            B[(hp.K_PROLONG, l)] += prolong(rc)
 
 
 def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4):
@@ -88,25 +128,13 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4):
     cycles (idx: bytes of a stored column index)."""
     from collections import defaultdict
     B = defaultdict(float)
-    L = pm.level_dims(cfg.dims, cfg.levels)
 
     def vcyc():
-        for l, d in enumerate(L):
-            rows = pm.nrows(d)
-            coarsest = l == cfg.levels - 1
-            nsweeps_zero = 1 if (cfg.coarsest if coarsest else cfg.pre) > 0 else 0
-            for c in range(8):
-                cr = rows // 8  # even dims on every level but possibly the coarsest
-                B[(hp.K_GS_ZERO, l)] += nsweeps_zero * pm.gs_colour_bytes(
-                    cr, pm.zero_guess_active_slots(c), dtype, idx)
-            full = (cfg.coarsest - 1) if coarsest else (cfg.pre - 1 + cfg.post)
-            B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.gs_colour_bytes(rows // 8, pm.SLOTS, dtype, idx)
-            if not coarsest:
-                rc = pm.nrows(L[l + 1])
-                # one forward pre-sweep from zero: the restriction reads 8 slots
-                B[(hp.K_RESTRICT, l)] += (pm.restrict_after_sweep_bytes(rc, dtype, idx=idx)
-                                          if cfg.pre == 1 and cfg.sweep == 0 else pm.restrict_bytes(rc, dtype, idx))
-                B[(hp.K_PROLONG, l)] += pm.prolong_bytes(rc, dtype)
+        vcycle_bytes(cfg, B, hp, pm,
+                     lambda rows, slots: pm.gs_colour_bytes(rows, slots, dtype, idx),
+                     lambda rc, slots: pm.restrict_after_sweep_bytes(rc, dtype, slots, idx=idx),
+                     lambda rc: pm.restrict_bytes(rc, dtype, idx),
+                     lambda rc: pm.prolong_bytes(rc, dtype))
 
     N = pm.nrows(cfg.dims)
     w = pm.wb(dtype)
@@ -137,23 +165,13 @@ def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
     """As kernel_bytes_table for K right-hand sides in lockstep."""
     from collections import defaultdict
     B = defaultdict(float)
-    L = pm.level_dims(cfg.dims, cfg.levels)
 
     def vcyc():
-        for l, d in enumerate(L):
-            rows = pm.nrows(d)
-            coarsest = l == cfg.levels - 1
-            nsweeps_zero = 1 if (cfg.coarsest if coarsest else cfg.pre) > 0 else 0
-            for c in range(8):
-                B[(hp.K_GS_ZERO, l)] += nsweeps_zero * pm.bgs_colour_bytes(
-                    rows // 8, pm.zero_guess_active_slots(c), dtype, K)
-            full = (cfg.coarsest - 1) if coarsest else (cfg.pre - 1 + cfg.post)
-            B[(hp.K_GS, l)] += max(full, 0) * 8 * pm.bgs_colour_bytes(rows // 8, pm.SLOTS, dtype, K)
-            if not coarsest:
-                rc = pm.nrows(L[l + 1])
-                B[(hp.K_RESTRICT, l)] += (pm.restrict_after_sweep_bytes(rc, dtype, 8, K)
-                                          if cfg.pre == 1 and cfg.sweep == 0 else pm.brestrict_bytes(rc, dtype, K))
-                B[(hp.K_PROLONG, l)] += pm.bprolong_bytes(rc, dtype, K)
+        vcycle_bytes(cfg, B, hp, pm,
+                     lambda rows, slots: pm.bgs_colour_bytes(rows, slots, dtype, K),
+                     lambda rc, slots: pm.restrict_after_sweep_bytes(rc, dtype, slots, K),
+                     lambda rc: pm.brestrict_bytes(rc, dtype, K),
+                     lambda rc: pm.bprolong_bytes(rc, dtype, K))
 
     N = pm.nrows(cfg.dims)
     w = pm.wb(dtype)
@@ -221,11 +239,11 @@ def main():
     graph = not args.eager
     PREC = {"fp64": "fp64", "mxp": args.inner}
     n, L, m = args.n, args.levels, args.restart
-    cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=0, restart=m)
+    cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=SWEEP_CODE[args.sweep], restart=m)
     N = n ** 3
     log(f"setup {n}^3 levels={L} (device: {torch.cuda.get_device_name(0)})")
     t = time.time()
-    P = hp.Problem(n, beta=args.beta, levels=L, sweep="forward", cols=args.cols)
+    P = hp.Problem(n, beta=args.beta, levels=L, sweep=args.sweep, cols=args.cols)
     idx = 2 if args.cols == "offset16" else 4
     b = P.rhs_from_x(torch.ones(N, dtype=torch.float64, device="cuda"))
     torch.cuda.synchronize()
@@ -315,7 +333,7 @@ def main():
                      {"grid": f"{n} x {n} x {n} ({N} unknowns)",
                       "operator": f"27-point stencil, beta = {args.beta:g}, Dirichlet-truncated",
                       "solver": f"GMRES({m})-IR, {args.inner} inner / fp64 outer; {L}-level V-cycle, "
-                                "forward multicolour Gauss-Seidel 1/1/1",
+                                f"{args.sweep} multicolour Gauss-Seidel 1/1/1",
                       "inner steps per timed solve": args.iters,
                       "launch": "eager" if args.eager else "hipGraph per inner step",
                       "device": torch.cuda.get_device_name(0)},
@@ -337,8 +355,8 @@ def main():
                  + "-inner/f64-outer",
         "data": "synthetic: generated 27-point stencil, b = A*1, x0 = 0",
         "config": {"workload": f"hpg-mxp {n}^3 27-pt nonsym beta={args.beta:g}, GMRES({m})-IR ({args.inner} inner), {L}-level "
-                               f"V-cycle fwd multicolour GS 1/1/1, {args.iters} inner steps per solve",
-                   "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L,
+                               f"V-cycle {args.sweep} multicolour GS 1/1/1, {args.iters} inner steps per solve",
+                   "grid": [n, n, n], "unknowns": N, "restart": m, "levels": L, "sweep": args.sweep,
                    "iters_per_solve": args.iters, "column_indices": args.cols,
                    "launch": "eager" if args.eager else "hipGraph per inner step"},
         "fp64_gflops": round(fp64_gflops, 2) if fp64_gflops else None,
@@ -381,7 +399,7 @@ def cpu_baseline(args, n, N, L, m, cfg, pm, np):
     threads = oracle.num_threads()
     bh = oracle.spmv(n, np.ones(N), beta=args.beta)
     t0 = time.perf_counter()
-    oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0, beta=args.beta)
+    oracle.gmres_ir(n, bh, levels=L, sweep=cfg.sweep, restart=m, max_iters=args.cpu_iters, tol=0.0, beta=args.beta)
     dt = time.perf_counter() - t0
     cflops = pm.solve_flops(cfg, [args.cpu_iters])
     cpu = {"value": round(cflops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
@@ -492,12 +510,12 @@ def run_batched(args, hp, pm, torch, np):
     from paper_2507_11512_amd import driver
     graph = not args.eager
     n, L, m = args.n, args.levels, args.restart
-    cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=0, restart=m)
+    cfg = pm.Config(dims=(n, n, n), levels=L, pre=1, post=1, coarsest=1, sweep=SWEEP_CODE[args.sweep], restart=m)
     N = n ** 3
     from paper_2507_11512_amd import inputs
     log(f"setup {n}^3 levels={L}, {k} right-hand sides (device: {torch.cuda.get_device_name(0)})")
     t = time.time()
-    P = hp.Problem(n, beta=args.beta, levels=L, sweep="forward")
+    P = hp.Problem(n, beta=args.beta, levels=L, sweep=args.sweep)
     U_ = torch.stack([torch.from_numpy(inputs.batch_u((n, n, n), j)) for j in range(k)]).cuda()
     B = torch.empty_like(U_)
     for j in range(k):
@@ -580,7 +598,7 @@ def run_batched(args, hp, pm, torch, np):
         import oracle
         bh = B[0].cpu().numpy()
         t0 = time.perf_counter()
-        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=0, restart=m, max_iters=args.cpu_iters, tol=0.0,
+        _, sto = oracle.gmres_ir(n, bh, levels=L, sweep=cfg.sweep, restart=m, max_iters=args.cpu_iters, tol=0.0,
                                  beta=args.beta)
         dt = time.perf_counter() - t0
         cflops = pm.solve_flops(cfg, [args.cpu_iters])
@@ -608,7 +626,7 @@ def run_batched(args, hp, pm, torch, np):
                  + "-inner/f64-outer",
         "data": f"synthetic: generated 27-point stencil, b_j = A u_j, u_j ~ N(0,1) seeded 11512+j, x0 = 0",
         "config": {"workload": f"hpg-mxp batched {n}^3 27-pt nonsym beta={args.beta:g}, {k} right-hand sides, "
-                               f"GMRES({m})-IR ({args.inner} inner), {L}-level V-cycle fwd multicolour GS 1/1/1, "
+                               f"GMRES({m})-IR ({args.inner} inner), {L}-level V-cycle {args.sweep} multicolour GS 1/1/1, "
                                f"{args.iters} inner steps per solve",
                    "grid": [n, n, n], "unknowns": N, "nrhs": k, "restart": m, "levels": L,
                    "iters_per_solve": args.iters,

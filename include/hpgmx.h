@@ -172,6 +172,22 @@ hpgmx_status hpgmx_setup_problem_stencil(const hpgmx_stencil_desc *desc, void *h
 #define HPGMX_COLS_OFFSET16 1
 hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
 
+/* Data layout and work order, for layout studies and tests; the defaults
+ * are the tuned ones and a production solve needs no call.  The choice
+ * changes where data sits and in which order workgroups take row tiles,
+ * never the arithmetic: results are bit-identical under every setting.
+ *   tile_order     0 = tiles in launch order, 1 = each of the eight XCDs
+ *                  takes one contiguous range of row tiles, 2 (default) =
+ *                  as 1, plus the slab order for the full-grid SpMV.
+ *   ell_chunk_log2 rows per ELL chunk as a power of two, 0..16 (0 =
+ *                  slot-major over the whole level; default 8).
+ *   ldq_pad        elements added between Krylov basis columns, even,
+ *                  0..2^20 (default 1088).
+ * A negative argument keeps that default.  EINVAL for values out of range;
+ * ESTATE after hpgmx_mg_setup (must precede it, and hpgmx_workspace_bytes
+ * when a workspace is bound). */
+hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad);
+
 /* Device bytes the hierarchy of `mg` plus the Krylov workspace for a
  * restart length `restart` need, for every inner dtype whose bit
  * (1 << hpgmx_dtype) is set in dtype_mask. */

@@ -84,6 +84,7 @@ struct hpgmx_ctx {
     hpgmx_problem_desc prob{};  // grid size (beta is unused once `stencil` is set)
     Stencil stencil{};
     bool cols16 = false;        // column format of the hierarchy (hpgmx_set_column_format)
+    Layout layout;              // data layout and tile order (hpgmx_set_layout)
     hipStream_t stream = nullptr;
     int device = 0;
     bool mg_ready = false;
@@ -228,29 +229,8 @@ struct PassScope {
 
 // ---- allocation plan ---------------------------------------------------------------------
 // Leading dimension of the Krylov basis: N rounded up to 64 elements plus a
-// skew (HPGMX_LDQ_PAD overrides the default for layout studies).
-i64 krylov_ldq(i64 N)
-{
-    i64 pad = kDefaultLdqPad;
-    const char *e = std::getenv("HPGMX_LDQ_PAD");
-    if (e && *e) {
-        const long v = std::atol(e);
-        if (v >= 0 && v <= (1 << 20)) pad = (v + 1) & ~1L;  // even: columns stay 8-byte aligned
-    }
-    return (N + 63) / 64 * 64 + pad;
-}
-
-// ELL chunk size (log2 rows per chunk, 0 = slot-major over the whole
-// matrix).  HPGMX_ELL_CHUNK_LOG2 overrides the default for layout studies.
-int ell_chunk_log2()
-{
-    const char *e = std::getenv("HPGMX_ELL_CHUNK_LOG2");
-    if (e && *e) {
-        const int v = std::atoi(e);
-        if (v >= 0 && v <= 16) return v;
-    }
-    return kDefaultEllChunkLog2;
-}
+// skew of `pad` elements.
+i64 krylov_ldq(i64 N, int pad) { return (N + 63) / 64 * 64 + pad; }
 
 
 void alloc_matrix_prec(hpgmx_ctx *c, Matrix &A, Prec p)
@@ -366,7 +346,7 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
             for (auto it = c->owned.begin(); it != c->owned.end(); ++it)
                 if (*it == K.Q) { (void)hipFree(K.Q); c->owned.erase(it); break; }
         }
-        K.ldq = krylov_ldq((i64)N0);
+        K.ldq = krylov_ldq((i64)N0, c->layout.ldq_pad);
         K.Q = c->dalloc((size_t)K.ldq * (m + 1) * vec_bytes(basis_prec(p)));
         K.m = m;
     }
@@ -380,7 +360,8 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
     if (p != P64) ensure_prec(c, P64);
 }
 
-size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, unsigned mask, bool cols16)
+size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, unsigned mask, bool cols16,
+                  const Layout &lay)
 {
     size_t tot = 0;
     auto add = [&](size_t b) { tot += round_up(b ? b : 1); };
@@ -397,7 +378,7 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
     const size_t N0 = (size_t)nx * ny * nz;
     for (int l = 0; l < mg.levels; ++l) {
         const size_t N = (size_t)nx * ny * nz;
-        const size_t E = (size_t)ell_entries((i64)N, ell_chunk_log2());
+        const size_t E = (size_t)ell_entries((i64)N, lay.clog2);
         if (cols16) {
             add(E * sizeof(short));  // 16-bit column offsets and their table
             add(sizeof(ColMap));
@@ -425,7 +406,7 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
     for (int p = 0; p < kNumPrec; ++p) {
         if (!((mask >> p) & 1u)) continue;
         const size_t kb = vec_bytes(basis_prec((Prec)p)), vb = vec_bytes((Prec)p);
-        add((size_t)krylov_ldq((i64)N0) * (m + 1) * kb);
+        add((size_t)krylov_ldq((i64)N0, lay.ldq_pad) * (m + 1) * kb);
         add((N0 + 1) * vb);
         add(N0 * kb);
         if (mg16((Prec)p)) add(N0 * vb);
@@ -848,7 +829,7 @@ void ensure_batch_prec(hpgmx_ctx *c, Batch &B, Prec p, int m)
             for (auto it = c->owned.begin(); it != c->owned.end(); ++it)
                 if (*it == Kr.Q) { (void)hipFree(Kr.Q); c->owned.erase(it); break; }
         }
-        Kr.ldq = krylov_ldq(N0 * K);
+        Kr.ldq = krylov_ldq(N0 * K, c->layout.ldq_pad);
         Kr.Q = c->dalloc((size_t)Kr.ldq * (m + 1) * vec_bytes(p));
         Kr.m = m;
     }
@@ -1225,7 +1206,8 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
     return status;
 }
 
-size_t plan_batch_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int nrhs, int m, unsigned mask)
+size_t plan_batch_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int nrhs, int m, unsigned mask,
+                        const Layout &lay)
 {
     const int K = batch_width(nrhs);
     size_t tot = 0;
@@ -1245,7 +1227,7 @@ size_t plan_batch_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, i
             add((N + 1) * K * vb);
             nx /= 2; ny /= 2; nz /= 2;
         }
-        add((size_t)krylov_ldq((i64)(N0 * K)) * (m + 1) * vb);
+        add((size_t)krylov_ldq((i64)(N0 * K), lay.ldq_pad) * (m + 1) * vb);
         add((N0 + 1) * K * vb);
         add(N0 * K * vb);
         for (int i = 0; i < 3; ++i) add((N0 + 1) * K * vb);  // staging (ABI calls, autotuning)
@@ -1398,7 +1380,7 @@ hpgmx_status hpgmx_workspace_bytes(hpgmx_handle h, const hpgmx_mg_desc *mg, int 
         check_ptr(bytes, "bytes");
         if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
         if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
-        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0x3Fu, h->cols16);
+        *bytes = plan_bytes(h->prob, *mg, restart, dtype_mask & 0x3Fu, h->cols16, h->layout);
         return HPGMX_OK;
     });
 }
@@ -1424,6 +1406,23 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format)
         if (h->mg_ready) fail(HPGMX_ESTATE, "the column format must be chosen before hpgmx_mg_setup");
         if (format != HPGMX_COLS_INT32 && format != HPGMX_COLS_OFFSET16) fail(HPGMX_EINVAL, "unknown column format");
         h->cols16 = format == HPGMX_COLS_OFFSET16;
+        return HPGMX_OK;
+    });
+}
+
+hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad)
+{
+    return guarded(h, [&]() -> hpgmx_status {
+        if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
+        if (h->mg_ready) fail(HPGMX_ESTATE, "the layout must be chosen before hpgmx_mg_setup");
+        if (tile_order > kRemapSlab) fail(HPGMX_EINVAL, "tile_order must be 0, 1 or 2 (negative: default)");
+        if (ell_chunk_log2 > 16) fail(HPGMX_EINVAL, "ell_chunk_log2 must be 0..16 (negative: default)");
+        if (ldq_pad > (1 << 20) || (ldq_pad > 0 && ldq_pad % 2))
+            fail(HPGMX_EINVAL, "ldq_pad must be even and at most 2^20 (negative: default)");
+        const Layout def;
+        h->layout.order = tile_order < 0 ? def.order : tile_order;
+        h->layout.clog2 = ell_chunk_log2 < 0 ? def.clog2 : ell_chunk_log2;
+        h->layout.ldq_pad = ldq_pad < 0 ? def.ldq_pad : ldq_pad;
         return HPGMX_OK;
     });
 }
@@ -1455,7 +1454,8 @@ hpgmx_status hpgmx_mg_setup(hpgmx_handle h, const hpgmx_mg_desc *mg)
         for (int l = 0; l < mg->levels; ++l) {
             Matrix &A = h->lv[l].A;
             A.g = make_geom(nx, ny, nz);
-            A.clog2 = ell_chunk_log2();
+            A.clog2 = h->layout.clog2;
+            A.order = h->layout.order;
             A.c16 = h->cols16;
             A.col = h->dalloc((size_t)ell_entries(A.g.N, A.clog2) * (A.c16 ? sizeof(short) : sizeof(int)));
             if (A.c16) {
@@ -1729,7 +1729,7 @@ hpgmx_status hpgmx_workspace_bytes_batched(hpgmx_handle h, const hpgmx_mg_desc *
         check_nrhs(nrhs);
         if (mg->levels < 1 || mg->levels > kMaxLevels) fail(HPGMX_EINVAL, "levels out of range");
         if (restart < 1 || restart > kMaxRestart) fail(HPGMX_EINVAL, "restart out of range");
-        *bytes = plan_batch_bytes(h->prob, *mg, nrhs, restart, dtype_mask & 0xFu);
+        *bytes = plan_batch_bytes(h->prob, *mg, nrhs, restart, dtype_mask & 0xFu, h->layout);
         return HPGMX_OK;
     });
 }

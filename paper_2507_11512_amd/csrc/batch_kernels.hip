@@ -273,7 +273,7 @@ void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y,
         with_kr(K, R, [&](auto kc, auto rc) {
             constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
             hipLaunchKernelGGL((k_bspmv<V, KK, RR>), dim3(lanes_grid(A.g.N, KK, RR)), dim3(kBlock), 0, s,
-                               A.g.N, A.clog2, xcd_remap_enabled(), v, (const int *)A.col, d, (const T *)x, (T *)y, ctrl, k);
+                               A.g.N, A.clog2, tile_remap(A), v, (const int *)A.col, d, (const T *)x, (T *)y, ctrl, k);
         });
     });
     HPGMX_LAUNCH_CHECK();
@@ -286,7 +286,7 @@ static void bgs_launch(const Matrix &A, const V *v, const V *d, int c, const voi
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
     hipLaunchKernelGGL((k_bgs<V, K, R, MASK>), dim3(lanes_grid(cnt, K, R)), dim3(kBlock), 0, s, row0, cnt,
-                       A.g.N, A.clog2, xcd_remap_enabled(), v, (const int *)A.col, d, (const T *)r, (T *)z);
+                       A.g.N, A.clog2, tile_remap(A), v, (const int *)A.col, d, (const T *)r, (T *)z);
 }
 
 #define HPGMX_BGS_CASE(C, FWD) \
@@ -334,7 +334,7 @@ void launch_brestrict(const Matrix &Af, const Geom &gc, Prec p, int K, int R, co
         with_kr(K, R, [&](auto kc, auto rcn) {
             constexpr int KK = decltype(kc)::value, RR = decltype(rcn)::value;
             hipLaunchKernelGGL((k_brestrict<V, KK, RR>), dim3(lanes_grid(gc.N, KK, RR)), dim3(kBlock), 0, s,
-                               Af.g, gc, Af.clog2, xcd_remap_enabled(), v, (const int *)Af.col, d, (const T *)r,
+                               Af.g, gc, Af.clog2, tile_remap(Af), v, (const int *)Af.col, d, (const T *)r,
                                (const T *)z, (T *)rc);
         });
     });
@@ -355,10 +355,10 @@ void launch_brestrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, int 
             const dim3 gr(lanes_grid(gc.N, KK, RR)), bl(kBlock);
             if (forward)
                 hipLaunchKernelGGL((k_brestrict_after_sweep<V, KK, RR, kFwd>), gr, bl, 0, s, Af.g, gc, Af.clog2,
-                                   xcd_remap_enabled(), v, (const int *)Af.col, (const T *)z, (T *)rc);
+                                   tile_remap(Af), v, (const int *)Af.col, (const T *)z, (T *)rc);
             else
                 hipLaunchKernelGGL((k_brestrict_after_sweep<V, KK, RR, kBwd>), gr, bl, 0, s, Af.g, gc, Af.clog2,
-                                   xcd_remap_enabled(), v, (const int *)Af.col, (const T *)z, (T *)rc);
+                                   tile_remap(Af), v, (const int *)Af.col, (const T *)z, (T *)rc);
         });
     });
     HPGMX_LAUNCH_CHECK();
@@ -385,7 +385,7 @@ void launch_bresid64(const Matrix &A, int K, int R, const double *x, const doubl
     with_kr(K, R, [&](auto kc, auto rc) {
         constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
         hipLaunchKernelGGL((k_bresid64<KK, RR>), dim3(lanes_grid(A.g.N, KK, RR)), dim3(kBlock), 0, s, A.g.N,
-                           A.clog2, xcd_remap_enabled(), A.v64, (const int *)A.col, A.d64, x, b, r);
+                           A.clog2, tile_remap(A), A.v64, (const int *)A.col, A.d64, x, b, r);
     });
     HPGMX_LAUNCH_CHECK();
     launch_norm64(A.g.N * K, K, r, partials, ctrl, kFinishResid, m, s);

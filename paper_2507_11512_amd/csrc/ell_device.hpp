@@ -166,7 +166,6 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int remap)
 // maps a tile of the XCD-contiguous order to its tile in the slab order; it
 // is a permutation of [0, T) when T is a multiple of 64 and each colour block
 // holds T/8 tiles, which the host checks (full_grid_order).
-constexpr int kRemapSlab = 2;
 __device__ __forceinline__ i64 slab_perm(i64 t, i64 T)
 {
     const i64 per = T / kXcds, sub = T / (kXcds * kXcds);
@@ -200,14 +199,14 @@ __device__ __forceinline__ RowLoop row_loop(i64 N, int remap)
     return RowLoop{t0 + j, t1, (i64)cnt, N};
 }
 
-// Remapping switch (HPGMX_XCD_REMAP=0 turns it off for layout studies).
-int xcd_remap_enabled();
+// Whether the launches of a matrix use the XCD-aware tile order.
+inline int tile_remap(const Matrix &A) { return A.order != 0 ? 1 : 0; }
 // Work order of a full-grid launch over all N rows of every colour with
-// `lanes` lanes per row, in T tiles of 256 lanes: kRemapSlab when the slab
-// order is a permutation (all grid extents even, so the colour blocks are
-// equal, and T a multiple of 64), else the XCD-contiguous order (or none,
-// with remapping off).
-int full_grid_order(const Geom &g, int lanes);
+// `lanes` lanes per row, in T tiles of 256 lanes: kRemapSlab when the matrix
+// asks for it and the slab order is a permutation (all grid extents even, so
+// the colour blocks are equal, and T a multiple of 64), else the
+// XCD-contiguous order (or none, when the matrix's order is 0).
+int full_grid_order(const Matrix &A, int lanes);
 
 __device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ i64 gtid_xcd(int remap)

@@ -45,6 +45,18 @@ constexpr int kDefaultEllChunkLog2 = 8;  // ELL chunking default (see ell_row)
 // Extra elements between Krylov basis columns, so that columns do not start
 // on the same large power-of-two boundary (DRAM channel/bank aliasing).
 constexpr int kDefaultLdqPad = 1088;
+// Tile orders of the row-per-lane launches: 0 the launch order, 1 each XCD
+// owns one contiguous range of tiles, kRemapSlab (the default) also the slab
+// order for the full-grid SpMV (see slab_perm).
+constexpr int kRemapSlab = 2;
+
+// Data layout and tile order of a handle.  The defaults are the tuned
+// ones; hpgmx_set_layout changes them for layout studies and tests.
+struct Layout {
+    int order = kRemapSlab;
+    int clog2 = kDefaultEllChunkLog2;  // ELL chunking (see ell_row)
+    int ldq_pad = kDefaultLdqPad;      // elements between Krylov basis columns
+};
 
 using bf16 = __hip_bfloat16;
 
@@ -157,6 +169,7 @@ ColMap make_colmap(const Geom &g);
 struct Matrix {
     Geom g;
     int clog2 = 0;         // ELL chunking (see ell_row)
+    int order = kRemapSlab;   // tile order of its launches (Layout::order)
     bool c16 = false;         // column format: int32 indices, or 16-bit offsets
     void *col = nullptr;      // int32 [laid out as the values], or 16-bit offset pairs (see ell_row)
     int *cmap = nullptr;      // the ColMap D[c][s] on the device (16-bit offsets)

@@ -495,7 +495,7 @@ void launch_resid64(const Matrix &A, const double *x, const double *b, double *r
     const unsigned nb = (unsigned)red_blocks(A.g.N);
     with_cols(A, [&](auto c16) {
         hipLaunchKernelGGL(k_resid64<decltype(c16)::value>, dim3(nb), dim3(kBlock), 0, s, A.g, A.clog2,
-                           xcd_remap_enabled(), A.v64, (const void *)A.col, A.cmap, A.d64, x, b, r, partials);
+                           tile_remap(A), A.v64, (const void *)A.col, A.cmap, A.d64, x, b, r, partials);
     });
     HPGMX_LAUNCH_CHECK();
     launch_finish(partials, (int)nb, 1, 1, kFinishResid, ctrl, 0, m, s);

@@ -13,24 +13,10 @@
 
 namespace hpgmx {
 
-// HPGMX_XCD_REMAP (layout studies): 0 = no remapping, 1 = XCD-contiguous
-// tiles only, 2 (default) = also the slab order where it is used.
-static int xcd_remap_mode()
+int full_grid_order(const Matrix &A, int lanes)
 {
-    static const int mode = [] {
-        const char *e = std::getenv("HPGMX_XCD_REMAP");
-        if (!(e && *e)) return 2;
-        const int v = std::atoi(e);
-        return v < 0 ? 0 : v > 2 ? 2 : v;
-    }();
-    return mode;
-}
-
-int xcd_remap_enabled() { return xcd_remap_mode() != 0 ? 1 : 0; }
-
-int full_grid_order(const Geom &g, int lanes)
-{
-    if (xcd_remap_mode() < 2) return xcd_remap_enabled();
+    if (A.order < kRemapSlab) return A.order != 0 ? 1 : 0;
+    const Geom &g = A.g;
     const i64 lanes_total = g.N * lanes;
     const bool even = g.nx % 2 == 0 && g.ny % 2 == 0 && g.nz % 2 == 0;
     const bool whole = lanes_total % ((i64)kBlock * kXcds * kXcds) == 0;
@@ -282,7 +268,7 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
         using T = typename VecT<V>::T;
         with_cols(A, [&](auto c16) {
             hipLaunchKernelGGL((k_spmv<V, S, decltype(c16)::value>), dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g,
-                               A.clog2, std::is_same<V, double>::value ? xcd_remap_enabled() : full_grid_order(A.g, 1),
+                               A.clog2, std::is_same<V, double>::value ? tile_remap(A) : full_grid_order(A, 1),
                                (const V *)v, (const void *)A.col, A.cmap, (const V *)d, (const S *)x, (T *)y, scale);
         });
     });
@@ -323,7 +309,7 @@ static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void
     if (cnt == 0) return;
     with_cols(A, [&](auto c16) {
         hipLaunchKernelGGL((k_gs<V, S, MASK, decltype(c16)::value>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0,
-                           cnt, A.g.N, A.clog2, xcd_remap_enabled(), v, (const void *)A.col,
+                           cnt, A.g.N, A.clog2, tile_remap(A), v, (const void *)A.col,
                            A.c16 ? A.cmap + c * kSlots : nullptr, d, (const S *)r, (S *)z);
     });
     HPGMX_LAUNCH_CHECK();
@@ -393,7 +379,7 @@ void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, co
         using S = decltype(sv);
         with_cols(Af, [&](auto c16) {
             hipLaunchKernelGGL((k_restrict<V, S, decltype(c16)::value>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s,
-                               Af.g, gc, Af.clog2, xcd_remap_enabled(), (const V *)v, (const void *)Af.col,
+                               Af.g, gc, Af.clog2, tile_remap(Af), (const V *)v, (const void *)Af.col,
                                Af.c16 ? Af.cmap + 4 * kSlots : nullptr, (const V *)d, (const S *)r, (const S *)z,
                                (S *)rc);
         });
@@ -443,11 +429,11 @@ void launch_restrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, bool 
             const int *cm4 = Af.c16 ? Af.cmap + 4 * kSlots : nullptr;
             if (forward)
                 hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kFwd, C>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s,
-                                   Af.g, gc, Af.clog2, xcd_remap_enabled(), (const V *)v, (const void *)Af.col, cm4,
+                                   Af.g, gc, Af.clog2, tile_remap(Af), (const V *)v, (const void *)Af.col, cm4,
                                    (const S *)z, (S *)rc);
             else
                 hipLaunchKernelGGL((k_restrict_after_sweep<V, S, kBwd, C>), dim3(grid_for(gc.N)), dim3(kBlock), 0, s,
-                                   Af.g, gc, Af.clog2, xcd_remap_enabled(), (const V *)v, (const void *)Af.col, cm4,
+                                   Af.g, gc, Af.clog2, tile_remap(Af), (const V *)v, (const void *)Af.col, cm4,
                                    (const S *)z, (S *)rc);
         });
     });

@@ -43,7 +43,8 @@ EXPORTS = ["hpgmx_setup_problem", "hpgmx_setup_problem_stencil", "hpgmx_stencil_
            "hpgmx_batch_get_tuning", "hpgmx_workspace_bytes_batched", "hpgmx_spmv_batched",
            "hpgmx_smooth_batched", "hpgmx_vcycle_batched", "hpgmx_gmres_ir_solve_batched",
            "hpgmx_presmooth_restrict", "hpgmx_presmooth_restrict_batched", "hpgmx_krylov_cycle_get",
-           "hpgmx_stencil_grad_noalloc", "hpgmx_set_column_format"]
+           "hpgmx_stencil_grad_noalloc", "hpgmx_set_column_format",
+           "hpgmx_set_layout"]
 
 
 class ProblemDesc(C.Structure):
@@ -88,6 +89,7 @@ def _load():
         "hpgmx_stencil_grad": [H, vp, vp, vp],
         "hpgmx_stencil_grad_noalloc": [H, vp, vp, vp],
         "hpgmx_set_column_format": [H, i],
+        "hpgmx_set_layout": [H, i, i, i],
         "hpgmx_workspace_bytes": [H, C.POINTER(MgDesc), i, C.c_uint, C.POINTER(C.c_size_t)],
         "hpgmx_bind_workspace": [H, vp, C.c_size_t],
         "hpgmx_mg_setup": [H, C.POINTER(MgDesc)],
@@ -213,6 +215,10 @@ def bind_workspace(h, tensor):
 
 def set_column_format(h, fmt):
     _check(h, lib.hpgmx_set_column_format(h, int(fmt)))
+
+
+def set_layout(h, tile_order=-1, ell_chunk_log2=-1, ldq_pad=-1):
+    _check(h, lib.hpgmx_set_layout(h, int(tile_order), int(ell_chunk_log2), int(ldq_pad)))
 
 
 def mg_setup(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD):
@@ -392,6 +398,9 @@ class Problem:
 
     >>> P = Problem(128, beta=0.5, levels=4, sweep='forward')
     >>> x, stats = P.solve(b, tol=1e-9, restart=30, precision='mxp')
+
+    `cols` picks the column-index format ("int32" or "offset16"); `layout`,
+    for layout studies only, is a dict of set_layout's keyword arguments.
     """
 
     _SWEEPS = {"forward": GS_FORWARD, "backward": GS_BACKWARD, "symmetric": GS_SYMMETRIC}
@@ -399,7 +408,7 @@ class Problem:
              "fp16-mg": F16_MG, "bf16-mg": BF16_MG}
 
     def __init__(self, n, beta=0.5, levels=4, sweep="forward", pre=1, post=1, coarsest=1,
-                 stream=None, workspace=None, coef=None, cols="int32"):
+                 stream=None, workspace=None, coef=None, cols="int32", layout=None):
         import torch
         self.dims = (n, n, n) if isinstance(n, int) else tuple(n)
         self.N = self.dims[0] * self.dims[1] * self.dims[2]
@@ -412,6 +421,8 @@ class Problem:
         sw = self._SWEEPS[sweep] if isinstance(sweep, str) else int(sweep)
         try:
             set_column_format(self.h, {"int32": COLS_INT32, "offset16": COLS_OFFSET16}[cols])
+            if layout is not None:
+                set_layout(self.h, **layout)
             if workspace is not None:
                 bind_workspace(self.h, workspace)
                 self.workspace = workspace

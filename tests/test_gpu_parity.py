@@ -545,13 +545,12 @@ def test_bound_workspace_matches_owned_memory(hp):
     assert torch.equal(x, x2)
 
 
-@pytest.mark.parametrize("clog2", ["0", "6", "8"])
-def test_ell_chunk_layouts(hp, clog2, monkeypatch):
+@pytest.mark.parametrize("clog2", [0, 6, 8])
+def test_ell_chunk_layouts(hp, clog2):
     """The SpMV, smoother, restriction and solve agree with the oracle for
     every ELL chunking (ragged grids leave a partial last chunk)."""
-    monkeypatch.setenv("HPGMX_ELL_CHUNK_LOG2", clog2)
     dims = (24, 20, 14)
-    P = hp.Problem(dims, beta=0.5, levels=2, sweep="forward")
+    P = hp.Problem(dims, beta=0.5, levels=2, sweep="forward", layout={"ell_chunk_log2": clog2})
     x = rnd(inputs.uniform(dims, 900), 1)
     y = dev(np.zeros(x.size), 1)
     hp.spmv(P.h, 0, 1, dev(x, 1), y)
@@ -566,6 +565,40 @@ def test_ell_chunk_layouts(hp, clog2, monkeypatch):
     res = np.linalg.norm(b - oracle.spmv(dims, host(xg))) / np.linalg.norm(b)
     P.close()
     assert st.converged and res <= 1e-9
+
+
+@pytest.mark.parametrize("dims", [(64, 64, 64), (32, 24, 16)])
+def test_layouts_bit_identical(hp, dims):
+    """Tile order, ELL chunking and basis skew move data and work, never the
+    arithmetic: every layout gives the same iterates bit for bit (64^3 takes
+    the slab order of the full-grid SpMV, the ragged grid cannot)."""
+    b = oracle.spmv(dims, inputs.ones(dims))
+    ref = None
+    for lay in [None, {"tile_order": 0}, {"tile_order": 1}, {"ell_chunk_log2": 0, "ldq_pad": 0},
+                {"tile_order": 0, "ell_chunk_log2": 5, "ldq_pad": 2}]:
+        P = hp.Problem(dims, beta=0.5, levels=3, sweep="forward", layout=lay)
+        x, st = P.solve(dev(b, 0), tol=1e-9, precision="mxp")
+        P.close()
+        got = (host(x), st.iters)
+        if ref is None:
+            ref = got
+            assert st.converged
+        else:
+            assert got[1] == ref[1] and np.array_equal(got[0], ref[0]), lay
+
+
+def test_layout_errors(hp):
+    h = hp.setup_problem(16, 16, 16, beta=0.5)
+    try:
+        for args in [(3, -1, -1), (-1, 17, -1), (-1, -1, 3), (-1, -1, (1 << 20) + 2)]:
+            with pytest.raises(hp.HpgmxError):
+                hp.set_layout(h, *args)
+        hp.set_layout(h, 1, 4, 64)
+        hp.mg_setup(h, 2, 1, 1, 1, hp.GS_FORWARD)
+        with pytest.raises(hp.HpgmxError):
+            hp.set_layout(h, -1, -1, -1)
+    finally:
+        hp.destroy(h)
 
 
 @pytest.mark.parametrize("dtype", [0, 1, 4, 5])
