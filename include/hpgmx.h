@@ -177,13 +177,20 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  * changes where data sits and in which order workgroups take row tiles,
  * never the arithmetic: results are bit-identical under every setting.
  *   tile_order     0 = tiles in launch order, 1 = each of the eight XCDs
- *                  takes one contiguous range of row tiles, 2 (default) =
- *                  as 1, plus the slab order for the full-grid SpMV.
+ *                  takes one contiguous range of row tiles, 3 = as 1, plus
+ *                  the plane order for the full-grid SpMVs (each XCD takes
+ *                  a slab of grid planes and walks it plane by plane through
+ *                  all eight colours), 2 (default) = as 1, plus the order
+ *                  measured fastest for each full-grid SpMV: the slab order
+ *                  (each XCD takes one eighth of every colour block) for the
+ *                  FP32 and 16-bit SpMV, the plane order for the batched
+ *                  SpMV, the XCD-contiguous order for the FP64 SpMV.
  *   ell_chunk_log2 rows per ELL chunk as a power of two, 0..16 (0 =
  *                  slot-major over the whole level; default 8).
  *   ldq_pad        elements added between Krylov basis columns, even,
  *                  0..2^20 (default 1088).
- * A negative argument keeps that default.  EINVAL for values out of range;
+ * A negative argument keeps that default.  Orders 2 and 3 fall back to 1 on
+ * levels with an odd extent.  EINVAL for values out of range;
  * ESTATE after hpgmx_mg_setup (must precede it, and hpgmx_workspace_bytes
  * when a workspace is bound). */
 hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad);

@@ -1415,7 +1415,7 @@ hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2
     return guarded(h, [&]() -> hpgmx_status {
         if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
         if (h->mg_ready) fail(HPGMX_ESTATE, "the layout must be chosen before hpgmx_mg_setup");
-        if (tile_order > kRemapSlab) fail(HPGMX_EINVAL, "tile_order must be 0, 1 or 2 (negative: default)");
+        if (tile_order > kRemapPlanes) fail(HPGMX_EINVAL, "tile_order must be 0..3 (negative: default)");
         if (ell_chunk_log2 > 16) fail(HPGMX_EINVAL, "ell_chunk_log2 must be 0..16 (negative: default)");
         if (ldq_pad > (1 << 20) || (ldq_pad > 0 && ldq_pad % 2))
             fail(HPGMX_EINVAL, "ldq_pad must be even and at most 2^20 (negative: default)");

@@ -29,7 +29,7 @@ namespace hpgmx {
 // With ctrl, vector j of the output is scaled by ctrl[j].colscale[k] (the
 // unnormalised-basis scale of the column x was computed from).
 template <typename V, int K, int R>
-__global__ __launch_bounds__(kBlock) void k_bspmv(i64 N, int clog2, int remap, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, int clog2, int remap, const V *__restrict__ offv,
                                                   const int *__restrict__ offc,
                                                   const V *__restrict__ diag,
                                                   const typename VecT<V>::T *__restrict__ x,
@@ -38,9 +38,11 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(i64 N, int clog2, int remap, c
 {
     using T = typename VecT<V>::T;
     constexpr int L = K / R;
+    const i64 N = gm.N;
     const i64 t = gtid_xcd(remap);
-    const i64 p = t / L;
+    i64 p = t / L;
     if (p >= N) return;
+    if (remap == kRemapPlanes) p = plane_row(p, gm);
     const int g = (int)(t % L);
     const i64 o = p * K + g * R;
     const EllRow er = ell_row(p, N, clog2);
@@ -272,8 +274,12 @@ void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y,
         using T = typename VecT<V>::T;
         with_kr(K, R, [&](auto kc, auto rc) {
             constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
+            // The default order takes the plane order here: at 192^3 x 8 it
+            // cut the fetched bytes from 1.94x to 1.30x the algorithmic ones
+            // and the time by 6 % (the slab order ran slower).
+            const int order = A.order >= kRemapSlab ? plane_order(A) : tile_remap(A);
             hipLaunchKernelGGL((k_bspmv<V, KK, RR>), dim3(lanes_grid(A.g.N, KK, RR)), dim3(kBlock), 0, s,
-                               A.g.N, A.clog2, tile_remap(A), v, (const int *)A.col, d, (const T *)x, (T *)y, ctrl, k);
+                               A.g, A.clog2, order, v, (const int *)A.col, d, (const T *)x, (T *)y, ctrl, k);
         });
     });
     HPGMX_LAUNCH_CHECK();

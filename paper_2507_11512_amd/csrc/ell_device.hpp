@@ -173,6 +173,24 @@ __device__ __forceinline__ i64 slab_perm(i64 t, i64 T)
     return (u / sub) * per + x * sub + u % sub;
 }
 
+// Plane-interleaved order of a full-grid launch (remap == kRemapPlanes).
+// Work item v of the XCD-contiguous order is the v-th row of a sequence that
+// runs over the lattice planes kk of the colour blocks and, within one kk,
+// over the eight colours: the four on grid plane 2kk first, then the four on
+// 2kk + 1.  XCD x then owns a slab of consecutive grid planes with every
+// colour in it, and the rows it has in flight gather their neighbours from
+// two or three adjacent grid planes, which stay in that XCD's L2: each
+// vector entry comes from HBM about once per launch rather than once per
+// XCD.  Needs equal colour blocks (all extents even) and N < 2^32, which
+// the host checks.
+__device__ __forceinline__ i64 plane_row(i64 v, const Geom &g)
+{
+    const unsigned P = (unsigned)g.bx[0] * (unsigned)g.by[0];
+    const unsigned q = (unsigned)v / P, local = (unsigned)v - q * P;
+    const unsigned c = (q & 7u) ^ 4u, kk = q >> 3;
+    return g.off[c] + (i64)kk * P + local;
+}
+
 // Row loop of a grid-stride launch: the N rows are cut into 256-row tiles,
 // XCD x owns tiles [T x / 8, T (x+1) / 8) and its workgroups stride through
 // them.  Without remap: the plain grid-stride loop.
@@ -202,15 +220,19 @@ __device__ __forceinline__ RowLoop row_loop(i64 N, int remap)
 // Whether the launches of a matrix use the XCD-aware tile order.
 inline int tile_remap(const Matrix &A) { return A.order != 0 ? 1 : 0; }
 // Work order of a full-grid launch over all N rows of every colour with
-// `lanes` lanes per row, in T tiles of 256 lanes: kRemapSlab when the matrix
-// asks for it and the slab order is a permutation (all grid extents even, so
-// the colour blocks are equal, and T a multiple of 64), else the
-// XCD-contiguous order (or none, when the matrix's order is 0).
+// `lanes` lanes per row, in T tiles of 256 lanes: the matrix's order when it
+// applies -- kRemapPlanes needs all grid extents even (equal colour blocks)
+// and N < 2^32, kRemapSlab needs even extents and T a multiple of 64 (then
+// slab_perm is a permutation) -- else the XCD-contiguous order (or none,
+// when the matrix's order is 0).
 int full_grid_order(const Matrix &A, int lanes);
+// kRemapPlanes where it applies (even extents, N < 2^32), else 1.
+int plane_order(const Matrix &A);
 
 __device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ i64 gtid_xcd(int remap)
 {
+    if (remap == kRemapPlanes) remap = 1;  // the row permutation is applied by the kernel (plane_row)
     i64 t = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (remap == kRemapSlab) t = slab_perm(t, gridDim.x);
     return t * blockDim.x + threadIdx.x;

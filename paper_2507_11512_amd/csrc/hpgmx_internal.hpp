@@ -46,9 +46,10 @@ constexpr int kDefaultEllChunkLog2 = 8;  // ELL chunking default (see ell_row)
 // on the same large power-of-two boundary (DRAM channel/bank aliasing).
 constexpr int kDefaultLdqPad = 1088;
 // Tile orders of the row-per-lane launches: 0 the launch order, 1 each XCD
-// owns one contiguous range of tiles, kRemapSlab (the default) also the slab
-// order for the full-grid SpMV (see slab_perm).
+// owns one contiguous range of tiles; for the full-grid SpMV also
+// kRemapSlab (see slab_perm) or kRemapPlanes (see plane_row).
 constexpr int kRemapSlab = 2;
+constexpr int kRemapPlanes = 3;
 
 // Data layout and tile order of a handle.  The defaults are the tuned
 // ones; hpgmx_set_layout changes them for layout studies and tests.
