@@ -174,8 +174,9 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
 
 /* Data layout and work order, for layout studies and tests; the defaults
  * are the tuned ones and a production solve needs no call.  The choice
- * changes where data sits and in which order workgroups take row tiles,
- * never the arithmetic: results are bit-identical under every setting.
+ * changes where data sits, in which order workgroups take row tiles and
+ * how a sweep is cut into launches, never the arithmetic: results are
+ * bit-identical under every setting.
  *   tile_order     0 = tiles in launch order, 1 = each of the eight XCDs
  *                  takes one contiguous range of row tiles, 3 = as 1, plus
  *                  the plane order for the full-grid SpMVs (each XCD takes
@@ -189,11 +190,18 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  *                  slot-major over the whole level; default 8).
  *   ldq_pad        elements added between Krylov basis columns, even,
  *                  0..2^20 (default 1088).
+ *   pair_rows      a Gauss-Seidel sweep from a zero guess relaxes two
+ *                  colours (c, c ^ 1) per launch on levels with an even x
+ *                  extent: the first two pairs of the sweep on levels with
+ *                  at most pair_rows rows per colour, the last two on
+ *                  levels with at most pair_rows / 64; 0 = never (default
+ *                  2^17).
  * A negative argument keeps that default.  Orders 2 and 3 fall back to 1 on
  * levels with an odd extent.  EINVAL for values out of range;
  * ESTATE after hpgmx_mg_setup (must precede it, and hpgmx_workspace_bytes
  * when a workspace is bound). */
-hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad);
+hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad,
+                              long long pair_rows);
 
 /* Device bytes the hierarchy of `mg` plus the Krylov workspace for a
  * restart length `restart` need, for every inner dtype whose bit

@@ -421,9 +421,22 @@ void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool for
                    int skip_first_colour)
 {
     const Matrix &A = c->lv[l].A;
+    const long long rows = A.g.off[1] - A.g.off[0];
+    const bool pairs = zero && !skip_first_colour && gs_pair_possible(A);
     for (int n = 0; n < 8; ++n) {
         const int col = forward ? n : 7 - n;
         if (n == 0 && skip_first_colour) continue;
+        // A pair costs colour col ^ 1 two extra evaluations of colour col's
+        // rows: cheap when col reads at most 6 slots (the first two pairs of
+        // a sweep), 18 or 22 slots for the other two, which pay only on
+        // levels 64 times smaller.
+        const bool cheap = __builtin_popcount(zero_guess_mask(col, forward)) <= 6;
+        if (pairs && rows <= (cheap ? c->layout.pair_rows : c->layout.pair_rows / 64)) {
+            ProfScope ps(c, HPGMX_K_GS_ZERO, l);
+            launch_gs_pair_zero(A, p, col, forward, r, z, c->stream);
+            ++n;
+            continue;
+        }
         const int mode = !zero ? kGsFull : forward ? kGsZeroForward : kGsZeroBackward;
         ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
         launch_gs_colour(A, p, col, mode, r, z, c->stream);
@@ -1410,7 +1423,8 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format)
     });
 }
 
-hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad)
+hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad,
+                              long long pair_rows)
 {
     return guarded(h, [&]() -> hpgmx_status {
         if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
@@ -1423,6 +1437,7 @@ hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2
         h->layout.order = tile_order < 0 ? def.order : tile_order;
         h->layout.clog2 = ell_chunk_log2 < 0 ? def.clog2 : ell_chunk_log2;
         h->layout.ldq_pad = ldq_pad < 0 ? def.ldq_pad : ldq_pad;
+        h->layout.pair_rows = pair_rows < 0 ? def.pair_rows : pair_rows;
         return HPGMX_OK;
     });
 }

@@ -124,6 +124,65 @@ __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const void 
 }
 
 constexpr unsigned kAllSlots = (1u << kSlots) - 1u;
+// The -x and +x neighbours (slots 12 and 13): the only couplings between
+// colours c and c ^ 1.
+constexpr unsigned kXSlots = (1u << 12) | (1u << 13);
+
+// Column of slot s of row p, decoded as ell_row_dot decodes it.
+template <bool C16>
+__device__ __forceinline__ i64 ell_slot_col(const void *__restrict__ offc, const EllRow &er, int s, i64 p,
+                                            const int *Dc, i64 N)
+{
+    if constexpr (C16) {
+        const unsigned w = __builtin_nontemporal_load(static_cast<const unsigned *>(offc) + er.pbase +
+                                                      (i64)(s >> 1) * er.pstride);
+        return ell_col(pair_half(w, s), p, Dc[s], N);
+    } else {
+        return ld_stream(static_cast<const int *>(offc) + er.base + (i64)s * er.stride);
+    }
+}
+
+// As ell_row_dot, with the x-neighbour slots 12 and 13 (both in MASK) taking
+// the values x12 and x13 instead of gathered ones; same operations in the
+// same order.
+template <typename T, typename V, unsigned MASK, bool C16, typename X>
+__device__ __forceinline__ T ell_row_dot_x(const V *__restrict__ offv, const void *__restrict__ offc,
+                                           const X *x, const EllRow &er, i64 p, const int *Dc, i64 N,
+                                           X x12, X x13)
+{
+    static_assert((MASK & kXSlots) == kXSlots, "both x-neighbour slots must be in the mask");
+    constexpr unsigned G = MASK & ~kXSlots;  // the gathered slots
+    V a[kSlots];
+    int ci[kSlots];
+    unsigned w[kPairs];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) {
+            const i64 e = er.base + (i64)s * er.stride;
+            a[s] = ld_stream(offv + e);
+            if constexpr (!C16)
+                if (G & (1u << s)) ci[s] = ld_stream(static_cast<const int *>(offc) + e);
+        }
+    }
+    if constexpr (C16) load_pairs<G>(static_cast<const unsigned *>(offc), er, w);
+    sched_fence();
+    X xv[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (G & (1u << s)) {
+            if constexpr (C16) xv[s] = x[ell_col(pair_half(w[s >> 1], s), p, Dc[s], N)];
+            else xv[s] = x[ci[s]];
+        }
+    }
+    xv[12] = x12;
+    xv[13] = x13;
+    sched_fence();
+    T acc = (T)0;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s)
+        if (MASK & (1u << s)) acc += to_t<T>(a[s]) * to_t<T>(xv[s]);
+    return acc;
+}
 
 // Calls f(std::true_type) for a matrix with 16-bit column offsets, else
 // f(std::false_type) (the kernels' C16 parameter).

@@ -50,6 +50,7 @@ constexpr int kDefaultLdqPad = 1088;
 // kRemapSlab (see slab_perm) or kRemapPlanes (see plane_row).
 constexpr int kRemapSlab = 2;
 constexpr int kRemapPlanes = 3;
+constexpr long long kDefaultPairRows = 1 << 17;
 
 // Data layout and tile order of a handle.  The defaults are the tuned
 // ones; hpgmx_set_layout changes them for layout studies and tests.
@@ -57,6 +58,9 @@ struct Layout {
     int order = kRemapSlab;
     int clog2 = kDefaultEllChunkLog2;  // ELL chunking (see ell_row)
     int ldq_pad = kDefaultLdqPad;      // elements between Krylov basis columns
+    // Sweeps from a zero guess relax two colours per launch on levels with
+    // at most this many rows per colour (launch_gs_pair_zero).
+    long long pair_rows = kDefaultPairRows;
 };
 
 using bf16 = __hip_bfloat16;
@@ -270,6 +274,12 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 // One colour of a Gauss-Seidel sweep: rows of colour c, slots per `mode`.
 void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
                       hipStream_t s);
+// Colours a and a ^ 1 of a sweep from a zero guess in one launch (a even
+// for a forward sweep, odd for a backward one); same result bit for bit.
+// Needs gs_pair_possible(A) (equal blocks: an even x extent).
+void launch_gs_pair_zero(const Matrix &A, Prec p, int a, bool forward, const void *r, void *z,
+                         hipStream_t s);
+bool gs_pair_possible(const Matrix &A);
 void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
                      void *rc, hipStream_t s);
 // The same result when z is the outcome of a single Gauss-Seidel sweep from

@@ -366,6 +366,101 @@ void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, v
     });
 }
 
+// ---- Gauss-Seidel from a zero guess, two colours per launch ----------------------------------
+// Colours a and b = a ^ 1, consecutive in a forward (a even) or backward
+// (a odd) sweep, couple only through the x-neighbours (slots 12 and 13), and
+// in a sweep from a zero guess a row reads only colours relaxed before it.
+// One launch relaxes both: a lane of colour a does what k_gs does; a lane of
+// colour b first evaluates its two colour-a neighbours with colour a's own
+// expression (same loads, same operations, hence the same bits), then its
+// own row with those two values in place of the gathered ones.  Nothing the
+// launch writes is read by it, so the result equals the two single-colour
+// launches bit for bit.  The price is two extra row evaluations per colour-b
+// row, worth paying where a launch is latency bound (the small levels).
+// Row tiles alternate between the colours, so each XCD gets the same slab
+// of both blocks; the blocks must have equal sizes (even x extent).
+template <typename V, typename S, unsigned MA, unsigned MB, bool C16>
+__global__ __launch_bounds__(kBlock) void k_gs_pair_zero(i64 rowa, i64 rowb, i64 cnt, i64 N, int clog2,
+                                                         int remap, const V *__restrict__ offv,
+                                                         const void *__restrict__ offc,
+                                                         const int *__restrict__ cmapa,
+                                                         const int *__restrict__ cmapb,
+                                                         const V *__restrict__ diag,
+                                                         const S *__restrict__ r, S *z)
+{
+    static_assert((MA & kXSlots) == 0 && (MB & kXSlots) == kXSlots, "colours a, b = a ^ 1 in sweep order");
+    using T = typename VecT<V>::T;
+    const i64 t = gtid_xcd(remap);
+    const i64 tile = t / kBlock;
+    const i64 u = (tile >> 1) * kBlock + t % kBlock;
+    if (u >= cnt) return;
+    if ((tile & 1) == 0) {
+        const i64 p = rowa + u;
+        const EllRow er = ell_row(p, N, clog2);
+        const T rp = to_t<T>(r[p]);
+        const T dg = to_t<T>(ld_stream(diag + p));
+        z[p] = from_t<S>((rp - ell_row_dot<T, V, MA, C16>(offv, offc, z, er, p, cmapa, N)) / dg);
+        return;
+    }
+    const i64 p = rowb + u;
+    const EllRow er = ell_row(p, N, clog2);
+    S xn[2];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const i64 q = ell_slot_col<C16>(offc, er, 12 + m, p, cmapb, N);
+        if (q == N) {  // padded slot: the zero entry, as the gather would read it
+            xn[m] = z[N];
+            continue;
+        }
+        const EllRow eq = ell_row(q, N, clog2);
+        const T rq = to_t<T>(r[q]);
+        const T dq = to_t<T>(ld_stream(diag + q));
+        xn[m] = from_t<S>((rq - ell_row_dot<T, V, MA, C16>(offv, offc, z, eq, q, cmapa, N)) / dq);
+    }
+    const T rp = to_t<T>(r[p]);
+    const T dg = to_t<T>(ld_stream(diag + p));
+    z[p] = from_t<S>((rp - ell_row_dot_x<T, V, MB, C16>(offv, offc, z, er, p, cmapb, N, xn[0], xn[1])) / dg);
+}
+
+template <typename V, typename S, int A_, bool FWD>
+static void gs_pair_launch(const Matrix &A, const V *v, const V *d, const void *r, void *z, hipStream_t s)
+{
+    constexpr int B_ = A_ ^ 1;
+    const i64 rowa = A.g.off[A_], rowb = A.g.off[B_], cnt = A.g.off[A_ + 1] - rowa;
+    if (cnt == 0) return;
+    with_cols(A, [&](auto c16) {
+        hipLaunchKernelGGL((k_gs_pair_zero<V, S, zero_guess_mask(A_, FWD), zero_guess_mask(B_, FWD),
+                                           decltype(c16)::value>),
+                           dim3(2 * grid_for(cnt)), dim3(kBlock), 0, s, rowa, rowb, cnt, A.g.N, A.clog2,
+                           tile_remap(A), v, (const void *)A.col, A.c16 ? A.cmap + A_ * kSlots : nullptr,
+                           A.c16 ? A.cmap + B_ * kSlots : nullptr, d, (const S *)r, (S *)z);
+    });
+    HPGMX_LAUNCH_CHECK();
+}
+
+bool gs_pair_possible(const Matrix &A) { return A.g.nx % 2 == 0; }
+
+void launch_gs_pair_zero(const Matrix &A, Prec p, int a, bool forward, const void *r, void *z, hipStream_t s)
+{
+    if (!gs_pair_possible(A) || (forward ? (a & 1) : !(a & 1)))
+        throw std::runtime_error("launch_gs_pair_zero: needs an even x extent and a first colour in sweep order");
+    with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using S = decltype(sv);
+        switch (a) {
+        case 0: gs_pair_launch<V, S, 0, true>(A, v, d, r, z, s); break;
+        case 2: gs_pair_launch<V, S, 2, true>(A, v, d, r, z, s); break;
+        case 4: gs_pair_launch<V, S, 4, true>(A, v, d, r, z, s); break;
+        case 6: gs_pair_launch<V, S, 6, true>(A, v, d, r, z, s); break;
+        case 1: gs_pair_launch<V, S, 1, false>(A, v, d, r, z, s); break;
+        case 3: gs_pair_launch<V, S, 3, false>(A, v, d, r, z, s); break;
+        case 5: gs_pair_launch<V, S, 5, false>(A, v, d, r, z, s); break;
+        case 7: gs_pair_launch<V, S, 7, false>(A, v, d, r, z, s); break;
+        default: break;
+        }
+    });
+}
+
 // ---- fused residual-restriction (eq. (6)) ------------------------------------------------------
 // The colour-4 block of the fine level holds the injection points in the
 // coarse level's natural order: row q of that block is coarse point

@@ -297,6 +297,25 @@ def test_solve_batched_tiles_do_not_change_results(hp):
     force_tiles(hp, P, nrhs, 1, 0)
 
 
+@pytest.mark.parametrize("dims", [(32, 32, 32), (24, 20, 16)])
+def test_solve_batched_tile_orders_bit_identical(hp, dims):
+    """Every tile order of the batched launches (the plane order of the
+    full-grid SpMV included) gives the same iterates bit for bit."""
+    import torch
+    nrhs = 8
+    _, B = _batch_rhs(dims, nrhs)
+    ref = None
+    for order in (-1, 0, 1, 3):
+        P = hp.Problem(dims, beta=0.5, levels=3, sweep="forward", layout={"tile_order": order})
+        X, stats = P.solve_batched(dev(B, 0), precision="mxp")
+        P.close()
+        assert all(s.converged for s in stats)
+        if ref is None:
+            ref = (X, [s.iters for s in stats])
+        else:
+            assert [s.iters for s in stats] == ref[1] and torch.equal(X, ref[0]), order
+
+
 @pytest.mark.parametrize("dtype", [0, 1])
 def test_autotune_table(hp, dtype):
     dims = (32, 32, 32)

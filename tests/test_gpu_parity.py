@@ -574,7 +574,8 @@ def test_layouts_bit_identical(hp, dims):
     the slab order of the full-grid SpMV, the ragged grid cannot)."""
     b = oracle.spmv(dims, inputs.ones(dims))
     ref = None
-    for lay in [None, {"tile_order": 0}, {"tile_order": 1}, {"ell_chunk_log2": 0, "ldq_pad": 0},
+    for lay in [None, {"tile_order": 0}, {"tile_order": 1}, {"tile_order": 3}, {"pair_rows": 0},
+                {"pair_rows": 1 << 40}, {"ell_chunk_log2": 0, "ldq_pad": 0},
                 {"tile_order": 0, "ell_chunk_log2": 5, "ldq_pad": 2}]:
         P = hp.Problem(dims, beta=0.5, levels=3, sweep="forward", layout=lay)
         x, st = P.solve(dev(b, 0), tol=1e-9, precision="mxp")
@@ -587,16 +588,58 @@ def test_layouts_bit_identical(hp, dims):
             assert got[1] == ref[1] and np.array_equal(got[0], ref[0]), lay
 
 
+@pytest.mark.parametrize("cols", ["int32", "offset16"])
+@pytest.mark.parametrize("dtype", [0, 1, 2, 3, 4, 5])
+def test_paired_zero_sweep_bit_identical(hp, dtype, cols):
+    """A sweep from a zero guess that relaxes two colours per launch gives
+    the single-colour launches' result bit for bit, forward and backward,
+    on every level (16^3 down to 4^3), in every storage precision."""
+    import torch
+    dims = (16, 16, 16)
+    Ps = [hp.Problem(dims, beta=0.5, levels=3, sweep="forward", cols=cols, layout={"pair_rows": pr})
+          for pr in (0, 1 << 40)]
+    try:
+        for lvl in range(3):
+            d = tuple(v >> lvl for v in dims)
+            r = rnd(inputs.uniform(d, 960 + lvl), dtype)
+            for sweep in (0, 1):
+                zs = []
+                for P in Ps:
+                    z = dev(np.zeros(r.size), dtype)
+                    hp.smooth(P.h, lvl, dtype, sweep, dev(r, dtype), z, zero_guess=True)
+                    zs.append(z)
+                assert torch.equal(zs[0], zs[1]), (lvl, sweep)
+                if lvl == 0 and dtype in (0, 1):
+                    ref = oracle.gs(d, r, np.zeros(r.size), sweep)
+                    assert np.max(np.abs(host(zs[1]) - ref)) <= _gs_tol(d, r, np.zeros(r.size), ref, dtype, 8)
+    finally:
+        for P in Ps:
+            P.close()
+
+
+def test_paired_zero_sweep_solves_identical(hp):
+    """Whole solves with and without the paired launches: same iterates."""
+    dims = (32, 32, 32)
+    b = oracle.spmv(dims, inputs.ones(dims))
+    out = []
+    for pr in (0, 1 << 40):
+        P = hp.Problem(dims, beta=0.5, levels=4, sweep="symmetric", layout={"pair_rows": pr})
+        x, st = P.solve(dev(b, 0), tol=1e-9, precision="mxp")
+        P.close()
+        out.append((host(x), st.iters))
+    assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
+
+
 def test_layout_errors(hp):
     h = hp.setup_problem(16, 16, 16, beta=0.5)
     try:
-        for args in [(3, -1, -1), (-1, 17, -1), (-1, -1, 3), (-1, -1, (1 << 20) + 2)]:
+        for args in [(4, -1, -1, -1), (-1, 17, -1, -1), (-1, -1, 3, -1), (-1, -1, (1 << 20) + 2, -1)]:
             with pytest.raises(hp.HpgmxError):
                 hp.set_layout(h, *args)
-        hp.set_layout(h, 1, 4, 64)
+        hp.set_layout(h, 1, 4, 64, 100)
         hp.mg_setup(h, 2, 1, 1, 1, hp.GS_FORWARD)
         with pytest.raises(hp.HpgmxError):
-            hp.set_layout(h, -1, -1, -1)
+            hp.set_layout(h, -1, -1, -1, -1)
     finally:
         hp.destroy(h)
 
