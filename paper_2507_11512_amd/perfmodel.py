@@ -142,9 +142,10 @@ def mgb(dtype):
 
 def gs_colour_bytes(rows, active_slots, dtype, idx=IDX):
     """One colour launch: matrix slice for `active_slots` slots + diagonal,
-    r read, z written, neighbour z counted once per row."""
+    r read, z written, neighbour z counted once per row (none when no slot
+    is active: the first colour of a sweep from a zero guess)."""
     v, w = vb(dtype), mgb(dtype)
-    return rows * (active_slots * (v + idx) + v + 3 * w)
+    return rows * (active_slots * (v + idx) + v + (3 if active_slots else 2) * w)
 
 
 def spmv_bytes(rows, dtype, idx=IDX):
@@ -190,7 +191,7 @@ def resid64_bytes(rows, idx=IDX):
 # with K.  Per right-hand side and row the matrix share is (26 (v + IDX) + v) / K.
 def bgs_colour_bytes(rows, active_slots, dtype, K):
     v, w = vb(dtype), wb(dtype)
-    return rows * (active_slots * (v + IDX) + v + 3 * K * w)
+    return rows * (active_slots * (v + IDX) + v + (3 if active_slots else 2) * K * w)
 
 
 def bspmv_bytes(rows, dtype, K):

@@ -63,3 +63,6 @@ def test_single_vector_row_bytes():
     assert pm.spmv_bytes(1, 1, idx=2) == 168 and pm.gs_colour_bytes(1, 26, 1, idx=2) == 172
     # FP64: 26 (8 + 4) + 8 + 2 * 8 and 26 (8 + 4) + 8 + 3 * 8
     assert pm.spmv_bytes(1, 0) == 336 and pm.gs_colour_bytes(1, 26, 0) == 344
+    # the first colour of a sweep from zero reads no neighbour: diagonal, r, z
+    assert pm.gs_colour_bytes(1, 0, 1) == 12 and pm.gs_colour_bytes(1, 2, 1) == 2 * 8 + 16
+    assert pm.bgs_colour_bytes(1, 0, 1, 8) == 4 + 2 * 8 * 4
