@@ -196,12 +196,17 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  *                  at most pair_rows rows per colour, the last two on
  *                  levels with at most pair_rows / 64; 0 = never (default
  *                  2^17).
+ *   spmv_in_sweep  1 (default): the last colour launch of the V-cycle (the
+ *                  last colour of the level-0 post-sweep, whose neighbours
+ *                  are all final) also writes the rows of its colour of
+ *                  w = A z, and the solver's SpMV covers the other seven
+ *                  colours; 0: one SpMV over all rows.
  * A negative argument keeps that default.  Orders 2 and 3 fall back to 1 on
  * levels with an odd extent.  EINVAL for values out of range;
  * ESTATE after hpgmx_mg_setup (must precede it, and hpgmx_workspace_bytes
  * when a workspace is bound). */
 hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad,
-                              long long pair_rows);
+                              long long pair_rows, int spmv_in_sweep);
 
 /* Device bytes the hierarchy of `mg` plus the Krylov workspace for a
  * restart length `restart` need, for every inner dtype whose bit

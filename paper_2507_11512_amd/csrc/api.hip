@@ -85,6 +85,7 @@ struct hpgmx_ctx {
     Stencil stencil{};
     bool cols16 = false;        // column format of the hierarchy (hpgmx_set_column_format)
     Layout layout;              // data layout and tile order (hpgmx_set_layout)
+    bool fuse_spmv = true;      // last colour launch of the V-cycle writes its SpMV rows
     hipStream_t stream = nullptr;
     int device = 0;
     bool mg_ready = false;
@@ -417,8 +418,10 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
 }
 
 // ---- smoothing and the V-cycle ---------------------------------------------------------------------
+// With out.w the sweep's last colour launch also writes the SpMV rows of
+// its colour (see SpmvOut).
 void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool forward, bool zero,
-                   int skip_first_colour)
+                   int skip_first_colour, SpmvOut out = {})
 {
     const Matrix &A = c->lv[l].A;
     const long long rows = A.g.off[1] - A.g.off[0];
@@ -439,14 +442,14 @@ void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool for
         }
         const int mode = !zero ? kGsFull : forward ? kGsZeroForward : kGsZeroBackward;
         ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
-        launch_gs_colour(A, p, col, mode, r, z, c->stream);
+        launch_gs_colour(A, p, col, mode, r, z, c->stream, n == 7 ? out : SpmvOut{});
     }
 }
 
 // `nsweeps` sweeps of kind `kind` on level l; the first starts from z = 0
 // when `zero` is set.
 void smooth_level(hpgmx_ctx *c, int l, Prec p, int kind, const void *r, void *z, bool zero,
-                  int nsweeps)
+                  int nsweeps, SpmvOut out = {})
 {
     if (nsweeps <= 0) {
         if (zero)
@@ -456,17 +459,28 @@ void smooth_level(hpgmx_ctx *c, int l, Prec p, int kind, const void *r, void *z,
     }
     for (int s = 0; s < nsweeps; ++s) {
         const bool zg = zero && s == 0;
+        const SpmvOut o = s == nsweeps - 1 ? out : SpmvOut{};
         if (kind == HPGMX_GS_FORWARD) {
-            sweep_colours(c, l, p, r, z, true, zg, 0);
+            sweep_colours(c, l, p, r, z, true, zg, 0, o);
         } else if (kind == HPGMX_GS_BACKWARD) {
-            sweep_colours(c, l, p, r, z, false, zg, 0);
+            sweep_colours(c, l, p, r, z, false, zg, 0, o);
         } else {
             sweep_colours(c, l, p, r, z, true, zg, 0);
             // The backward half begins by relaxing colour 7 again with
             // unchanged neighbours, which reproduces its value: skip it.
-            sweep_colours(c, l, p, r, z, false, false, 1);
+            sweep_colours(c, l, p, r, z, false, false, 1, o);
         }
     }
+}
+
+// The colour whose SpMV rows the V-cycle's last colour launch writes (the
+// last colour of the level-0 post-sweep: 7 forward, 0 backward and
+// symmetric), or -1 when the V-cycle does not end with a full sweep on level
+// 0 (one level, or no post-sweep).
+int fused_spmv_colour(const hpgmx_ctx *c)
+{
+    if (c->mg.levels < 2 || c->mg.post_sweeps < 1) return -1;
+    return c->mg.sweep == HPGMX_GS_FORWARD ? 7 : 0;
 }
 
 // A pre-smoother of one forward or backward sweep from z = 0 lets the fused
@@ -490,7 +504,9 @@ void presmooth_restrict(hpgmx_ctx *c, int l, Prec p, int kind, int nsweeps, cons
 }
 
 // z = M^{-1} r on level l (z is overwritten; the cycle starts from zero).
-void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z)
+// With out.w (level 0 only, see fused_spmv_colour) the last colour launch
+// also writes its rows of w = A z.
+void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, SpmvOut out = {})
 {
     const hpgmx_mg_desc &mg = c->mg;
     const int vt = vt_of(p);
@@ -505,7 +521,7 @@ void vcycle(hpgmx_ctx *c, int l, Prec p, const void *r, void *z)
         ProfScope ps(c, HPGMX_K_PROLONG, l);
         launch_prolong(c->lv[l].A.g, C.A.g, p, C.z[vt], z, c->stream);
     }
-    smooth_level(c, l, p, mg.sweep, r, z, false, mg.post_sweeps);
+    smooth_level(c, l, p, mg.sweep, r, z, false, mg.post_sweeps, out);
 }
 
 // ---- GMRES-IR (Alg. 3) ----------------------------------------------------------------------------------
@@ -692,18 +708,22 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             // then the copy of its scalars (see enqueue_scal)
             auto run_step = [&](int k) {
                 auto step = [&]() {
+                    // the rows of colour fc of w = A z come from the V-cycle's
+                    // last colour launch, the others from the SpMV
+                    const int fc = c->fuse_spmv ? fused_spmv_colour(c) : -1;
+                    const SpmvOut out = fc >= 0 ? SpmvOut{col(k + 1), spmv_scale(p, c->ctrl, k)} : SpmvOut{};
                     if (mg) {
                         {
                             ProfScope ps(c, HPGMX_K_CAST, 0);
                             launch_cast_mg(N, p, (const float *)col(k), c->ctrl, false, k, K.r0, c->stream);
                         }
-                        vcycle(c, 0, p, K.r0, K.z);
+                        vcycle(c, 0, p, K.r0, K.z, out);
                     } else {
-                        vcycle(c, 0, p, col(k), K.z);
+                        vcycle(c, 0, p, col(k), K.z, out);
                     }
                     {
                         ProfScope ps(c, HPGMX_K_SPMV, 0);
-                        launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k);
+                        launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k, fc);
                     }
                     {
                         PassScope ps(c, HPGMX_K_DOT, 0);
@@ -1424,7 +1444,7 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format)
 }
 
 hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2, int ldq_pad,
-                              long long pair_rows)
+                              long long pair_rows, int spmv_in_sweep)
 {
     return guarded(h, [&]() -> hpgmx_status {
         if (h->poisoned) fail(HPGMX_ESTATE, "handle poisoned: " + h->err);
@@ -1438,6 +1458,8 @@ hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2
         h->layout.clog2 = ell_chunk_log2 < 0 ? def.clog2 : ell_chunk_log2;
         h->layout.ldq_pad = ldq_pad < 0 ? def.ldq_pad : ldq_pad;
         h->layout.pair_rows = pair_rows < 0 ? def.pair_rows : pair_rows;
+        if (spmv_in_sweep > 1) fail(HPGMX_EINVAL, "spmv_in_sweep must be 0 or 1 (negative: default)");
+        h->fuse_spmv = spmv_in_sweep != 0;
         return HPGMX_OK;
     });
 }

@@ -124,6 +124,18 @@ __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const void 
 }
 
 constexpr unsigned kAllSlots = (1u << kSlots) - 1u;
+
+// One SpMV row from its parts: (a_pp x_p + acc) * scale, acc the slot sum of
+// ell_row_dot.  Contraction is off so that the SpMV kernel and the last
+// Gauss-Seidel colour launch, which computes the rows of its colour (see
+// k_gs), round alike.
+template <typename T>
+__device__ __forceinline__ T spmv_row_value(T d, T x, T acc, const double *scale)
+{
+#pragma clang fp contract(off)
+    const T v = d * x + acc;
+    return scale ? v * (T)*scale : v;
+}
 // The -x and +x neighbours (slots 12 and 13): the only couplings between
 // colours c and c ^ 1.
 constexpr unsigned kXSlots = (1u << 12) | (1u << 13);
@@ -222,13 +234,13 @@ __device__ __forceinline__ unsigned xcd_tile(unsigned b, unsigned nb, int remap)
 // and 16-bit SpMV at 320^3 runs 6030 -> 6260 GB/s, while the FP64 SpMV, the
 // batched SpMV and the FP64 residuals ran 1-4 % slower and keep the
 // XCD-contiguous order; the per-colour kernels are unaffected.  slab_perm
-// maps a tile of the XCD-contiguous order to its tile in the slab order; it
-// is a permutation of [0, T) when T is a multiple of 64 and each colour block
-// holds T/8 tiles, which the host checks (full_grid_order).
-__device__ __forceinline__ i64 slab_perm(i64 t, i64 T)
+// maps a tile of the XCD-contiguous order to its tile in the slab order; over
+// nb equal colour blocks of T/nb tiles each it is a permutation of [0, T)
+// when T/nb is a multiple of 8, which the host checks (full_grid_order).
+__device__ __forceinline__ i64 slab_perm(i64 t, i64 T, int nb = kXcds)
 {
-    const i64 per = T / kXcds, sub = T / (kXcds * kXcds);
-    const i64 x = t / per, u = t % per;
+    const i64 per = T / nb, sub = per / kXcds, span = T / kXcds;  // span = nb * sub
+    const i64 x = t / span, u = t % span;
     return (u / sub) * per + x * sub + u % sub;
 }
 
@@ -289,11 +301,11 @@ int full_grid_order(const Matrix &A, int lanes);
 int plane_order(const Matrix &A);
 
 __device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
-__device__ __forceinline__ i64 gtid_xcd(int remap)
+__device__ __forceinline__ i64 gtid_xcd(int remap, int nb = kXcds)
 {
     if (remap == kRemapPlanes) remap = 1;  // the row permutation is applied by the kernel (plane_row)
     i64 t = xcd_tile(blockIdx.x, gridDim.x, remap);
-    if (remap == kRemapSlab) t = slab_perm(t, gridDim.x);
+    if (remap == kRemapSlab) t = slab_perm(t, gridDim.x, nb);
     return t * blockDim.x + threadIdx.x;
 }
 

@@ -269,11 +269,24 @@ void launch_int2nat(const Geom &g, Prec src, const void *in, Prec dst, void *nat
 // k, fed with the unnormalised basis column k), or for the 16-bit hierarchy
 // y = (A x) * ctrl->mg_post.  x in the multigrid vector type of p, y in the
 // Krylov type (FP32 for the 16-bit hierarchy).
+// With skip = 0 or 7 the rows of that colour are left out (they come from the
+// last colour launch of the V-cycle, see SpmvOut).
 void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
-                 const Ctrl *ctrl = nullptr, int k = 0);
+                 const Ctrl *ctrl = nullptr, int k = 0, int skip = -1);
+// The scale launch_spmv applies to its output (null without ctrl).
+const double *spmv_scale(Prec p, const Ctrl *ctrl, int k);
+// SpMV rows written by a Gauss-Seidel colour launch: y (Krylov type) and the
+// scale of launch_spmv; w = nullptr for none.
+struct SpmvOut {
+    void *w = nullptr;
+    const double *scale = nullptr;
+};
 // One colour of a Gauss-Seidel sweep: rows of colour c, slots per `mode`.
+// With out.w (full mode only) the launch also writes (A z)_p for the rows of
+// its colour, valid when every neighbour of the colour is final (the last
+// colour launch of a V-cycle).
 void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
-                      hipStream_t s);
+                      hipStream_t s, SpmvOut out = {});
 // Colours a and a ^ 1 of a sweep from a zero guess in one launch (a even
 // for a forward sweep, odd for a backward one); same result bit for bit.
 // Needs gs_pair_possible(A) (equal blocks: an even x extent).

@@ -247,7 +247,8 @@ template <typename F> static void with_matrix(const Matrix &A, Prec p, F &&f)
 // (the unnormalised-basis scale of the column x was computed from).  x is a
 // multigrid vector (type S), y a Krylov vector (type T).
 template <typename V, typename S, bool C16>
-__global__ __launch_bounds__(kBlock) void k_spmv(Geom g, int clog2, int remap, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_spmv(Geom g, i64 row0, i64 cnt, int nb, int clog2, int remap,
+                                                 const V *__restrict__ offv,
                                                  const void *__restrict__ offc, const int *__restrict__ cmap,
                                                  const V *__restrict__ diag,
                                                  const S *__restrict__ x,
@@ -258,14 +259,13 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, int clog2, int remap, c
     __shared__ int cm[C16 ? kColMapSize : 1];
     if constexpr (C16) stage_colmap(cm, cmap);
     const i64 N = g.N;
-    i64 p = gtid_xcd(remap);
-    if (p >= N) return;
-    if (remap == kRemapPlanes) p = plane_row(p, g);
+    i64 p = gtid_xcd(remap, nb);
+    if (p >= cnt) return;
+    p = remap == kRemapPlanes ? plane_row(p, g) : row0 + p;
     const EllRow er = ell_row(p, N, clog2);
-    const T dx = to_t<T>(ld_stream(diag + p)) * to_t<T>(x[p]);
+    const T d = to_t<T>(ld_stream(diag + p)), xp = to_t<T>(x[p]);
     const int *Dc = C16 ? cm + row_colour(g, p) * kSlots : nullptr;
-    const T v = dx + ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N);
-    y[p] = scale ? v * (T)*scale : v;
+    y[p] = spmv_row_value<T>(d, xp, ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N), scale);
 }
 
 // Order of the single-vector SpMV.  With the default (kRemapSlab) the FP32
@@ -273,22 +273,40 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, int clog2, int remap, c
 // order.  The plane order brings the fetched bytes of the 320^3 SpMV down to
 // the algorithmic ones (FP32: 1.13x -> 1.00x), but it ran 5 % (FP32) and 1 %
 // (FP64) slower: the redundant fetches of the other orders are served by
-// the last-level cache, not HBM.
-static int spmv_order(const Matrix &A, bool fp64)
+// the last-level cache, not HBM.  Over nb < 8 colour blocks (one colour's
+// rows come from the last Gauss-Seidel launch) the plane order gives way to
+// the XCD-contiguous one.
+static int spmv_order(const Matrix &A, bool fp64, int nb)
 {
-    return fp64 && A.order == kRemapSlab ? tile_remap(A) : full_grid_order(A, 1);
+    if (fp64 && A.order == kRemapSlab) return tile_remap(A);
+    const int o = full_grid_order(A, 1);
+    return nb < 8 && o == kRemapPlanes ? 1 : o;
 }
 
-void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s, const Ctrl *ctrl, int k)
+const double *spmv_scale(Prec p, const Ctrl *ctrl, int k)
 {
-    const double *scale = !ctrl ? nullptr : mg16(p) ? &ctrl->mg_post : ctrl->colscale + k;
+    return !ctrl ? nullptr : mg16(p) ? &ctrl->mg_post : ctrl->colscale + k;
+}
+
+void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s, const Ctrl *ctrl, int k,
+                 int skip)
+{
+    const double *scale = spmv_scale(p, ctrl, k);
+    // rows of every colour but `skip`: a contiguous range when skip is the
+    // first or the last colour
+    i64 row0 = 0, cnt = A.g.N;
+    int nb = 8;
+    if (skip == 0) { row0 = A.g.off[1]; cnt = A.g.N - row0; nb = 7; }
+    else if (skip == 7) { cnt = A.g.off[7]; nb = 7; }
+    else if (skip >= 0) throw std::runtime_error("launch_spmv: only the first or the last colour can be left out");
+    if (cnt == 0) return;
     with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
         using S = decltype(sv);
         using T = typename VecT<V>::T;
         with_cols(A, [&](auto c16) {
-            hipLaunchKernelGGL((k_spmv<V, S, decltype(c16)::value>), dim3(grid_for(A.g.N)), dim3(kBlock), 0, s, A.g,
-                               A.clog2, spmv_order(A, std::is_same<V, double>::value),
+            hipLaunchKernelGGL((k_spmv<V, S, decltype(c16)::value>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, A.g,
+                               row0, cnt, nb, A.clog2, spmv_order(A, std::is_same<V, double>::value, nb),
                                (const V *)v, (const void *)A.col, A.cmap, (const V *)d, (const S *)x, (T *)y, scale);
         });
     });
@@ -305,12 +323,18 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 // that couple to colours relaxed earlier in the sweep (the others still hold
 // zero, and skipping them gives the same result bit for bit).  r and z are
 // stored in S and the row is evaluated in T.
-template <typename V, typename S, unsigned MASK, bool C16>
+//
+// With WOUT (the last colour launch of a V-cycle, all slots): every
+// neighbour of the colour is final once the colour is relaxed, so the
+// launch also writes the SpMV rows of its colour, w_p = (A z)_p, from the
+// slot sum it already holds (spmv_row_value; same bits as k_spmv).
+template <typename V, typename S, unsigned MASK, bool C16, bool WOUT = false>
 __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
                                                const V *__restrict__ offv,
                                                const void *__restrict__ offc, const int *__restrict__ cmapc,
                                                const V *__restrict__ diag,
-                                               const S *__restrict__ r, S *z)
+                                               const S *__restrict__ r, S *z,
+                                               typename VecT<V>::T *__restrict__ w, const double *scale)
 {
     using T = typename VecT<V>::T;
     const i64 t = gtid_xcd(remap);
@@ -319,18 +343,23 @@ __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clo
     const EllRow er = ell_row(p, N, clog2);
     const T rp = to_t<T>(r[p]);
     const T dg = to_t<T>(ld_stream(diag + p));
-    z[p] = from_t<S>((rp - ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmapc, N)) / dg);
+    const T acc = ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmapc, N);
+    const S zp = from_t<S>((rp - acc) / dg);
+    z[p] = zp;
+    if constexpr (WOUT) w[p] = spmv_row_value<T>(dg, to_t<T>(zp), acc, scale);
 }
 
-template <typename V, typename S, unsigned MASK>
-static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z, hipStream_t s)
+template <typename V, typename S, unsigned MASK, bool WOUT = false>
+static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z, hipStream_t s,
+                      SpmvOut out = {})
 {
+    using T = typename VecT<V>::T;
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
     with_cols(A, [&](auto c16) {
-        hipLaunchKernelGGL((k_gs<V, S, MASK, decltype(c16)::value>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0,
-                           cnt, A.g.N, A.clog2, tile_remap(A), v, (const void *)A.col,
-                           A.c16 ? A.cmap + c * kSlots : nullptr, d, (const S *)r, (S *)z);
+        hipLaunchKernelGGL((k_gs<V, S, MASK, decltype(c16)::value, WOUT>), dim3(grid_for(cnt)), dim3(kBlock), 0, s,
+                           row0, cnt, A.g.N, A.clog2, tile_remap(A), v, (const void *)A.col,
+                           A.c16 ? A.cmap + c * kSlots : nullptr, d, (const S *)r, (S *)z, (T *)out.w, out.scale);
     });
     HPGMX_LAUNCH_CHECK();
 }
@@ -340,9 +369,12 @@ static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void
 
 template <typename V, typename S>
 static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const void *r, void *z,
-                 hipStream_t s)
+                 hipStream_t s, SpmvOut out)
 {
-    if (mode == kGsFull) {
+    if (out.w) {
+        if (mode != kGsFull) throw std::runtime_error("the SpMV rows ride only on a full colour launch");
+        gs_launch<V, S, kAllSlots, true>(A, v, d, c, r, z, s, out);
+    } else if (mode == kGsFull) {
         gs_launch<V, S, kAllSlots>(A, v, d, c, r, z, s);
     } else if (mode == kGsZeroForward) {
         switch (c) {
@@ -358,11 +390,11 @@ static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const
 }
 
 void launch_gs_colour(const Matrix &A, Prec p, int c, int mode, const void *r, void *z,
-                      hipStream_t s)
+                      hipStream_t s, SpmvOut out)
 {
     with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
-        gs_t<V, decltype(sv)>(A, v, d, c, mode, r, z, s);
+        gs_t<V, decltype(sv)>(A, v, d, c, mode, r, z, s, out);
     });
 }
 

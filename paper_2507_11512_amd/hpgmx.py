@@ -89,7 +89,7 @@ def _load():
         "hpgmx_stencil_grad": [H, vp, vp, vp],
         "hpgmx_stencil_grad_noalloc": [H, vp, vp, vp],
         "hpgmx_set_column_format": [H, i],
-        "hpgmx_set_layout": [H, i, i, i, C.c_longlong],
+        "hpgmx_set_layout": [H, i, i, i, C.c_longlong, i],
         "hpgmx_workspace_bytes": [H, C.POINTER(MgDesc), i, C.c_uint, C.POINTER(C.c_size_t)],
         "hpgmx_bind_workspace": [H, vp, C.c_size_t],
         "hpgmx_mg_setup": [H, C.POINTER(MgDesc)],
@@ -217,8 +217,9 @@ def set_column_format(h, fmt):
     _check(h, lib.hpgmx_set_column_format(h, int(fmt)))
 
 
-def set_layout(h, tile_order=-1, ell_chunk_log2=-1, ldq_pad=-1, pair_rows=-1):
-    _check(h, lib.hpgmx_set_layout(h, int(tile_order), int(ell_chunk_log2), int(ldq_pad), int(pair_rows)))
+def set_layout(h, tile_order=-1, ell_chunk_log2=-1, ldq_pad=-1, pair_rows=-1, spmv_in_sweep=-1):
+    _check(h, lib.hpgmx_set_layout(h, int(tile_order), int(ell_chunk_log2), int(ldq_pad), int(pair_rows),
+                                   int(spmv_in_sweep)))
 
 
 def mg_setup(h, levels=4, pre=1, post=1, coarsest=1, sweep=GS_FORWARD):

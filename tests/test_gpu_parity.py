@@ -575,7 +575,7 @@ def test_layouts_bit_identical(hp, dims):
     b = oracle.spmv(dims, inputs.ones(dims))
     ref = None
     for lay in [None, {"tile_order": 0}, {"tile_order": 1}, {"tile_order": 3}, {"pair_rows": 0},
-                {"pair_rows": 1 << 40}, {"ell_chunk_log2": 0, "ldq_pad": 0},
+                {"pair_rows": 1 << 40}, {"spmv_in_sweep": 0}, {"ell_chunk_log2": 0, "ldq_pad": 0},
                 {"tile_order": 0, "ell_chunk_log2": 5, "ldq_pad": 2}]:
         P = hp.Problem(dims, beta=0.5, levels=3, sweep="forward", layout=lay)
         x, st = P.solve(dev(b, 0), tol=1e-9, precision="mxp")
@@ -630,16 +630,37 @@ def test_paired_zero_sweep_solves_identical(hp):
     assert out[0][1] == out[1][1] and np.array_equal(out[0][0], out[1][0])
 
 
+@pytest.mark.parametrize("sweep", ["forward", "backward", "symmetric"])
+@pytest.mark.parametrize("precision,cols", [("mxp", "int32"), ("fp64", "int32"), ("fp16-mg", "int32"),
+                                            ("bf16", "int32"), ("mxp", "offset16")])
+def test_spmv_rows_in_last_colour_bit_identical(hp, sweep, precision, cols):
+    """The last colour launch of each V-cycle writing its colour's rows of
+    w = A z (the SpMV then covering the other seven colours) gives the
+    iterates of one SpMV over all rows, bit for bit: 64^3 takes the slab
+    order over seven blocks for the FP32 and 16-bit SpMV."""
+    dims = (64, 64, 64)
+    b = oracle.spmv(dims, inputs.ones(dims))
+    out = []
+    for fuse in (0, 1):
+        P = hp.Problem(dims, beta=0.5, levels=3, sweep=sweep, cols=cols, layout={"spmv_in_sweep": fuse})
+        x, st = P.solve(dev(b, 0), tol=1e-9, max_iters=60, precision=precision)
+        P.close()
+        out.append((host(x), st.iters, st.final_rel_res))
+    assert out[0][1] == out[1][1] and out[0][2] == out[1][2]
+    assert np.array_equal(out[0][0], out[1][0])
+
+
 def test_layout_errors(hp):
     h = hp.setup_problem(16, 16, 16, beta=0.5)
     try:
-        for args in [(4, -1, -1, -1), (-1, 17, -1, -1), (-1, -1, 3, -1), (-1, -1, (1 << 20) + 2, -1)]:
+        for args in [(4, -1, -1, -1, -1), (-1, 17, -1, -1, -1), (-1, -1, 3, -1, -1),
+                     (-1, -1, (1 << 20) + 2, -1, -1), (-1, -1, -1, -1, 2)]:
             with pytest.raises(hp.HpgmxError):
                 hp.set_layout(h, *args)
-        hp.set_layout(h, 1, 4, 64, 100)
+        hp.set_layout(h, 1, 4, 64, 100, 0)
         hp.mg_setup(h, 2, 1, 1, 1, hp.GS_FORWARD)
         with pytest.raises(hp.HpgmxError):
-            hp.set_layout(h, -1, -1, -1, -1)
+            hp.set_layout(h, -1, -1, -1, -1, -1)
     finally:
         hp.destroy(h)
 

@@ -80,7 +80,7 @@ def test_forward_tables_unchanged():
         K_FINISH, K_GEMV, K_UPDATE, K_PERMUTE = 10, 11, 12, 13
         F16_MG, BF16_MG = 4, 5
     cfg = pm.Config(dims=(64, 64, 64), levels=3, sweep=0)
-    T = bench.kernel_bytes_table(cfg, [5], 1, H, pm)
+    T = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=False)
     V = 6  # V-cycles: 5 inner steps + the end of the cycle
     for l, d in enumerate(pm.level_dims(cfg.dims, 3)):
         cr = pm.nrows(d) // 8
@@ -88,3 +88,23 @@ def test_forward_tables_unchanged():
         assert T[(H.K_GS_ZERO, l)] == pytest.approx(V * zero)
         full = 8 * pm.gs_colour_bytes(cr, 26, 1) if l < 2 else 0
         assert T.get((H.K_GS, l), 0) == pytest.approx(V * full)
+
+
+def test_fused_spmv_rows_in_the_tables():
+    """The last colour's rows of w move from the SpMV to the last colour
+    launch: the SpMV loses their row bytes, the GS launch gains the write of
+    w, once per inner step."""
+    class H:
+        K_GS, K_GS_ZERO, K_RESTRICT, K_PROLONG = 0, 1, 2, 3
+        K_SPMV, K_DOT, K_CGS_DOT, K_CGS_NORM, K_RESID64, K_CAST = 4, 5, 6, 7, 8, 9
+        K_FINISH, K_GEMV, K_UPDATE, K_PERMUTE = 10, 11, 12, 13
+        F16_MG, BF16_MG = 4, 5
+    cfg = pm.Config(dims=(64, 64, 64), levels=3, sweep=0)
+    sep = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=False)
+    fus = bench.kernel_bytes_table(cfg, [5], 1, H, pm)
+    B = 64 ** 3 // 8
+    assert fus[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * B * 4
+    assert sep[(H.K_SPMV, 0)] - fus[(H.K_SPMV, 0)] == 5 * pm.spmv_bytes(B, 1)
+    one = pm.Config(dims=(64, 64, 64), levels=1, sweep=0)   # no post-sweep on level 0: nothing fused
+    assert bench.kernel_bytes_table(one, [5], 1, H, pm) == bench.kernel_bytes_table(one, [5], 1, H, pm,
+                                                                                  spmv_in_sweep=False)
