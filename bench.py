@@ -123,12 +123,14 @@ def vcycle_bytes(cfg, B, hp, pm, colour, restrict_after, restrict_full, prolong)
             B[(hp.K_PROLONG, l)] += prolong(rc)
 
 
-def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=True):
+def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=2):
     """Algorithmic bytes per (kernel id, level) over one solve with the given
-    cycles (idx: bytes of a stored column index).  With spmv_in_sweep (the
-    library's default) the last colour launch of each inner V-cycle also
-    writes its colour's rows of w = A z, and the SpMV covers the other 7/8
-    of the rows."""
+    cycles (idx: bytes of a stored column index).  spmv_in_sweep as the
+    library's layout setting: with 1 the last colour launch of each inner
+    V-cycle also writes its colour's rows of w = A z and the SpMV covers the
+    other 7/8 of the rows; with 2 (the default) the three launches before it
+    also write partial sums of their rows, and the SpMV reads only the
+    remaining slots of those rows."""
     from collections import defaultdict
     B = defaultdict(float)
 
@@ -141,8 +143,12 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=True):
 
     N = pm.nrows(cfg.dims)
     w = pm.wb(dtype)
-    fused = spmv_in_sweep and cfg.levels > 1 and cfg.post >= 1
+    fused = spmv_in_sweep in (1, 2) and cfg.levels > 1 and cfg.post >= 1
+    split = fused and spmv_in_sweep == 2
     last = N // 8 if fused else 0   # rows of the last colour (even grids)
+    fwd = cfg.sweep == 0
+    # the three colours before the last in sweep order: rows, slots left to the SpMV
+    late = [26 - pm.zero_guess_active_slots(c, fwd) for c in ((4, 5, 6) if fwd else (3, 2, 1))] if split else []
     mg16 = dtype in (hp.F16_MG, hp.BF16_MG)
     cast_mg = N * (w + pm.mgb(dtype)) if mg16 else 0   # scaled 16-bit copy of the V-cycle input
     for kk in cycles:
@@ -152,8 +158,10 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=True):
         for k in range(kk):
             B[(hp.K_CAST, 0)] += cast_mg
             vcyc()
-            B[(hp.K_GS, 0)] += last * w                     # the fused rows of w
-            B[(hp.K_SPMV, 0)] += pm.spmv_bytes(N - last, dtype, idx)
+            B[(hp.K_GS, 0)] += last * w * (1 + len(late))   # fused rows of w, partial sums
+            B[(hp.K_SPMV, 0)] += pm.spmv_bytes(N - last * (1 + len(late)), dtype, idx)
+            for ls in late:
+                B[(hp.K_SPMV, 0)] += pm.spmv_split_bytes(last, ls, dtype, idx)
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, 1)
             B[(hp.K_CGS_DOT, 0)] += pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += pm.cgs_pass_bytes(N, k + 1, dtype)

@@ -196,11 +196,17 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  *                  at most pair_rows rows per colour, the last two on
  *                  levels with at most pair_rows / 64; 0 = never (default
  *                  2^17).
- *   spmv_in_sweep  1 (default): the last colour launch of the V-cycle (the
- *                  last colour of the level-0 post-sweep, whose neighbours
- *                  are all final) also writes the rows of its colour of
- *                  w = A z, and the solver's SpMV covers the other seven
- *                  colours; 0: one SpMV over all rows.
+ *   spmv_in_sweep  how the solver's SpMV w = A z after each V-cycle shares
+ *                  work with the V-cycle's last level-0 sweep.  0: one SpMV
+ *                  over all rows.  1: the sweep's last colour launch (whose
+ *                  neighbours are all final) also writes its colour's rows
+ *                  of w, and the SpMV covers the other seven colours (same
+ *                  bits as 0).  2 (default): as 1, and the three launches
+ *                  before it also write, for their rows, the sum over the
+ *                  slots to colours relaxed before them, so the SpMV reads
+ *                  only the remaining 2, 6 and 8 slots of those rows.
+ *                  3: the row sums of 2, all formed by the SpMV (same bits
+ *                  as 2; differs from 0 and 1 in rounding only).
  * A negative argument keeps that default.  Orders 2 and 3 fall back to 1 on
  * levels with an odd extent.  EINVAL for values out of range;
  * ESTATE after hpgmx_mg_setup (must precede it, and hpgmx_workspace_bytes

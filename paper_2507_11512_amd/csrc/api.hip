@@ -41,6 +41,13 @@ struct Level {
     void *z[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
+// How the SpMV after a V-cycle shares its work with the V-cycle's last
+// level-0 sweep (hpgmx_set_layout spmv_in_sweep).
+constexpr int kSpmvPlain = 0;   // one SpMV over all rows
+constexpr int kSpmvLast = 1;    // the last colour launch writes its colour's rows
+constexpr int kSpmvSplit = 2;   // ... and the three colours before it their partial sums
+constexpr int kSpmvSplitSeparate = 3;  // the split sums of kSpmvSplit, all formed by the SpMV
+
 struct Krylov {
     int m = 0;
     i64 ldq = 0;        // leading dimension of Q (N rounded up, plus a skew)
@@ -48,6 +55,7 @@ struct Krylov {
     void *z = nullptr;  // V-cycle output (multigrid vector type), SpMV input
     void *u = nullptr;  // end-of-cycle Q y (Krylov type)
     void *r0 = nullptr; // 16-bit hierarchy: the scaled V-cycle input
+    void *part = nullptr;  // partial SpMV sums of the last sweep (Krylov type, N entries)
 };
 
 // Index of the multigrid vector type: 0 double, 1 float, 2 __half, 3 bf16.
@@ -85,7 +93,7 @@ struct hpgmx_ctx {
     Stencil stencil{};
     bool cols16 = false;        // column format of the hierarchy (hpgmx_set_column_format)
     Layout layout;              // data layout and tile order (hpgmx_set_layout)
-    bool fuse_spmv = true;      // last colour launch of the V-cycle writes its SpMV rows
+    int spmv_mode = kSpmvSplit; // how the V-cycle's last sweep shares the SpMV's work (hpgmx_set_layout)
     hipStream_t stream = nullptr;
     int device = 0;
     bool mg_ready = false;
@@ -355,6 +363,7 @@ void ensure_krylov(hpgmx_ctx *c, Prec p, int m)
         K.z = gathered_vector(c, (i64)N0, p);
         K.u = c->dalloc(N0 * vec_bytes(basis_prec(p)));
         if (mg16(p)) K.r0 = c->dalloc(N0 * vec_bytes(p));
+        K.part = c->dalloc(N0 * vec_bytes(basis_prec(p)));
     }
     ensure_level_vectors(c, p);
     ensure_prec(c, p);
@@ -411,6 +420,7 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
         add((N0 + 1) * vb);
         add(N0 * kb);
         if (mg16((Prec)p)) add(N0 * vb);
+        add(N0 * kb);  // partial SpMV sums
     }
     for (int vt = 0; vt < 4; ++vt)  // ABI staging buffers
         if (vt_used[vt]) for (int i = 0; i < 3; ++i) add((N0 + 1) * vt_bytes[vt]);
@@ -419,7 +429,8 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
 
 // ---- smoothing and the V-cycle ---------------------------------------------------------------------
 // With out.w the sweep's last colour launch also writes the SpMV rows of
-// its colour (see SpmvOut).
+// its colour, with out.part the three launches before it their partial
+// SpMV sums (see SpmvOut).
 void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool forward, bool zero,
                    int skip_first_colour, SpmvOut out = {})
 {
@@ -442,7 +453,10 @@ void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool for
         }
         const int mode = !zero ? kGsFull : forward ? kGsZeroForward : kGsZeroBackward;
         ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
-        launch_gs_colour(A, p, col, mode, r, z, c->stream, n == 7 ? out : SpmvOut{});
+        SpmvOut o{};
+        if (n == 7) { o.w = out.w; o.scale = out.scale; }
+        else if (n >= 4 && out.part) { o.part = out.part; o.forward = forward; }
+        launch_gs_colour(A, p, col, mode, r, z, c->stream, o);
     }
 }
 
@@ -708,10 +722,15 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
             // then the copy of its scalars (see enqueue_scal)
             auto run_step = [&](int k) {
                 auto step = [&]() {
-                    // the rows of colour fc of w = A z come from the V-cycle's
-                    // last colour launch, the others from the SpMV
-                    const int fc = c->fuse_spmv ? fused_spmv_colour(c) : -1;
-                    const SpmvOut out = fc >= 0 ? SpmvOut{col(k + 1), spmv_scale(p, c->ctrl, k)} : SpmvOut{};
+                    // w = A z: with kSpmvLast the rows of colour fc come from
+                    // the V-cycle's last colour launch, the others from the
+                    // SpMV; with kSpmvSplit the three launches before it
+                    // also leave partial sums for their rows
+                    const int fc = fused_spmv_colour(c);
+                    const int sm = fc < 0 ? kSpmvPlain : c->spmv_mode;
+                    SpmvOut out{};
+                    if (sm == kSpmvLast || sm == kSpmvSplit) { out.w = col(k + 1); out.scale = spmv_scale(p, c->ctrl, k); }
+                    if (sm == kSpmvSplit) out.part = K.part;
                     if (mg) {
                         {
                             ProfScope ps(c, HPGMX_K_CAST, 0);
@@ -723,7 +742,11 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                     }
                     {
                         ProfScope ps(c, HPGMX_K_SPMV, 0);
-                        launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k, fc);
+                        if (sm == kSpmvSplit || sm == kSpmvSplitSeparate)
+                            launch_spmv_split(A0, p, K.z, col(k + 1), K.part, fc == 7, sm == kSpmvSplit, c->stream,
+                                              c->ctrl, k);
+                        else
+                            launch_spmv(A0, p, K.z, col(k + 1), c->stream, c->ctrl, k, sm == kSpmvLast ? fc : -1);
                     }
                     {
                         PassScope ps(c, HPGMX_K_DOT, 0);
@@ -1458,8 +1481,8 @@ hpgmx_status hpgmx_set_layout(hpgmx_handle h, int tile_order, int ell_chunk_log2
         h->layout.clog2 = ell_chunk_log2 < 0 ? def.clog2 : ell_chunk_log2;
         h->layout.ldq_pad = ldq_pad < 0 ? def.ldq_pad : ldq_pad;
         h->layout.pair_rows = pair_rows < 0 ? def.pair_rows : pair_rows;
-        if (spmv_in_sweep > 1) fail(HPGMX_EINVAL, "spmv_in_sweep must be 0 or 1 (negative: default)");
-        h->fuse_spmv = spmv_in_sweep != 0;
+        if (spmv_in_sweep > kSpmvSplitSeparate) fail(HPGMX_EINVAL, "spmv_in_sweep must be 0..3 (negative: default)");
+        h->spmv_mode = spmv_in_sweep < 0 ? kSpmvSplit : spmv_in_sweep;
         return HPGMX_OK;
     });
 }

@@ -44,6 +44,12 @@ template <> __device__ __forceinline__ bf16 from_t<bf16, float>(float v) { retur
 
 __device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
 
+// acc + a x with one rounding.  The row products are written as explicit
+// fused multiply-adds so that every kernel that forms a row sum (the SpMV,
+// the smoother, their batched and fused variants) rounds it alike.
+__device__ __forceinline__ float madd(float a, float x, float acc) { return __builtin_fmaf(a, x, acc); }
+__device__ __forceinline__ double madd(double a, double x, double acc) { return __builtin_fma(a, x, acc); }
+
 // Column of a slot from its 16-bit offset d (see ColMap): p + D + d, or the
 // zero entry N for a padded slot.
 __device__ __forceinline__ int ell_col(short d, i64 p, int D, i64 N)
@@ -119,7 +125,7 @@ __device__ __forceinline__ T ell_row_dot(const V *__restrict__ offv, const void 
     T acc = (T)0;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
-        if (MASK & (1u << s)) acc += to_t<T>(a[s]) * to_t<T>(xv[s]);
+        if (MASK & (1u << s)) acc = madd(to_t<T>(a[s]), to_t<T>(xv[s]), acc);
     return acc;
 }
 
@@ -152,6 +158,45 @@ __device__ __forceinline__ i64 ell_slot_col(const void *__restrict__ offc, const
     } else {
         return ld_stream(static_cast<const int *>(offc) + er.base + (i64)s * er.stride);
     }
+}
+
+// As ell_row_dot over MASK, returning also accE, the sum over the slots of
+// EMASK alone: two accumulations in slot order over the same loads (accE
+// equals ell_row_dot over EMASK bit for bit).
+template <typename T, typename V, unsigned MASK, unsigned EMASK, bool C16, typename X>
+__device__ __forceinline__ T ell_row_dot2(const V *__restrict__ offv, const void *__restrict__ offc,
+                                          const X *x, const EllRow &er, i64 p, const int *Dc, i64 N, T &accE)
+{
+    V a[kSlots];
+    int ci[kSlots];
+    unsigned w[kPairs];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) {
+            const i64 e = er.base + (i64)s * er.stride;
+            a[s] = ld_stream(offv + e);
+            if constexpr (!C16) ci[s] = ld_stream(static_cast<const int *>(offc) + e);
+        }
+    }
+    if constexpr (C16) load_pairs<MASK>(static_cast<const unsigned *>(offc), er, w);
+    sched_fence();
+    X xv[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) {
+            if constexpr (C16) xv[s] = x[ell_col(pair_half(w[s >> 1], s), p, Dc[s], N)];
+            else xv[s] = x[ci[s]];
+        }
+    }
+    sched_fence();
+    T acc = (T)0, ae = (T)0;
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) acc = madd(to_t<T>(a[s]), to_t<T>(xv[s]), acc);
+        if (EMASK & MASK & (1u << s)) ae = madd(to_t<T>(a[s]), to_t<T>(xv[s]), ae);
+    }
+    accE = ae;
+    return acc;
 }
 
 // As ell_row_dot, with the x-neighbour slots 12 and 13 (both in MASK) taking
@@ -192,7 +237,7 @@ __device__ __forceinline__ T ell_row_dot_x(const V *__restrict__ offv, const voi
     T acc = (T)0;
 #pragma unroll
     for (int s = 0; s < kSlots; ++s)
-        if (MASK & (1u << s)) acc += to_t<T>(a[s]) * to_t<T>(xv[s]);
+        if (MASK & (1u << s)) acc = madd(to_t<T>(a[s]), to_t<T>(xv[s]), acc);
     return acc;
 }
 
@@ -411,7 +456,7 @@ __device__ __forceinline__ void ell_row_dot_b(const V *__restrict__ offv, const 
             const int s = s0 + u;
             if (s < kSlots && (MASK & (1u << s))) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) acc[r] += to_t<T>(a[s]) * xv[u].v[r];
+                for (int r = 0; r < R; ++r) acc[r] = madd(to_t<T>(a[s]), xv[u].v[r], acc[r]);
             }
         }
     }

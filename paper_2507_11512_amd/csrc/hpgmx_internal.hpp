@@ -275,11 +275,24 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
                  const Ctrl *ctrl = nullptr, int k = 0, int skip = -1);
 // The scale launch_spmv applies to its output (null without ctrl).
 const double *spmv_scale(Prec p, const Ctrl *ctrl, int k);
-// SpMV rows written by a Gauss-Seidel colour launch: y (Krylov type) and the
-// scale of launch_spmv; w = nullptr for none.
+// The SpMV after a V-cycle whose last level-0 sweep (direction `forward`)
+// wrote the rows of its last colour (7 forward, 0 backward) and, for the
+// three colours before it, the partial sums `part` (fused = true); the rows
+// of those three colours are (A z)_p = a_pp z_p + (part_p + the sum over the
+// remaining slots).  With fused = false the same values are formed from z
+// alone (part unused) and the last colour's rows are computed too.
+void launch_spmv_split(const Matrix &A, Prec p, const void *x, void *y, const void *part, bool forward,
+                       bool fused, hipStream_t s, const Ctrl *ctrl, int k);
+// What a Gauss-Seidel colour launch of the last level-0 sweep writes for the
+// SpMV that follows: with w, the SpMV rows of its colour (y of launch_spmv,
+// Krylov type, and its scale); with part, the partial sums of its rows over
+// the slots to colours relaxed before it in direction `forward` (Krylov
+// type, indexed by row; see launch_spmv_split).  Neither: nothing.
 struct SpmvOut {
     void *w = nullptr;
     const double *scale = nullptr;
+    void *part = nullptr;
+    bool forward = true;
 };
 // One colour of a Gauss-Seidel sweep: rows of colour c, slots per `mode`.
 // With out.w (full mode only) the launch also writes (A z)_p for the rows of

@@ -313,6 +313,98 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
     HPGMX_LAUNCH_CHECK();
 }
 
+// ---- SpMV after the last sweep of a V-cycle ---------------------------------------------------
+// In sweep order, the colours at positions 4-6 (forward: 4, 5, 6; backward:
+// 3, 2, 1) have their row sums split in two: E, the slots to the colours
+// relaxed before them in the sweep, and L, the others, each summed in slot
+// order, and (A z)_p = a_pp z_p + (sum_E + sum_L).  FUSED: sum_E comes from
+// part (written by the colour's own launch, k_gs with kWoutPart) and only
+// the L slots are read here -- 2, 6 and 8 of 26 -- and the rows of the
+// sweep's last colour were written by its launch, so they are not in the
+// range; otherwise both sums are formed here from z, and every row is.
+// The other colours' rows are k_spmv rows.  The two forms give the same bits.
+template <typename T, typename V, typename S, int C, bool FWD, bool FUSED, bool C16>
+__device__ __forceinline__ T split_row_sum(const V *__restrict__ offv, const void *__restrict__ offc,
+                                           const S *x, const EllRow &er, i64 p, const int *Dc, i64 N,
+                                           const T *__restrict__ part)
+{
+    constexpr unsigned E = zero_guess_mask(C, FWD), L = kAllSlots & ~E;
+    T se = (T)0;
+    if constexpr (FUSED) se = part[p];
+    const T sl = ell_row_dot<T, V, L, C16>(offv, offc, x, er, p, Dc, N);
+    if constexpr (!FUSED) se = ell_row_dot<T, V, E, C16>(offv, offc, x, er, p, Dc, N);
+    return se + sl;
+}
+
+template <typename V, typename S, bool C16, bool FWD, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_spmv_split(Geom g, i64 row0, i64 cnt, int nb, int clog2, int remap,
+                                                       const V *__restrict__ offv,
+                                                       const void *__restrict__ offc,
+                                                       const int *__restrict__ cmap,
+                                                       const V *__restrict__ diag,
+                                                       const S *__restrict__ x,
+                                                       typename VecT<V>::T *__restrict__ y,
+                                                       const typename VecT<V>::T *__restrict__ part,
+                                                       const double *scale)
+{
+    using T = typename VecT<V>::T;
+    __shared__ int cm[C16 ? kColMapSize : 1];
+    if constexpr (C16) stage_colmap(cm, cmap);
+    const i64 N = g.N;
+    i64 p = gtid_xcd(remap, nb);
+    if (p >= cnt) return;
+    p += row0;
+    const EllRow er = ell_row(p, N, clog2);
+    const int c = row_colour(g, p);
+    const int *Dc = C16 ? cm + c * kSlots : nullptr;
+    const T d = to_t<T>(ld_stream(diag + p)), xp = to_t<T>(x[p]);
+    T acc;
+    switch (FWD ? c : 7 - c) {  // position of the colour in the sweep
+    case 4: acc = split_row_sum<T, V, S, FWD ? 4 : 3, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
+    case 5: acc = split_row_sum<T, V, S, FWD ? 5 : 2, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
+    case 6: acc = split_row_sum<T, V, S, FWD ? 6 : 1, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
+    default: acc = ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N); break;
+    }
+    y[p] = spmv_row_value<T>(d, xp, acc, scale);
+}
+
+void launch_spmv_split(const Matrix &A, Prec p, const void *x, void *y, const void *part, bool forward,
+                       bool fused, hipStream_t s, const Ctrl *ctrl, int k)
+{
+    const double *scale = spmv_scale(p, ctrl, k);
+    i64 row0 = 0, cnt = A.g.N;
+    int nb = 8;
+    if (fused) {
+        nb = 7;
+        if (forward) cnt = A.g.off[7];
+        else { row0 = A.g.off[1]; cnt = A.g.N - row0; }
+    }
+    if (cnt == 0) return;
+    with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using S = decltype(sv);
+        using T = typename VecT<V>::T;
+        int order = spmv_order(A, std::is_same<V, double>::value, nb);
+        if (order == kRemapPlanes) order = 1;
+        with_cols(A, [&](auto c16) {
+            constexpr bool C = decltype(c16)::value;
+            auto go = [&](auto kern) {
+                hipLaunchKernelGGL(kern, dim3(grid_for(cnt)), dim3(kBlock), 0, s, A.g, row0, cnt, nb, A.clog2, order,
+                                   (const V *)v, (const void *)A.col, A.cmap, (const V *)d, (const S *)x, (T *)y,
+                                   (const T *)part, scale);
+            };
+            if (forward) {
+                if (fused) go(k_spmv_split<V, S, C, true, true>);
+                else go(k_spmv_split<V, S, C, true, false>);
+            } else {
+                if (fused) go(k_spmv_split<V, S, C, false, true>);
+                else go(k_spmv_split<V, S, C, false, false>);
+            }
+        });
+    });
+    HPGMX_LAUNCH_CHECK();
+}
+
 // ---- Gauss-Seidel, one colour ---------------------------------------------------------------
 // Rows p in [row0, row0 + cnt) of one colour:
 //   z_p <- (r_p - sum_{s in MASK} a_{p,s} z_{col(p,s)}) / a_pp
@@ -324,11 +416,17 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 // zero, and skipping them gives the same result bit for bit).  r and z are
 // stored in S and the row is evaluated in T.
 //
-// With WOUT (the last colour launch of a V-cycle, all slots): every
-// neighbour of the colour is final once the colour is relaxed, so the
-// launch also writes the SpMV rows of its colour, w_p = (A z)_p, from the
-// slot sum it already holds (spmv_row_value; same bits as k_spmv).
-template <typename V, typename S, unsigned MASK, bool C16, bool WOUT = false>
+// The last sweep of a V-cycle's level-0 post-smoothing also prepares the
+// SpMV w = A z that follows it (WOUT):
+//  * kWoutRow, the sweep's last colour (every neighbour is final once it is
+//    relaxed): the launch writes the SpMV rows of its colour,
+//    w_p = (A z)_p, from the slot sum it already holds (spmv_row_value,
+//    same bits as the SpMV kernels);
+//  * kWoutPart, the three colours before it: the launch writes part_p, the
+//    sum over the slots EMASK of the neighbours relaxed before the colour
+//    (final from then on); the SpMV adds the remaining slots (k_spmv_split).
+constexpr int kWoutNone = 0, kWoutRow = 1, kWoutPart = 2;
+template <typename V, typename S, unsigned MASK, bool C16, int WOUT = kWoutNone, unsigned EMASK = 0>
 __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
                                                const V *__restrict__ offv,
                                                const void *__restrict__ offc, const int *__restrict__ cmapc,
@@ -343,25 +441,42 @@ __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clo
     const EllRow er = ell_row(p, N, clog2);
     const T rp = to_t<T>(r[p]);
     const T dg = to_t<T>(ld_stream(diag + p));
-    const T acc = ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmapc, N);
-    const S zp = from_t<S>((rp - acc) / dg);
-    z[p] = zp;
-    if constexpr (WOUT) w[p] = spmv_row_value<T>(dg, to_t<T>(zp), acc, scale);
+    if constexpr (WOUT == kWoutPart) {
+        T accE;
+        const T acc = ell_row_dot2<T, V, MASK, EMASK, C16>(offv, offc, z, er, p, cmapc, N, accE);
+        z[p] = from_t<S>((rp - acc) / dg);
+        w[p] = accE;
+    } else {
+        const T acc = ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmapc, N);
+        const S zp = from_t<S>((rp - acc) / dg);
+        z[p] = zp;
+        if constexpr (WOUT == kWoutRow) w[p] = spmv_row_value<T>(dg, to_t<T>(zp), acc, scale);
+    }
 }
 
-template <typename V, typename S, unsigned MASK, bool WOUT = false>
+template <typename V, typename S, unsigned MASK, int WOUT = kWoutNone, unsigned EMASK = 0>
 static void gs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z, hipStream_t s,
                       SpmvOut out = {})
 {
     using T = typename VecT<V>::T;
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
+    void *w = WOUT == kWoutPart ? out.part : out.w;
     with_cols(A, [&](auto c16) {
-        hipLaunchKernelGGL((k_gs<V, S, MASK, decltype(c16)::value, WOUT>), dim3(grid_for(cnt)), dim3(kBlock), 0, s,
-                           row0, cnt, A.g.N, A.clog2, tile_remap(A), v, (const void *)A.col,
-                           A.c16 ? A.cmap + c * kSlots : nullptr, d, (const S *)r, (S *)z, (T *)out.w, out.scale);
+        hipLaunchKernelGGL((k_gs<V, S, MASK, decltype(c16)::value, WOUT, EMASK>), dim3(grid_for(cnt)), dim3(kBlock),
+                           0, s, row0, cnt, A.g.N, A.clog2, tile_remap(A), v, (const void *)A.col,
+                           A.c16 ? A.cmap + c * kSlots : nullptr, d, (const S *)r, (S *)z, (T *)w, out.scale);
     });
     HPGMX_LAUNCH_CHECK();
+}
+
+// The full-slot launch of colour C that also writes its partial SpMV sums
+// over the neighbours relaxed before it (direction FWD).
+template <typename V, typename S, int C, bool FWD>
+static void gs_part_launch(const Matrix &A, const V *v, const V *d, const void *r, void *z, hipStream_t s,
+                           SpmvOut out)
+{
+    gs_launch<V, S, kAllSlots, kWoutPart, zero_guess_mask(C, FWD)>(A, v, d, C, r, z, s, out);
 }
 
 #define HPGMX_GS_CASE(C, FWD) \
@@ -371,9 +486,21 @@ template <typename V, typename S>
 static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const void *r, void *z,
                  hipStream_t s, SpmvOut out)
 {
-    if (out.w) {
+    if (out.w || out.part) {
         if (mode != kGsFull) throw std::runtime_error("the SpMV rows ride only on a full colour launch");
-        gs_launch<V, S, kAllSlots, true>(A, v, d, c, r, z, s, out);
+        if (out.w) {
+            gs_launch<V, S, kAllSlots, kWoutRow>(A, v, d, c, r, z, s, out);
+        } else {
+            switch (c + (out.forward ? 0 : 8)) {
+            case 4: gs_part_launch<V, S, 4, true>(A, v, d, r, z, s, out); break;
+            case 5: gs_part_launch<V, S, 5, true>(A, v, d, r, z, s, out); break;
+            case 6: gs_part_launch<V, S, 6, true>(A, v, d, r, z, s, out); break;
+            case 8 + 1: gs_part_launch<V, S, 1, false>(A, v, d, r, z, s, out); break;
+            case 8 + 2: gs_part_launch<V, S, 2, false>(A, v, d, r, z, s, out); break;
+            case 8 + 3: gs_part_launch<V, S, 3, false>(A, v, d, r, z, s, out); break;
+            default: throw std::runtime_error("partial SpMV sums: colours 4-6 (forward) or 3-1 (backward) only");
+            }
+        }
     } else if (mode == kGsFull) {
         gs_launch<V, S, kAllSlots>(A, v, d, c, r, z, s);
     } else if (mode == kGsZeroForward) {

@@ -155,6 +155,14 @@ def spmv_bytes(rows, dtype, idx=IDX):
     return rows * (SLOTS * (v + idx) + v + mgb(dtype) + wb(dtype))
 
 
+def spmv_split_bytes(rows, late_slots, dtype, idx=IDX):
+    """SpMV rows whose sum over the slots to earlier colours was written by
+    the colour's own smoother launch: the `late_slots` remaining slots, the
+    diagonal, x, the partial sum read and y written."""
+    v = vb(dtype)
+    return rows * (late_slots * (v + idx) + v + mgb(dtype) + 2 * wb(dtype))
+
+
 def cgs_pass_bytes(rows, kb, dtype):
     """w <- w - Q c fused with a reduction: kb columns and w read, w written."""
     return rows * (kb + 2) * wb(dtype)

@@ -80,7 +80,7 @@ def test_forward_tables_unchanged():
         K_FINISH, K_GEMV, K_UPDATE, K_PERMUTE = 10, 11, 12, 13
         F16_MG, BF16_MG = 4, 5
     cfg = pm.Config(dims=(64, 64, 64), levels=3, sweep=0)
-    T = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=False)
+    T = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=0)
     V = 6  # V-cycles: 5 inner steps + the end of the cycle
     for l, d in enumerate(pm.level_dims(cfg.dims, 3)):
         cr = pm.nrows(d) // 8
@@ -100,11 +100,16 @@ def test_fused_spmv_rows_in_the_tables():
         K_FINISH, K_GEMV, K_UPDATE, K_PERMUTE = 10, 11, 12, 13
         F16_MG, BF16_MG = 4, 5
     cfg = pm.Config(dims=(64, 64, 64), levels=3, sweep=0)
-    sep = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=False)
-    fus = bench.kernel_bytes_table(cfg, [5], 1, H, pm)
+    sep = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=0)
+    last = bench.kernel_bytes_table(cfg, [5], 1, H, pm, spmv_in_sweep=1)
     B = 64 ** 3 // 8
-    assert fus[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * B * 4
-    assert sep[(H.K_SPMV, 0)] - fus[(H.K_SPMV, 0)] == 5 * pm.spmv_bytes(B, 1)
+    assert last[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * B * 4
+    assert sep[(H.K_SPMV, 0)] - last[(H.K_SPMV, 0)] == 5 * pm.spmv_bytes(B, 1)
+    # with partial sums: colours 4, 5, 6 leave 8, 6 and 2 slots to the SpMV
+    split = bench.kernel_bytes_table(cfg, [5], 1, H, pm)
+    assert split[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * 4 * B * 4
+    row = lambda ls: ls * 8 + 4 + 4 + 2 * 4
+    assert sep[(H.K_SPMV, 0)] - split[(H.K_SPMV, 0)] == 5 * (4 * pm.spmv_bytes(B, 1) - B * sum(map(row, (8, 6, 2))))
     one = pm.Config(dims=(64, 64, 64), levels=1, sweep=0)   # no post-sweep on level 0: nothing fused
     assert bench.kernel_bytes_table(one, [5], 1, H, pm) == bench.kernel_bytes_table(one, [5], 1, H, pm,
-                                                                                  spmv_in_sweep=False)
+                                                                                  spmv_in_sweep=0)
