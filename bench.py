@@ -128,9 +128,9 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=2):
     cycles (idx: bytes of a stored column index).  spmv_in_sweep as the
     library's layout setting: with 1 the last colour launch of each inner
     V-cycle also writes its colour's rows of w = A z and the SpMV covers the
-    other 7/8 of the rows; with 2 (the default) the three launches before it
-    also write partial sums of their rows, and the SpMV reads only the
-    remaining slots of those rows."""
+    other 7/8 of the rows; with 2 (the default) the launches at sweep
+    positions 2-6 also write partial sums of their rows, and the SpMV reads
+    only the remaining slots of those rows."""
     from collections import defaultdict
     B = defaultdict(float)
 
@@ -147,8 +147,8 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=2):
     split = fused and spmv_in_sweep == 2
     last = N // 8 if fused else 0   # rows of the last colour (even grids)
     fwd = cfg.sweep == 0
-    # the three colours before the last in sweep order: rows, slots left to the SpMV
-    late = [26 - pm.zero_guess_active_slots(c, fwd) for c in ((4, 5, 6) if fwd else (3, 2, 1))] if split else []
+    # sweep positions 2-6: slots left to the SpMV
+    late = [26 - pm.zero_guess_active_slots(c if fwd else 7 - c, fwd) for c in range(2, 7)] if split else []
     mg16 = dtype in (hp.F16_MG, hp.BF16_MG)
     cast_mg = N * (w + pm.mgb(dtype)) if mg16 else 0   # scaled 16-bit copy of the V-cycle input
     for kk in cycles:

@@ -201,10 +201,11 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  *                  over all rows.  1: the sweep's last colour launch (whose
  *                  neighbours are all final) also writes its colour's rows
  *                  of w, and the SpMV covers the other seven colours (same
- *                  bits as 0).  2 (default): as 1, and the three launches
- *                  before it also write, for their rows, the sum over the
- *                  slots to colours relaxed before them, so the SpMV reads
- *                  only the remaining 2, 6 and 8 slots of those rows.
+ *                  bits as 0).  2 (default): as 1, and the launches of the
+ *                  sweep's third to seventh colours also write, for their
+ *                  rows, the sum over the slots to colours relaxed before
+ *                  them, so the SpMV reads only the remaining 20, 18, 8, 6
+ *                  and 2 slots of those rows.
  *                  3: the row sums of 2, all formed by the SpMV (same bits
  *                  as 2; differs from 0 and 1 in rounding only).
  * A negative argument keeps that default.  Orders 2 and 3 fall back to 1 on

@@ -47,6 +47,7 @@ constexpr int kSpmvPlain = 0;   // one SpMV over all rows
 constexpr int kSpmvLast = 1;    // the last colour launch writes its colour's rows
 constexpr int kSpmvSplit = 2;   // ... and the three colours before it their partial sums
 constexpr int kSpmvSplitSeparate = 3;  // the split sums of kSpmvSplit, all formed by the SpMV
+constexpr int kSplitFirst = 2;  // first sweep position with partial sums (see k_spmv_split)
 
 struct Krylov {
     int m = 0;
@@ -429,8 +430,8 @@ size_t plan_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, int m, 
 
 // ---- smoothing and the V-cycle ---------------------------------------------------------------------
 // With out.w the sweep's last colour launch also writes the SpMV rows of
-// its colour, with out.part the three launches before it their partial
-// SpMV sums (see SpmvOut).
+// its colour, with out.part the launches at sweep positions 2-6 their
+// partial SpMV sums (see SpmvOut).
 void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool forward, bool zero,
                    int skip_first_colour, SpmvOut out = {})
 {
@@ -455,7 +456,7 @@ void sweep_colours(hpgmx_ctx *c, int l, Prec p, const void *r, void *z, bool for
         ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
         SpmvOut o{};
         if (n == 7) { o.w = out.w; o.scale = out.scale; }
-        else if (n >= 4 && out.part) { o.part = out.part; o.forward = forward; }
+        else if (n >= kSplitFirst && out.part) { o.part = out.part; o.forward = forward; }
         launch_gs_colour(A, p, col, mode, r, z, c->stream, o);
     }
 }
@@ -724,8 +725,8 @@ hpgmx_status solve(hpgmx_ctx *c, const double *b, double *x, const hpgmx_solve_d
                 auto step = [&]() {
                     // w = A z: with kSpmvLast the rows of colour fc come from
                     // the V-cycle's last colour launch, the others from the
-                    // SpMV; with kSpmvSplit the three launches before it
-                    // also leave partial sums for their rows
+                    // SpMV; with kSpmvSplit the launches at sweep positions
+                    // 2-6 also leave partial sums for their rows
                     const int fc = fused_spmv_colour(c);
                     const int sm = fc < 0 ? kSpmvPlain : c->spmv_mode;
                     SpmvOut out{};

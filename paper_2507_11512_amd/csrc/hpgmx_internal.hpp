@@ -277,9 +277,9 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 const double *spmv_scale(Prec p, const Ctrl *ctrl, int k);
 // The SpMV after a V-cycle whose last level-0 sweep (direction `forward`)
 // wrote the rows of its last colour (7 forward, 0 backward) and, for the
-// three colours before it, the partial sums `part` (fused = true); the rows
-// of those three colours are (A z)_p = a_pp z_p + (part_p + the sum over the
-// remaining slots).  With fused = false the same values are formed from z
+// colours at sweep positions 2-6, the partial sums `part` (fused = true);
+// the rows of those colours are (A z)_p = a_pp z_p + (part_p + the sum over
+// the remaining slots).  With fused = false the same values are formed from z
 // alone (part unused) and the last colour's rows are computed too.
 void launch_spmv_split(const Matrix &A, Prec p, const void *x, void *y, const void *part, bool forward,
                        bool fused, hipStream_t s, const Ctrl *ctrl, int k);

@@ -314,15 +314,17 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 }
 
 // ---- SpMV after the last sweep of a V-cycle ---------------------------------------------------
-// In sweep order, the colours at positions 4-6 (forward: 4, 5, 6; backward:
-// 3, 2, 1) have their row sums split in two: E, the slots to the colours
+// In sweep order, the colours at positions 2-6 (forward: 2 ... 6; backward:
+// 5 ... 1) have their row sums split in two: E, the slots to the colours
 // relaxed before them in the sweep, and L, the others, each summed in slot
 // order, and (A z)_p = a_pp z_p + (sum_E + sum_L).  FUSED: sum_E comes from
 // part (written by the colour's own launch, k_gs with kWoutPart) and only
-// the L slots are read here -- 2, 6 and 8 of 26 -- and the rows of the
-// sweep's last colour were written by its launch, so they are not in the
-// range; otherwise both sums are formed here from z, and every row is.
-// The other colours' rows are k_spmv rows.  The two forms give the same bits.
+// the L slots are read here -- 20, 18, 8, 6 and 2 of 26 -- and the rows of
+// the sweep's last colour were written by its launch, so they are not in
+// the range; otherwise both sums are formed here from z, and every row is.
+// The rows of the first colour (no E slots) are k_spmv rows.  The two forms
+// give the same bits.  (Position 1 would save 2 slots for the 4 bytes of a
+// partial sum written and read again: not worth a launch variant.)
 template <typename T, typename V, typename S, int C, bool FWD, bool FUSED, bool C16>
 __device__ __forceinline__ T split_row_sum(const V *__restrict__ offv, const void *__restrict__ offc,
                                            const S *x, const EllRow &er, i64 p, const int *Dc, i64 N,
@@ -360,6 +362,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_split(Geom g, i64 row0, i64 cnt
     const T d = to_t<T>(ld_stream(diag + p)), xp = to_t<T>(x[p]);
     T acc;
     switch (FWD ? c : 7 - c) {  // position of the colour in the sweep
+    case 2: acc = split_row_sum<T, V, S, FWD ? 2 : 5, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
+    case 3: acc = split_row_sum<T, V, S, FWD ? 3 : 4, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
     case 4: acc = split_row_sum<T, V, S, FWD ? 4 : 3, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
     case 5: acc = split_row_sum<T, V, S, FWD ? 5 : 2, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
     case 6: acc = split_row_sum<T, V, S, FWD ? 6 : 1, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
@@ -422,7 +426,7 @@ void launch_spmv_split(const Matrix &A, Prec p, const void *x, void *y, const vo
 //    relaxed): the launch writes the SpMV rows of its colour,
 //    w_p = (A z)_p, from the slot sum it already holds (spmv_row_value,
 //    same bits as the SpMV kernels);
-//  * kWoutPart, the three colours before it: the launch writes part_p, the
+//  * kWoutPart, the colours at sweep positions 2-6: the launch writes part_p, the
 //    sum over the slots EMASK of the neighbours relaxed before the colour
 //    (final from then on); the SpMV adds the remaining slots (k_spmv_split).
 constexpr int kWoutNone = 0, kWoutRow = 1, kWoutPart = 2;
@@ -492,13 +496,17 @@ static void gs_t(const Matrix &A, const V *v, const V *d, int c, int mode, const
             gs_launch<V, S, kAllSlots, kWoutRow>(A, v, d, c, r, z, s, out);
         } else {
             switch (c + (out.forward ? 0 : 8)) {
+            case 2: gs_part_launch<V, S, 2, true>(A, v, d, r, z, s, out); break;
+            case 3: gs_part_launch<V, S, 3, true>(A, v, d, r, z, s, out); break;
             case 4: gs_part_launch<V, S, 4, true>(A, v, d, r, z, s, out); break;
             case 5: gs_part_launch<V, S, 5, true>(A, v, d, r, z, s, out); break;
             case 6: gs_part_launch<V, S, 6, true>(A, v, d, r, z, s, out); break;
             case 8 + 1: gs_part_launch<V, S, 1, false>(A, v, d, r, z, s, out); break;
             case 8 + 2: gs_part_launch<V, S, 2, false>(A, v, d, r, z, s, out); break;
             case 8 + 3: gs_part_launch<V, S, 3, false>(A, v, d, r, z, s, out); break;
-            default: throw std::runtime_error("partial SpMV sums: colours 4-6 (forward) or 3-1 (backward) only");
+            case 8 + 4: gs_part_launch<V, S, 4, false>(A, v, d, r, z, s, out); break;
+            case 8 + 5: gs_part_launch<V, S, 5, false>(A, v, d, r, z, s, out); break;
+            default: throw std::runtime_error("partial SpMV sums: sweep positions 2-6 only");
             }
         }
     } else if (mode == kGsFull) {

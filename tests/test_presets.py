@@ -105,11 +105,12 @@ def test_fused_spmv_rows_in_the_tables():
     B = 64 ** 3 // 8
     assert last[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * B * 4
     assert sep[(H.K_SPMV, 0)] - last[(H.K_SPMV, 0)] == 5 * pm.spmv_bytes(B, 1)
-    # with partial sums: colours 4, 5, 6 leave 8, 6 and 2 slots to the SpMV
+    # with partial sums: colours 2 ... 6 leave 20, 18, 8, 6 and 2 slots to the SpMV
     split = bench.kernel_bytes_table(cfg, [5], 1, H, pm)
-    assert split[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * 4 * B * 4
+    assert split[(H.K_GS, 0)] - sep[(H.K_GS, 0)] == 5 * 6 * B * 4
     row = lambda ls: ls * 8 + 4 + 4 + 2 * 4
-    assert sep[(H.K_SPMV, 0)] - split[(H.K_SPMV, 0)] == 5 * (4 * pm.spmv_bytes(B, 1) - B * sum(map(row, (8, 6, 2))))
+    assert sep[(H.K_SPMV, 0)] - split[(H.K_SPMV, 0)] == 5 * (6 * pm.spmv_bytes(B, 1) -
+                                                             B * sum(map(row, (20, 18, 8, 6, 2))))
     one = pm.Config(dims=(64, 64, 64), levels=1, sweep=0)   # no post-sweep on level 0: nothing fused
     assert bench.kernel_bytes_table(one, [5], 1, H, pm) == bench.kernel_bytes_table(one, [5], 1, H, pm,
                                                                                   spmv_in_sweep=0)
