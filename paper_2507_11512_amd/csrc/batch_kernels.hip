@@ -52,11 +52,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, int clog2, int remap,
     ell_row_dot_b<T, V, K, R, kAllSlots>(offv, offc, x + g * R, er, acc);
     Pack<T, R> out;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const T dx = d * xp.v[r];
-        const T v = dx + acc[r];
-        out.v[r] = ctrl ? v * (T)ctrl[g * R + r].colscale[k] : v;
-    }
+    for (int r = 0; r < R; ++r)
+        out.v[r] = spmv_row_value<T>(d, xp.v[r], acc[r], ctrl ? ctrl[g * R + r].colscale + k : nullptr);
     stp<T, R>(y + o, out);
 }
 
@@ -189,8 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_bresid64(i64 N, int clog2, int remap
     Pack<double, R> out;
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-        const double v = d * xp.v[i] + acc[i];
-        out.v[i] = bp.v[i] - v;
+        out.v[i] = bp.v[i] - spmv_row_value<double>(d, xp.v[i], acc[i], nullptr);
     }
     stp<double, R>(r + o, out);
 }

@@ -115,8 +115,9 @@ __global__ __launch_bounds__(kBlock) void k_resid64(Geom g, int clog2, int remap
         const EllRow er = ell_row(p, N, clog2);
         const double bp = b[p];
         const int *Dc = C16 ? cm + row_colour(g, p) * kSlots : nullptr;
-        const double v = ld_stream(diag + p) * x[p] + ell_row_dot<double, double, kAllSlots, C16>(offv, offc, x, er, p, Dc, N);
-        const double rv = bp - v;
+        const double rv = bp - spmv_row_value<double>(ld_stream(diag + p), x[p],
+                                                      ell_row_dot<double, double, kAllSlots, C16>(offv, offc, x, er, p, Dc, N),
+                                                      nullptr);
         r[p] = rv;
         acc[0] += rv * rv;
     }

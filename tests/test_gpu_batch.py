@@ -266,7 +266,11 @@ def test_solve_batched_freezes_each_rhs(hp, precision):
                 assert st.converged and st.iters == 0 and np.all(Xh[j] == 0.0)
                 continue
             xsh = host(xs)
-            tol = 1e-10 if precision == "fp64" else 1e-6
+            # The single solver's SpMV takes 5/8 of its row sums in two parts
+            # (partial sums left by the last sweep); the batched one sums them
+            # whole.  The FP32 roundings differ, which an unconverged run
+            # (7 steps) carries into x at the 1e-6 level.
+            tol = 1e-10 if precision == "fp64" else (1e-6 if sts.converged else 1e-5)
             assert np.linalg.norm(Xh[j] - xsh) <= tol * np.linalg.norm(xsh), j
     with pytest.raises(hp.HpgmxError) as e:
         bad = dev(B, 0)
