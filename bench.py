@@ -175,8 +175,9 @@ def kernel_bytes_table(cfg, cycles, dtype, hp, pm, idx=4, spmv_in_sweep=2):
     return B
 
 
-def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
-    """As kernel_bytes_table for K right-hand sides in lockstep."""
+def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm, spmv_in_sweep=2):
+    """As kernel_bytes_table for K right-hand sides in lockstep (the partial
+    SpMV sums of spmv_in_sweep = 2 for FP32 and FP64 batches)."""
     from collections import defaultdict
     B = defaultdict(float)
 
@@ -189,12 +190,20 @@ def kernel_bytes_table_batched(cfg, cycles, dtype, K, hp, pm):
 
     N = pm.nrows(cfg.dims)
     w = pm.wb(dtype)
+    split = spmv_in_sweep in (2,) and dtype in (0, 1) and cfg.levels > 1 and cfg.post >= 1
+    last = N // 8 if split else 0
+    fwd = cfg.sweep == 0
+    late = [26 - pm.zero_guess_active_slots(c if fwd else 7 - c, fwd) for c in range(2, 7)] if split else []
+    v = pm.vb(dtype)
     for kk in cycles:
         B[(hp.K_RESID64, 0)] += pm.bresid64_bytes(N, K)
         B[(hp.K_CAST, 0)] += N * K * (8 + w)
         for k in range(kk):
             vcyc()
-            B[(hp.K_SPMV, 0)] += pm.bspmv_bytes(N, dtype, K)
+            B[(hp.K_GS, 0)] += last * K * w * (1 + len(late))   # fused rows of w, partial sums
+            B[(hp.K_SPMV, 0)] += pm.bspmv_bytes(N - last * (1 + len(late)), dtype, K)
+            for ls in late:   # remaining slots, diagonal, x, partial sums read, y written
+                B[(hp.K_SPMV, 0)] += last * (ls * (v + pm.IDX) + v + 3 * K * w)
             B[(hp.K_DOT, 0)] += pm.bdot_bytes(N, k + 1, dtype, K)
             B[(hp.K_CGS_DOT, 0)] += K * pm.cgs_dot_bytes(N, k + 1, dtype)
             B[(hp.K_CGS_NORM, 0)] += K * pm.cgs_pass_bytes(N, k + 1, dtype)

@@ -207,7 +207,9 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  *                  them, so the SpMV reads only the remaining 20, 18, 8, 6
  *                  and 2 slots of those rows.
  *                  3: the row sums of 2, all formed by the SpMV (same bits
- *                  as 2; differs from 0 and 1 in rounding only).
+ *                  as 2; differs from 0 and 1 in rounding only).  Batched
+ *                  solves follow 0, 2 and 3 (1 runs as 0) with FP32 or FP64
+ *                  matrices, and 0 with 16-bit ones.
  * A negative argument keeps that default.  Orders 2 and 3 fall back to 1 on
  * levels with an odd extent.  EINVAL for values out of range;
  * ESTATE after hpgmx_mg_setup (must precede it, and hpgmx_workspace_bytes

@@ -47,7 +47,7 @@ constexpr int kSpmvPlain = 0;   // one SpMV over all rows
 constexpr int kSpmvLast = 1;    // the last colour launch writes its colour's rows
 constexpr int kSpmvSplit = 2;   // ... and the three colours before it their partial sums
 constexpr int kSpmvSplitSeparate = 3;  // the split sums of kSpmvSplit, all formed by the SpMV
-constexpr int kSplitFirst = 2;  // first sweep position with partial sums (see k_spmv_split)
+constexpr int kSplitFirst = 2;  // first sweep position with partial sums (see launch_spmv_split)
 
 struct Krylov {
     int m = 0;
@@ -893,6 +893,7 @@ void ensure_batch_prec(hpgmx_ctx *c, Batch &B, Prec p, int m)
     if (!Kr.z) {
         Kr.z = gathered_batch(c, N0, K, p);
         Kr.u = c->dalloc((size_t)N0 * K * vec_bytes(p));
+        Kr.part = c->dalloc((size_t)N0 * K * vec_bytes(p));
     }
 }
 
@@ -913,8 +914,9 @@ int tile_r(const hpgmx_ctx *c, const Batch &B, Prec p, int kind, int l)
     return c->lv[l].A.g.N * B.K >= (1ll << 22) ? B.K : 1;
 }
 
+// With out.y / out.part as sweep_colours() with SpmvOut.
 void bsweep_colours(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z, bool forward, bool zero,
-                    int skip_first_colour)
+                    int skip_first_colour, BSpmvOut out = {})
 {
     const Matrix &A = c->lv[l].A;
     const int R = tile_r(c, B, p, zero ? HPGMX_BK_GS_ZERO : HPGMX_BK_GS, l);
@@ -923,12 +925,15 @@ void bsweep_colours(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *
         if (n == 0 && skip_first_colour) continue;
         const int mode = !zero ? kGsFull : forward ? kGsZeroForward : kGsZeroBackward;
         ProfScope ps(c, zero ? HPGMX_K_GS_ZERO : HPGMX_K_GS, l);
-        launch_bgs_colour(A, p, B.K, R, col, mode, r, z, c->stream);
+        BSpmvOut o{};
+        if (n == 7) { o.y = out.y; o.ctrl = out.ctrl; o.k = out.k; }
+        else if (n >= kSplitFirst && out.part) { o.part = out.part; o.forward = forward; }
+        launch_bgs_colour(A, p, B.K, R, col, mode, r, z, c->stream, o);
     }
 }
 
 void bsmooth_level(hpgmx_ctx *c, Batch &B, int l, Prec p, int kind, const void *r, void *z, bool zero,
-                   int nsweeps)
+                   int nsweeps, BSpmvOut out = {})
 {
     if (nsweeps <= 0) {
         if (zero)
@@ -938,13 +943,14 @@ void bsmooth_level(hpgmx_ctx *c, Batch &B, int l, Prec p, int kind, const void *
     }
     for (int s = 0; s < nsweeps; ++s) {
         const bool zg = zero && s == 0;
+        const BSpmvOut o = s == nsweeps - 1 ? out : BSpmvOut{};
         if (kind == HPGMX_GS_FORWARD) {
-            bsweep_colours(c, B, l, p, r, z, true, zg, 0);
+            bsweep_colours(c, B, l, p, r, z, true, zg, 0, o);
         } else if (kind == HPGMX_GS_BACKWARD) {
-            bsweep_colours(c, B, l, p, r, z, false, zg, 0);
+            bsweep_colours(c, B, l, p, r, z, false, zg, 0, o);
         } else {
             bsweep_colours(c, B, l, p, r, z, true, zg, 0);
-            bsweep_colours(c, B, l, p, r, z, false, false, 1);  // colour 7 is unchanged
+            bsweep_colours(c, B, l, p, r, z, false, false, 1, o);  // colour 7 is unchanged
         }
     }
 }
@@ -963,8 +969,8 @@ void bpresmooth_restrict(hpgmx_ctx *c, Batch &B, int l, Prec p, int kind, int ns
         launch_brestrict(c->lv[l].A, gc, p, B.K, R, r, z, rc, c->stream);
 }
 
-// The V-cycle of vcycle() for K right-hand sides at once.
-void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z)
+// The V-cycle of vcycle() for K right-hand sides at once (out: as vcycle()).
+void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z, BSpmvOut out = {})
 {
     const hpgmx_mg_desc &mg = c->mg;
     const int vt = vt_of(p);
@@ -979,7 +985,7 @@ void bvcycle(hpgmx_ctx *c, Batch &B, int l, Prec p, const void *r, void *z)
         ProfScope ps(c, HPGMX_K_PROLONG, l);
         launch_bprolong(c->lv[l].A.g, gc, p, B.K, B.lz[vt][l + 1], z, c->stream);
     }
-    bsmooth_level(c, B, l, p, mg.sweep, r, z, false, mg.post_sweeps);
+    bsmooth_level(c, B, l, p, mg.sweep, r, z, false, mg.post_sweeps, out);
 }
 
 // Times every R for every batched kernel kind and level (on zeroed staging
@@ -1159,11 +1165,23 @@ hpgmx_status bsolve(hpgmx_ctx *c, int nrhs, const double *Bn, double *Xn, const 
             // deep as in solve(); see enqueue_scal)
             auto run_step = [&](int k) {
                 auto step = [&]() {
-                    bvcycle(c, B, 0, p, col(k), Kr.z);
+                    // w = A z shared with the V-cycle's last sweep as in solve()
+                    // (FP32 and FP64 batches; the last colour alone is not
+                    // offered: kSpmvLast runs as kSpmvPlain)
+                    const int fc = fused_spmv_colour(c);
+                    const int sm = fc < 0 || (p != P32 && p != P64) || c->spmv_mode == kSpmvLast ? kSpmvPlain
+                                                                                                  : c->spmv_mode;
+                    BSpmvOut out{};
+                    if (sm == kSpmvSplit) { out.y = col(k + 1); out.ctrl = B.ctrl; out.k = k; out.part = Kr.part; }
+                    bvcycle(c, B, 0, p, col(k), Kr.z, out);
                     {
                         ProfScope ps(c, HPGMX_K_SPMV, 0);
-                        launch_bspmv(A0, p, K, tile_r(c, B, p, HPGMX_BK_SPMV, 0), Kr.z, col(k + 1), c->stream,
-                                     B.ctrl, k);
+                        const int Rs = tile_r(c, B, p, HPGMX_BK_SPMV, 0);
+                        if (sm == kSpmvSplit || sm == kSpmvSplitSeparate)
+                            launch_bspmv_split(A0, p, K, Rs, Kr.z, col(k + 1), Kr.part, fc == 7, sm == kSpmvSplit,
+                                               c->stream, B.ctrl, k);
+                        else
+                            launch_bspmv(A0, p, K, Rs, Kr.z, col(k + 1), c->stream, B.ctrl, k);
                     }
                     {
                         PassScope ps(c, HPGMX_K_DOT, 0);
@@ -1287,6 +1305,7 @@ size_t plan_batch_bytes(const hpgmx_problem_desc &pd, const hpgmx_mg_desc &mg, i
         add((size_t)krylov_ldq((i64)(N0 * K), lay.ldq_pad) * (m + 1) * vb);
         add((N0 + 1) * K * vb);
         add(N0 * K * vb);
+        add(N0 * K * vb);  // partial SpMV sums
         for (int i = 0; i < 3; ++i) add((N0 + 1) * K * vb);  // staging (ABI calls, autotuning)
     }
     if (!((mask >> HPGMX_F64) & 1u))

@@ -29,7 +29,8 @@ namespace hpgmx {
 // With ctrl, vector j of the output is scaled by ctrl[j].colscale[k] (the
 // unnormalised-basis scale of the column x was computed from).
 template <typename V, int K, int R>
-__global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, int clog2, int remap, const V *__restrict__ offv,
+__global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, i64 row0, i64 cnt, int clog2, int remap,
+                                                  const V *__restrict__ offv,
                                                   const int *__restrict__ offc,
                                                   const V *__restrict__ diag,
                                                   const typename VecT<V>::T *__restrict__ x,
@@ -41,8 +42,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, int clog2, int remap,
     const i64 N = gm.N;
     const i64 t = gtid_xcd(remap);
     i64 p = t / L;
-    if (p >= N) return;
-    if (remap == kRemapPlanes) p = plane_row(p, gm);
+    if (p >= cnt) return;
+    p = remap == kRemapPlanes ? plane_row(p, gm) : row0 + p;  // the plane order only over all rows
     const int g = (int)(t % L);
     const i64 o = p * K + g * R;
     const EllRow er = ell_row(p, N, clog2);
@@ -57,14 +58,67 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, int clog2, int remap,
     stp<T, R>(y + o, out);
 }
 
+// ---- SpMV after the last sweep of a V-cycle (see launch_spmv_split) ------------------------------
+template <typename T, typename V, int K, int R, int C, bool FWD, bool FUSED>
+__device__ __forceinline__ void bsplit_row_sum(const V *__restrict__ offv, const int *__restrict__ offc,
+                                               const T *x, const EllRow &er, const T *part, T (&acc)[R])
+{
+    constexpr unsigned E = zero_guess_mask(C, FWD), L = kAllSlots & ~E;
+    Pack<T, R> se;
+    if constexpr (FUSED) se = ldp<T, R>(part);
+    T sl[R];
+    ell_row_dot_b<T, V, K, R, L>(offv, offc, x, er, sl);
+    if constexpr (!FUSED) ell_row_dot_b<T, V, K, R, E>(offv, offc, x, er, se.v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = se.v[r] + sl[r];
+}
+
+// One colour block of the split rows (a launch per colour, as the
+// single-vector SpMV; compile-time slot masks).
+template <typename V, int K, int R, int C, bool FWD, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_bspmv_colour(i64 row0, i64 cnt, i64 N, int clog2, int remap,
+                                                         const V *__restrict__ offv,
+                                                         const int *__restrict__ offc,
+                                                         const V *__restrict__ diag,
+                                                         const typename VecT<V>::T *__restrict__ x,
+                                                         typename VecT<V>::T *__restrict__ y,
+                                                         const typename VecT<V>::T *__restrict__ part,
+                                                         const Ctrl *ctrl, int k)
+{
+    using T = typename VecT<V>::T;
+    constexpr int L = K / R;
+    const i64 t = gtid_xcd(remap);
+    const i64 q = t / L;
+    if (q >= cnt) return;
+    const int g = (int)(t % L);
+    const i64 p = row0 + q;
+    const i64 o = p * K + g * R;
+    const EllRow er = ell_row(p, N, clog2);
+    const Pack<T, R> xp = ldp<T, R>(x + o);
+    const T d = to_t<T>(ld_stream(diag + p));
+    T acc[R];
+    bsplit_row_sum<T, V, K, R, C, FWD, FUSED>(offv, offc, x + g * R, er, part + o, acc);
+    Pack<T, R> out;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        out.v[r] = spmv_row_value<T>(d, xp.v[r], acc[r], ctrl ? ctrl[g * R + r].colscale + k : nullptr);
+    stp<T, R>(y + o, out);
+}
+
 // ---- Gauss-Seidel, one colour (rows [row0, row0 + cnt)) ------------------------------------
-template <typename V, int K, int R, unsigned MASK>
+// WOUT as in k_gs (stencil_kernels.hip): the last sweep of a V-cycle's
+// level-0 post-smoothing also writes the SpMV rows of its last colour
+// (kWoutRow, right-hand side j scaled by ctrl[j].colscale[k]) and the
+// partial sums of the colours at sweep positions 2-6 (kWoutPart).
+constexpr int kBWoutNone = 0, kBWoutRow = 1, kBWoutPart = 2;
+template <typename V, int K, int R, unsigned MASK, int WOUT = kBWoutNone, unsigned EMASK = 0>
 __global__ __launch_bounds__(kBlock) void k_bgs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
                                                 const V *__restrict__ offv,
                                                 const int *__restrict__ offc,
                                                 const V *__restrict__ diag,
                                                 const typename VecT<V>::T *__restrict__ r,
-                                                typename VecT<V>::T *z)
+                                                typename VecT<V>::T *z,
+                                                typename VecT<V>::T *__restrict__ y, const Ctrl *ctrl, int k)
 {
     using T = typename VecT<V>::T;
     constexpr int L = K / R;
@@ -78,11 +132,27 @@ __global__ __launch_bounds__(kBlock) void k_bgs(i64 row0, i64 cnt, i64 N, int cl
     const Pack<T, R> rp = ldp<T, R>(r + o);
     const T dg = to_t<T>(ld_stream(diag + p));
     T acc[R];
-    ell_row_dot_b<T, V, K, R, MASK>(offv, offc, z + g * R, er, acc);
     Pack<T, R> out;
+    if constexpr (WOUT == kBWoutPart) {
+        Pack<T, R> pe;
+        ell_row_dot_b2<T, V, K, R, MASK, EMASK>(offv, offc, z + g * R, er, acc, pe.v);
 #pragma unroll
-    for (int i = 0; i < R; ++i) out.v[i] = (rp.v[i] - acc[i]) / dg;
-    stp<T, R>(z + o, out);
+        for (int i = 0; i < R; ++i) out.v[i] = (rp.v[i] - acc[i]) / dg;
+        stp<T, R>(z + o, out);
+        stp<T, R>(y + o, pe);
+    } else {
+        ell_row_dot_b<T, V, K, R, MASK>(offv, offc, z + g * R, er, acc);
+#pragma unroll
+        for (int i = 0; i < R; ++i) out.v[i] = (rp.v[i] - acc[i]) / dg;
+        stp<T, R>(z + o, out);
+        if constexpr (WOUT == kBWoutRow) {
+            Pack<T, R> w;
+#pragma unroll
+            for (int i = 0; i < R; ++i)
+                w.v[i] = spmv_row_value<T>(dg, out.v[i], acc[i], ctrl ? ctrl[g * R + i].colscale + k : nullptr);
+            stp<T, R>(y + o, w);
+        }
+    }
 }
 
 // ---- fused residual-restriction (eq. (6)) at the colour-4 rows ------------------------------
@@ -275,20 +345,85 @@ void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y,
             // and the time by 6 % (the slab order ran slower).
             const int order = A.order >= kRemapSlab ? plane_order(A) : tile_remap(A);
             hipLaunchKernelGGL((k_bspmv<V, KK, RR>), dim3(lanes_grid(A.g.N, KK, RR)), dim3(kBlock), 0, s,
-                               A.g, A.clog2, order, v, (const int *)A.col, d, (const T *)x, (T *)y, ctrl, k);
+                               A.g, (i64)0, A.g.N, A.clog2, order, v, (const int *)A.col, d, (const T *)x, (T *)y,
+                               ctrl, k);
         });
     });
     HPGMX_LAUNCH_CHECK();
 }
 
-template <typename V, int K, int R, unsigned MASK>
-static void bgs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z, hipStream_t s)
+template <typename V, int K, int R, int POS, bool FWD, bool FUSED>
+static void bspmv_colour_launch(const Matrix &A, const V *v, const V *d, const void *x, void *y, const void *part,
+                                hipStream_t s, const Ctrl *ctrl, int k)
+{
+    using T = typename VecT<V>::T;
+    constexpr int C = FWD ? POS : 7 - POS;
+    const i64 row0 = A.g.off[C], cnt = A.g.off[C + 1] - row0;
+    if (cnt == 0) return;
+    hipLaunchKernelGGL((k_bspmv_colour<V, K, R, C, FWD, FUSED>), dim3(lanes_grid(cnt, K, R)), dim3(kBlock), 0, s,
+                       row0, cnt, A.g.N, A.clog2, tile_remap(A), v, (const int *)A.col, d, (const T *)x, (T *)y,
+                       (const T *)part, ctrl, k);
+}
+
+void launch_bspmv_split(const Matrix &A, Prec p, int K, int R, const void *x, void *y, const void *part,
+                        bool forward, bool fused, hipStream_t s, const Ctrl *ctrl, int k)
+{
+    if (p != P32 && p != P64) throw std::runtime_error("launch_bspmv_split: FP32 and FP64 only");
+    with_values(A, p, [&](auto *v, auto *d) {
+        using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
+        using T = typename VecT<V>::T;
+        if constexpr (std::is_same<V, float>::value || std::is_same<V, double>::value) {
+            with_kr(K, R, [&](auto kc, auto rc) {
+                constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
+                // sweep positions 0 and 1 (and 7 when it is not fused): whole rows
+                auto rows = [&](int c0, int c1) {
+                    const i64 row0 = A.g.off[c0], cnt = A.g.off[c1] - row0;
+                    if (cnt == 0) return;
+                    hipLaunchKernelGGL((k_bspmv<V, KK, RR>), dim3(lanes_grid(cnt, KK, RR)), dim3(kBlock), 0, s,
+                                       A.g, row0, cnt, A.clog2, tile_remap(A), v, (const int *)A.col, d,
+                                       (const T *)x, (T *)y, ctrl, k);
+                };
+                if (forward) { rows(0, 2); if (!fused) rows(7, 8); }
+                else { rows(6, 8); if (!fused) rows(0, 1); }
+                auto split = [&](auto fwd, auto fus) {
+                    constexpr bool F = decltype(fwd)::value, U = decltype(fus)::value;
+                    bspmv_colour_launch<V, KK, RR, 2, F, U>(A, v, d, x, y, part, s, ctrl, k);
+                    bspmv_colour_launch<V, KK, RR, 3, F, U>(A, v, d, x, y, part, s, ctrl, k);
+                    bspmv_colour_launch<V, KK, RR, 4, F, U>(A, v, d, x, y, part, s, ctrl, k);
+                    bspmv_colour_launch<V, KK, RR, 5, F, U>(A, v, d, x, y, part, s, ctrl, k);
+                    bspmv_colour_launch<V, KK, RR, 6, F, U>(A, v, d, x, y, part, s, ctrl, k);
+                };
+                if (forward) {
+                    if (fused) split(std::true_type{}, std::true_type{});
+                    else split(std::true_type{}, std::false_type{});
+                } else {
+                    if (fused) split(std::false_type{}, std::true_type{});
+                    else split(std::false_type{}, std::false_type{});
+                }
+            });
+        }
+    });
+    HPGMX_LAUNCH_CHECK();
+}
+
+template <typename V, int K, int R, unsigned MASK, int WOUT = kBWoutNone, unsigned EMASK = 0>
+static void bgs_launch(const Matrix &A, const V *v, const V *d, int c, const void *r, void *z, hipStream_t s,
+                       BSpmvOut out = {})
 {
     using T = typename VecT<V>::T;
     const i64 row0 = A.g.off[c], cnt = A.g.off[c + 1] - A.g.off[c];
     if (cnt == 0) return;
-    hipLaunchKernelGGL((k_bgs<V, K, R, MASK>), dim3(lanes_grid(cnt, K, R)), dim3(kBlock), 0, s, row0, cnt,
-                       A.g.N, A.clog2, tile_remap(A), v, (const int *)A.col, d, (const T *)r, (T *)z);
+    void *y = WOUT == kBWoutPart ? out.part : out.y;
+    hipLaunchKernelGGL((k_bgs<V, K, R, MASK, WOUT, EMASK>), dim3(lanes_grid(cnt, K, R)), dim3(kBlock), 0, s, row0,
+                       cnt, A.g.N, A.clog2, tile_remap(A), v, (const int *)A.col, d, (const T *)r, (T *)z, (T *)y,
+                       out.ctrl, out.k);
+}
+
+template <typename V, int K, int R, int C, bool FWD>
+static void bgs_part_launch(const Matrix &A, const V *v, const V *d, const void *r, void *z, hipStream_t s,
+                            BSpmvOut out)
+{
+    bgs_launch<V, K, R, kAllSlots, kBWoutPart, zero_guess_mask(C, FWD)>(A, v, d, C, r, z, s, out);
 }
 
 #define HPGMX_BGS_CASE(C, FWD) \
@@ -296,9 +431,30 @@ static void bgs_launch(const Matrix &A, const V *v, const V *d, int c, const voi
 
 template <typename V, int K, int R>
 static void bgs_kr(const Matrix &A, const V *v, const V *d, int c, int mode, const void *r, void *z,
-                   hipStream_t s)
+                   hipStream_t s, BSpmvOut out)
 {
-    if (mode == kGsFull) {
+    constexpr bool kWide = std::is_same<V, float>::value || std::is_same<V, double>::value;
+    if (kWide && (out.y || out.part)) {
+        if (mode != kGsFull) throw std::runtime_error("the SpMV rows ride only on a full colour launch");
+        if constexpr (!kWide) return;
+        else if (out.y) {
+            bgs_launch<V, K, R, kAllSlots, kBWoutRow>(A, v, d, c, r, z, s, out);
+        } else {
+            switch (c + (out.forward ? 0 : 8)) {
+            case 2: bgs_part_launch<V, K, R, 2, true>(A, v, d, r, z, s, out); break;
+            case 3: bgs_part_launch<V, K, R, 3, true>(A, v, d, r, z, s, out); break;
+            case 4: bgs_part_launch<V, K, R, 4, true>(A, v, d, r, z, s, out); break;
+            case 5: bgs_part_launch<V, K, R, 5, true>(A, v, d, r, z, s, out); break;
+            case 6: bgs_part_launch<V, K, R, 6, true>(A, v, d, r, z, s, out); break;
+            case 8 + 1: bgs_part_launch<V, K, R, 1, false>(A, v, d, r, z, s, out); break;
+            case 8 + 2: bgs_part_launch<V, K, R, 2, false>(A, v, d, r, z, s, out); break;
+            case 8 + 3: bgs_part_launch<V, K, R, 3, false>(A, v, d, r, z, s, out); break;
+            case 8 + 4: bgs_part_launch<V, K, R, 4, false>(A, v, d, r, z, s, out); break;
+            case 8 + 5: bgs_part_launch<V, K, R, 5, false>(A, v, d, r, z, s, out); break;
+            default: throw std::runtime_error("partial SpMV sums: sweep positions 2-6 only");
+            }
+        }
+    } else if (mode == kGsFull) {
         bgs_launch<V, K, R, kAllSlots>(A, v, d, c, r, z, s);
     } else if (mode == kGsZeroForward) {
         switch (c) {
@@ -315,13 +471,18 @@ static void bgs_kr(const Matrix &A, const V *v, const V *d, int c, int mode, con
 #undef HPGMX_BGS_CASE
 
 void launch_bgs_colour(const Matrix &A, Prec p, int K, int R, int c, int mode, const void *r, void *z,
-                       hipStream_t s)
+                       hipStream_t s, BSpmvOut out)
 {
+    if ((out.y || out.part) && p != P32 && p != P64)
+        throw std::runtime_error("the batched SpMV rows ride on FP32 and FP64 sweeps only");
     with_values(A, p, [&](auto *v, auto *d) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
         with_kr(K, R, [&](auto kc, auto rc) {
             constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
-            bgs_kr<V, KK, RR>(A, v, d, c, mode, r, z, s);
+            if constexpr (std::is_same<V, float>::value || std::is_same<V, double>::value)
+                bgs_kr<V, KK, RR>(A, v, d, c, mode, r, z, s, out);
+            else
+                bgs_kr<V, KK, RR>(A, v, d, c, mode, r, z, s, BSpmvOut{});
         });
     });
     HPGMX_LAUNCH_CHECK();

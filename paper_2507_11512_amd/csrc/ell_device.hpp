@@ -462,4 +462,47 @@ __device__ __forceinline__ void ell_row_dot_b(const V *__restrict__ offv, const 
     }
 }
 
+// As ell_row_dot_b over MASK, with accE[r] the sum over the slots of EMASK
+// alone (equal to ell_row_dot_b over EMASK bit for bit).
+template <typename T, typename V, int K, int R, unsigned MASK, unsigned EMASK>
+__device__ __forceinline__ void ell_row_dot_b2(const V *__restrict__ offv, const int *__restrict__ offc,
+                                               const T *x, const EllRow &er, T (&acc)[R], T (&accE)[R])
+{
+    V a[kSlots];
+    int ci[kSlots];
+#pragma unroll
+    for (int s = 0; s < kSlots; ++s) {
+        if (MASK & (1u << s)) {
+            const i64 e = er.base + (i64)s * er.stride;
+            a[s] = ld_stream(offv + e);
+            ci[s] = ld_stream(offc + e);
+        }
+    }
+    sched_fence();
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = accE[r] = (T)0;
+    constexpr int G = gather_group<T, R>();
+#pragma unroll
+    for (int s0 = 0; s0 < kSlots; s0 += G) {
+        Pack<T, R> xv[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int s = s0 + u;
+            if (s < kSlots && (MASK & (1u << s))) xv[u] = ldp<T, R>(x + (i64)ci[s] * K);
+        }
+        sched_fence();
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int s = s0 + u;
+            if (s < kSlots && (MASK & (1u << s))) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    acc[r] = madd(to_t<T>(a[s]), xv[u].v[r], acc[r]);
+                    if (EMASK & (1u << s)) accE[r] = madd(to_t<T>(a[s]), xv[u].v[r], accE[r]);
+                }
+            }
+        }
+    }
+}
+
 }  // namespace hpgmx

@@ -379,8 +379,22 @@ bool batch_shape_ok(int K, int R);
 // Y = A X; with ctrl, vector j is scaled by ctrl[j].colscale[k].
 void launch_bspmv(const Matrix &A, Prec p, int K, int R, const void *x, void *y, hipStream_t s,
                   const Ctrl *ctrl = nullptr, int k = 0);
+// What a batched colour launch of the last level-0 sweep writes for the
+// batched SpMV (as SpmvOut, K interleaved right-hand sides): with y, the
+// SpMV rows of its colour, right-hand side j scaled by ctrl[j].colscale[k];
+// with part, the partial sums over the slots to colours relaxed before it.
+struct BSpmvOut {
+    void *y = nullptr;
+    const Ctrl *ctrl = nullptr;
+    int k = 0;
+    void *part = nullptr;
+    bool forward = true;
+};
 void launch_bgs_colour(const Matrix &A, Prec p, int K, int R, int c, int mode, const void *r,
-                       void *z, hipStream_t s);
+                       void *z, hipStream_t s, BSpmvOut out = {});
+// launch_spmv_split for K interleaved right-hand sides (the batched solver).
+void launch_bspmv_split(const Matrix &A, Prec p, int K, int R, const void *x, void *y, const void *part,
+                        bool forward, bool fused, hipStream_t s, const Ctrl *ctrl, int k);
 void launch_brestrict(const Matrix &Af, const Geom &gc, Prec p, int K, int R, const void *r,
                       const void *z, void *rc, hipStream_t s);
 void launch_brestrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, int K, int R, bool forward,

@@ -320,11 +320,11 @@ void launch_spmv(const Matrix &A, Prec p, const void *x, void *y, hipStream_t s,
 // order, and (A z)_p = a_pp z_p + (sum_E + sum_L).  FUSED: sum_E comes from
 // part (written by the colour's own launch, k_gs with kWoutPart) and only
 // the L slots are read here -- 20, 18, 8, 6 and 2 of 26 -- and the rows of
-// the sweep's last colour were written by its launch, so they are not in
-// the range; otherwise both sums are formed here from z, and every row is.
-// The rows of the first colour (no E slots) are k_spmv rows.  The two forms
-// give the same bits.  (Position 1 would save 2 slots for the 4 bytes of a
-// partial sum written and read again: not worth a launch variant.)
+// the sweep's last colour were written by its launch, so they are left out;
+// otherwise both sums are formed here from z, and every row is.  The rows
+// of the first two colours are whole k_spmv rows (position 1 would save 2
+// slots for the 4 bytes of a partial sum written and read again).  The two
+// forms give the same bits.
 template <typename T, typename V, typename S, int C, bool FWD, bool FUSED, bool C16>
 __device__ __forceinline__ T split_row_sum(const V *__restrict__ offv, const void *__restrict__ offc,
                                            const S *x, const EllRow &er, i64 p, const int *Dc, i64 N,
@@ -338,71 +338,89 @@ __device__ __forceinline__ T split_row_sum(const V *__restrict__ offv, const voi
     return se + sl;
 }
 
-template <typename V, typename S, bool C16, bool FWD, bool FUSED>
-__global__ __launch_bounds__(kBlock) void k_spmv_split(Geom g, i64 row0, i64 cnt, int nb, int clog2, int remap,
-                                                       const V *__restrict__ offv,
-                                                       const void *__restrict__ offc,
-                                                       const int *__restrict__ cmap,
-                                                       const V *__restrict__ diag,
-                                                       const S *__restrict__ x,
-                                                       typename VecT<V>::T *__restrict__ y,
-                                                       const typename VecT<V>::T *__restrict__ part,
-                                                       const double *scale)
+// One colour block of the split rows (compile-time slot masks; a launch per
+// colour keeps the short rows of the late colours from running at the
+// occupancy the whole rows need).
+template <typename V, typename S, bool C16, int C, bool FWD, bool FUSED>
+__global__ __launch_bounds__(kBlock) void k_spmv_colour(i64 row0, i64 cnt, i64 N, int clog2, int remap,
+                                                        const V *__restrict__ offv,
+                                                        const void *__restrict__ offc,
+                                                        const int *__restrict__ cmapc,
+                                                        const V *__restrict__ diag,
+                                                        const S *__restrict__ x,
+                                                        typename VecT<V>::T *__restrict__ y,
+                                                        const typename VecT<V>::T *__restrict__ part,
+                                                        const double *scale)
 {
     using T = typename VecT<V>::T;
-    __shared__ int cm[C16 ? kColMapSize : 1];
-    if constexpr (C16) stage_colmap(cm, cmap);
-    const i64 N = g.N;
-    i64 p = gtid_xcd(remap, nb);
-    if (p >= cnt) return;
-    p += row0;
+    const i64 t = gtid_xcd(remap);
+    if (t >= cnt) return;
+    const i64 p = row0 + t;
     const EllRow er = ell_row(p, N, clog2);
-    const int c = row_colour(g, p);
-    const int *Dc = C16 ? cm + c * kSlots : nullptr;
     const T d = to_t<T>(ld_stream(diag + p)), xp = to_t<T>(x[p]);
-    T acc;
-    switch (FWD ? c : 7 - c) {  // position of the colour in the sweep
-    case 2: acc = split_row_sum<T, V, S, FWD ? 2 : 5, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
-    case 3: acc = split_row_sum<T, V, S, FWD ? 3 : 4, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
-    case 4: acc = split_row_sum<T, V, S, FWD ? 4 : 3, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
-    case 5: acc = split_row_sum<T, V, S, FWD ? 5 : 2, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
-    case 6: acc = split_row_sum<T, V, S, FWD ? 6 : 1, FWD, FUSED, C16>(offv, offc, x, er, p, Dc, N, part); break;
-    default: acc = ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N); break;
-    }
-    y[p] = spmv_row_value<T>(d, xp, acc, scale);
+    y[p] = spmv_row_value<T>(d, xp, split_row_sum<T, V, S, C, FWD, FUSED, C16>(offv, offc, x, er, p, cmapc, N, part),
+                             scale);
+}
+
+template <typename V, typename S, bool C16, int POS, bool FWD, bool FUSED>
+static void spmv_colour_launch(const Matrix &A, const V *v, const V *d, const void *x, void *y, const void *part,
+                               const double *scale, hipStream_t s)
+{
+    using T = typename VecT<V>::T;
+    constexpr int C = FWD ? POS : 7 - POS;
+    const i64 row0 = A.g.off[C], cnt = A.g.off[C + 1] - row0;
+    if (cnt == 0) return;
+    hipLaunchKernelGGL((k_spmv_colour<V, S, C16, C, FWD, FUSED>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, row0, cnt,
+                       A.g.N, A.clog2, tile_remap(A), v, (const void *)A.col, C16 ? A.cmap + C * kSlots : nullptr, d,
+                       (const S *)x, (T *)y, (const T *)part, scale);
+}
+
+// Whole rows of the colours in [c0, c1) (consecutive blocks) with k_spmv.
+template <typename V, typename S, bool C16>
+static void spmv_rows_launch(const Matrix &A, const V *v, const V *d, int c0, int c1, const void *x, void *y,
+                             const double *scale, hipStream_t s)
+{
+    using T = typename VecT<V>::T;
+    const i64 row0 = A.g.off[c0], cnt = A.g.off[c1] - row0;
+    if (cnt == 0) return;
+    const int nb = c1 - c0;
+    int order = spmv_order(A, std::is_same<V, double>::value, nb);
+    if (order == kRemapPlanes) order = 1;
+    hipLaunchKernelGGL((k_spmv<V, S, C16>), dim3(grid_for(cnt)), dim3(kBlock), 0, s, A.g, row0, cnt, nb, A.clog2,
+                       order, v, (const void *)A.col, A.cmap, d, (const S *)x, (T *)y, scale);
 }
 
 void launch_spmv_split(const Matrix &A, Prec p, const void *x, void *y, const void *part, bool forward,
                        bool fused, hipStream_t s, const Ctrl *ctrl, int k)
 {
     const double *scale = spmv_scale(p, ctrl, k);
-    i64 row0 = 0, cnt = A.g.N;
-    int nb = 8;
-    if (fused) {
-        nb = 7;
-        if (forward) cnt = A.g.off[7];
-        else { row0 = A.g.off[1]; cnt = A.g.N - row0; }
-    }
-    if (cnt == 0) return;
     with_matrix(A, p, [&](auto *v, auto *d, auto sv) {
         using V = std::remove_const_t<std::remove_pointer_t<decltype(v)>>;
         using S = decltype(sv);
-        using T = typename VecT<V>::T;
-        int order = spmv_order(A, std::is_same<V, double>::value, nb);
-        if (order == kRemapPlanes) order = 1;
         with_cols(A, [&](auto c16) {
             constexpr bool C = decltype(c16)::value;
-            auto go = [&](auto kern) {
-                hipLaunchKernelGGL(kern, dim3(grid_for(cnt)), dim3(kBlock), 0, s, A.g, row0, cnt, nb, A.clog2, order,
-                                   (const V *)v, (const void *)A.col, A.cmap, (const V *)d, (const S *)x, (T *)y,
-                                   (const T *)part, scale);
+            // sweep positions 0 and 1 (and 7 when it is not fused): whole rows
+            if (forward) {
+                spmv_rows_launch<V, S, C>(A, v, d, 0, 2, x, y, scale, s);
+                if (!fused) spmv_rows_launch<V, S, C>(A, v, d, 7, 8, x, y, scale, s);
+            } else {
+                spmv_rows_launch<V, S, C>(A, v, d, 6, 8, x, y, scale, s);
+                if (!fused) spmv_rows_launch<V, S, C>(A, v, d, 0, 1, x, y, scale, s);
+            }
+            auto split = [&](auto fwd, auto fus) {
+                constexpr bool F = decltype(fwd)::value, U = decltype(fus)::value;
+                spmv_colour_launch<V, S, C, 2, F, U>(A, v, d, x, y, part, scale, s);
+                spmv_colour_launch<V, S, C, 3, F, U>(A, v, d, x, y, part, scale, s);
+                spmv_colour_launch<V, S, C, 4, F, U>(A, v, d, x, y, part, scale, s);
+                spmv_colour_launch<V, S, C, 5, F, U>(A, v, d, x, y, part, scale, s);
+                spmv_colour_launch<V, S, C, 6, F, U>(A, v, d, x, y, part, scale, s);
             };
             if (forward) {
-                if (fused) go(k_spmv_split<V, S, C, true, true>);
-                else go(k_spmv_split<V, S, C, true, false>);
+                if (fused) split(std::true_type{}, std::true_type{});
+                else split(std::true_type{}, std::false_type{});
             } else {
-                if (fused) go(k_spmv_split<V, S, C, false, true>);
-                else go(k_spmv_split<V, S, C, false, false>);
+                if (fused) split(std::false_type{}, std::true_type{});
+                else split(std::false_type{}, std::false_type{});
             }
         });
     });
@@ -428,7 +446,7 @@ void launch_spmv_split(const Matrix &A, Prec p, const void *x, void *y, const vo
 //    same bits as the SpMV kernels);
 //  * kWoutPart, the colours at sweep positions 2-6: the launch writes part_p, the
 //    sum over the slots EMASK of the neighbours relaxed before the colour
-//    (final from then on); the SpMV adds the remaining slots (k_spmv_split).
+//    (final from then on); the SpMV adds the remaining slots (launch_spmv_split).
 constexpr int kWoutNone = 0, kWoutRow = 1, kWoutPart = 2;
 template <typename V, typename S, unsigned MASK, bool C16, int WOUT = kWoutNone, unsigned EMASK = 0>
 __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clog2, int remap,
