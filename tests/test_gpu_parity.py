@@ -661,6 +661,32 @@ def test_spmv_in_last_sweep(hp, sweep, precision, cols):
         assert np.linalg.norm(out[m][0] - 1.0) <= 1e-8 * np.sqrt(out[m][0].size), m
 
 
+@pytest.mark.parametrize("dims,levels,pre,post", [((24, 20, 14), 2, 1, 1),   # a non-cubic grid
+                                                  ((32, 32, 32), 1, 1, 1),    # one level: no post-sweep
+                                                  ((32, 32, 32), 3, 1, 2),    # two post-sweeps
+                                                  ((32, 32, 32), 3, 0, 1),    # no pre-sweep
+                                                  ((32, 32, 32), 3, 1, 0)])   # no post-sweep: plain SpMV
+def test_spmv_in_last_sweep_configurations(hp, dims, levels, pre, post):
+    """The shared SpMV across multigrid shapes: where the V-cycle ends with a
+    level-0 post-sweep the split forms (2, 3) agree bit for bit and with one
+    SpMV (0) to rounding; where it does not, every mode is the plain SpMV."""
+    b = oracle.spmv(dims, inputs.ones(dims))
+    out = {}
+    for mode in (0, 2, 3):
+        P = hp.Problem(dims, beta=0.5, levels=levels, pre=pre, post=post, sweep="forward",
+                       layout={"spmv_in_sweep": mode})
+        x, st = P.solve(dev(b, 0), tol=1e-9, max_iters=400, precision="mxp")
+        P.close()
+        res = np.linalg.norm(b - oracle.spmv(dims, host(x))) / np.linalg.norm(b)
+        out[mode] = (host(x), st.iters, st.converged, res)
+    assert np.array_equal(out[2][0], out[3][0]) and out[2][1] == out[3][1]
+    if levels < 2 or post < 1:
+        assert np.array_equal(out[0][0], out[2][0])
+    for m in (0, 2):
+        assert out[m][2] and out[m][3] <= 1e-9, m
+    assert abs(out[0][1] - out[2][1]) <= 2
+
+
 def test_layout_errors(hp):
     h = hp.setup_problem(16, 16, 16, beta=0.5)
     try:
