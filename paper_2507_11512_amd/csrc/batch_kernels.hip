@@ -43,7 +43,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, i64 row0, i64 cnt, in
     const i64 t = gtid_xcd(remap);
     i64 p = t / L;
     if (p >= cnt) return;
-    p = remap == kRemapPlanes ? plane_row(p, gm) : row0 + p;  // the plane order only over all rows
+    // the plane order over all rows, the pair order over the rows of a colour pair
+    p = remap == kRemapPlanes ? plane_row(p, gm) : remap == kRemapPlanePair ? plane_pair_row(p, gm, row0) : row0 + p;
     const int g = (int)(t % L);
     const i64 o = p * K + g * R;
     const EllRow er = ell_row(p, N, clog2);
@@ -375,12 +376,16 @@ void launch_bspmv_split(const Matrix &A, Prec p, int K, int R, const void *x, vo
         if constexpr (std::is_same<V, float>::value || std::is_same<V, double>::value) {
             with_kr(K, R, [&](auto kc, auto rc) {
                 constexpr int KK = decltype(kc)::value, RR = decltype(rc)::value;
-                // sweep positions 0 and 1 (and 7 when it is not fused): whole rows
+                // sweep positions 0 and 1 (and 7 when it is not fused): whole rows;
+                // the colour pair in the plane-interleaved order where it applies
+                const int pair_order = A.order >= kRemapSlab && plane_order(A) == kRemapPlanes
+                                           ? kRemapPlanePair : tile_remap(A);
                 auto rows = [&](int c0, int c1) {
                     const i64 row0 = A.g.off[c0], cnt = A.g.off[c1] - row0;
                     if (cnt == 0) return;
+                    const int order = c1 - c0 == 2 ? pair_order : tile_remap(A);
                     hipLaunchKernelGGL((k_bspmv<V, KK, RR>), dim3(lanes_grid(cnt, KK, RR)), dim3(kBlock), 0, s,
-                                       A.g, row0, cnt, A.clog2, tile_remap(A), v, (const int *)A.col, d,
+                                       A.g, row0, cnt, A.clog2, order, v, (const int *)A.col, d,
                                        (const T *)x, (T *)y, ctrl, k);
                 };
                 if (forward) { rows(0, 2); if (!fused) rows(7, 8); }

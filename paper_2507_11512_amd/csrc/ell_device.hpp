@@ -307,6 +307,24 @@ __device__ __forceinline__ i64 plane_row(i64 v, const Geom &g)
     return g.off[c] + (i64)kk * P + local;
 }
 
+// Plane-interleaved order of a launch over two consecutive, equal colour
+// blocks c0 and c0 + 1 starting at row0 (remap == kRemapPlanePair): work
+// item v is the v-th row of a sequence that runs over the lattice planes kk
+// and, within one kk, over colour c0 then c0 + 1.  The pairs this is used
+// for, (0, 1) and (6, 7), differ in the x parity only, so both colours of
+// one kk lie on the same grid plane and gather from the same three grid
+// planes: XCD x owns a slab of planes and fetches those vector entries once
+// for both colours, instead of once per colour when each colour block is a
+// separate range.  Needs equal colour blocks and rows below 2^32, which the
+// host checks.
+__device__ __forceinline__ i64 plane_pair_row(i64 v, const Geom &g, i64 row0)
+{
+    const unsigned P = (unsigned)g.bx[0] * (unsigned)g.by[0];
+    const unsigned q = (unsigned)v / P, local = (unsigned)v - q * P;
+    const i64 B = g.off[1] - g.off[0];
+    return row0 + (i64)(q & 1u) * B + (i64)(q >> 1) * P + local;
+}
+
 // Row loop of a grid-stride launch: the N rows are cut into 256-row tiles,
 // XCD x owns tiles [T x / 8, T (x+1) / 8) and its workgroups stride through
 // them.  Without remap: the plain grid-stride loop.
@@ -348,7 +366,8 @@ int plane_order(const Matrix &A);
 __device__ __forceinline__ i64 gtid() { return (i64)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ i64 gtid_xcd(int remap, int nb = kXcds)
 {
-    if (remap == kRemapPlanes) remap = 1;  // the row permutation is applied by the kernel (plane_row)
+    // the row permutation of these two is applied by the kernel (plane_row, plane_pair_row)
+    if (remap == kRemapPlanes || remap == kRemapPlanePair) remap = 1;
     i64 t = xcd_tile(blockIdx.x, gridDim.x, remap);
     if (remap == kRemapSlab) t = slab_perm(t, gridDim.x, nb);
     return t * blockDim.x + threadIdx.x;

@@ -47,9 +47,12 @@ constexpr int kDefaultEllChunkLog2 = 8;  // ELL chunking default (see ell_row)
 constexpr int kDefaultLdqPad = 1088;
 // Tile orders of the row-per-lane launches: 0 the launch order, 1 each XCD
 // owns one contiguous range of tiles; for the full-grid SpMV also
-// kRemapSlab (see slab_perm) or kRemapPlanes (see plane_row).
+// kRemapSlab (see slab_perm) or kRemapPlanes (see plane_row); for a launch
+// over the whole rows of a colour pair, kRemapPlanePair (see
+// plane_pair_row).
 constexpr int kRemapSlab = 2;
 constexpr int kRemapPlanes = 3;
+constexpr int kRemapPlanePair = 4;
 constexpr long long kDefaultPairRows = 1 << 17;
 
 // Data layout and tile order of a handle.  The defaults are the tuned
