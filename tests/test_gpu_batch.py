@@ -337,9 +337,9 @@ def test_batched_rows_match_single_solver(hp):
         assert np.linalg.norm(host(X[j]) - host(x)) <= 1e-6 * np.linalg.norm(host(x))
 
 
-@pytest.mark.parametrize("dims,sweep", [((32, 32, 32), "forward"), ((24, 20, 16), "forward"),
-                                        ((24, 20, 16), "backward"), ((18, 14, 11), "forward")])
-def test_solve_batched_tile_orders_bit_identical(hp, dims, sweep):
+@pytest.mark.parametrize("dims,levels,sweep", [((32, 32, 32), 3, "forward"), ((24, 20, 16), 3, "forward"),
+                                               ((24, 20, 16), 3, "backward"), ((12, 10, 9), 1, "forward")])
+def test_solve_batched_tile_orders_bit_identical(hp, dims, levels, sweep):
     """Every tile order of the batched launches (the plane order of the
     full-grid SpMV and the plane-pair order of the SpMV over the colour pair
     (0, 1) or (6, 7) included; an odd extent falls back to the
@@ -349,7 +349,7 @@ def test_solve_batched_tile_orders_bit_identical(hp, dims, sweep):
     _, B = _batch_rhs(dims, nrhs)
     ref = None
     for order in (-1, 0, 1, 3):
-        P = hp.Problem(dims, beta=0.5, levels=3, sweep=sweep, layout={"tile_order": order})
+        P = hp.Problem(dims, beta=0.5, levels=levels, sweep=sweep, layout={"tile_order": order})
         X, stats = P.solve_batched(dev(B, 0), precision="mxp")
         P.close()
         assert all(s.converged for s in stats)
