@@ -185,7 +185,10 @@ hpgmx_status hpgmx_set_column_format(hpgmx_handle h, int format);
  *                  measured fastest for each full-grid SpMV: the slab order
  *                  (each XCD takes one eighth of every colour block) for the
  *                  FP32 and 16-bit SpMV, the plane order for the batched
- *                  SpMV, the XCD-contiguous order for the FP64 SpMV.
+ *                  SpMV, the XCD-contiguous order for the FP64 SpMV.  With
+ *                  2 and 3 the batched SpMV over the whole rows of the
+ *                  colour pair (0, 1) or (6, 7) walks each XCD's slab plane
+ *                  by plane through both colours (the plane-pair order).
  *   ell_chunk_log2 rows per ELL chunk as a power of two, 0..16 (0 =
  *                  slot-major over the whole level; default 8).
  *   ldq_pad        elements added between Krylov basis columns, even,
