@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(Geom gm, i64 row0, i64 cnt, in
 #pragma unroll
     for (int r = 0; r < R; ++r)
         out.v[r] = spmv_row_value<T>(d, xp.v[r], acc[r], ctrl ? ctrl[g * R + r].colscale + k : nullptr);
-    stp<T, R>(y + o, out);
+    stp_stream<T, R>(y + o, out);
 }
 
 // ---- SpMV after the last sweep of a V-cycle (see launch_spmv_split) ------------------------------
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmv_colour(i64 row0, i64 cnt, i64 
 #pragma unroll
     for (int r = 0; r < R; ++r)
         out.v[r] = spmv_row_value<T>(d, xp.v[r], acc[r], ctrl ? ctrl[g * R + r].colscale + k : nullptr);
-    stp<T, R>(y + o, out);
+    stp_stream<T, R>(y + o, out);
 }
 
 // ---- Gauss-Seidel, one colour (rows [row0, row0 + cnt)) ------------------------------------
@@ -139,8 +139,8 @@ __global__ __launch_bounds__(kBlock) void k_bgs(i64 row0, i64 cnt, i64 N, int cl
         ell_row_dot_b2<T, V, K, R, MASK, EMASK>(offv, offc, z + g * R, er, acc, pe.v);
 #pragma unroll
         for (int i = 0; i < R; ++i) out.v[i] = (rp.v[i] - acc[i]) / dg;
-        stp<T, R>(z + o, out);
-        stp<T, R>(y + o, pe);
+        stp<T, R>(z + o, out);  // plain: re-read by the next colour passes (see st_stream)
+        stp_stream<T, R>(y + o, pe);
     } else {
         ell_row_dot_b<T, V, K, R, MASK>(offv, offc, z + g * R, er, acc);
 #pragma unroll
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_bgs(i64 row0, i64 cnt, i64 N, int cl
 #pragma unroll
             for (int i = 0; i < R; ++i)
                 w.v[i] = spmv_row_value<T>(dg, out.v[i], acc[i], ctrl ? ctrl[g * R + i].colscale + k : nullptr);
-            stp<T, R>(y + o, w);
+            stp_stream<T, R>(y + o, w);
         }
     }
 }
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kBlock) void k_brestrict(Geom gf, Geom gc, int clog
         const T dz = d * zp.v[i];
         out.v[i] = rp.v[i] - (dz + acc[i]);
     }
-    stp<T, R>(rc + to_internal(gc, I, J, Kc) * K + g * R, out);
+    stp_stream<T, R>(rc + to_internal(gc, I, J, Kc) * K + g * R, out);
 }
 
 // ---- the fused restriction right after a single sweep from zero (see
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_brestrict_after_sweep(Geom gf, Geom 
     Pack<T, R> out;
 #pragma unroll
     for (int i = 0; i < R; ++i) out.v[i] = -acc[i];
-    stp<T, R>(rc + to_internal(gc, I, J, Kc) * K + g * R, out);
+    stp_stream<T, R>(rc + to_internal(gc, I, J, Kc) * K + g * R, out);
 }
 
 // ---- prolongation-correction z += P zc (one lane per element) -------------------------------
@@ -227,7 +227,8 @@ __global__ __launch_bounds__(kBlock) void k_bprolong(Geom gf, Geom gc, const T *
     if (q >= gc.N) return;
     const int j = (int)(e % K);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), Kc = (int)(q / ((i64)gc.nx * gc.ny));
-    z[(gf.off[4] + q) * K + j] += zc[to_internal(gc, I, J, Kc) * K + j];
+    const i64 o = (gf.off[4] + q) * K + j;
+    __builtin_nontemporal_store(z[o] + zc[to_internal(gc, I, J, Kc) * K + j], z + o);
 }
 
 // ---- FP64 outer residual r = b - A x ---------------------------------------------------------
@@ -259,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void k_bresid64(i64 N, int clog2, int remap
     for (int i = 0; i < R; ++i) {
         out.v[i] = bp.v[i] - spmv_row_value<double>(d, xp.v[i], acc[i], nullptr);
     }
-    stp<double, R>(r + o, out);
+    stp_stream<double, R>(r + o, out);
 }
 
 // ---- [nrhs][N] natural order <-> [N][K] colour-blocked --------------------------------------

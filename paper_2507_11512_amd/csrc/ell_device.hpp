@@ -32,6 +32,25 @@ template <> __device__ __forceinline__ bf16 ld_stream<bf16>(const bf16 *p)
     return __ushort_as_bfloat16(__builtin_nontemporal_load(reinterpret_cast<const unsigned short *>(p)));
 }
 
+// Results that a later kernel reads are written with nontemporal stores.  On
+// MI355X a pass that streams data written just before with plain stores runs
+// far below the streaming rate: a 4 GB read pass (31 Krylov columns) that
+// includes a 131 MB vector written by the preceding kernel took 715 us after
+// plain stores and 588 us after nontemporal ones, which cost the writing
+// kernel 3 us.  Measured on whole solves (bit-identical): the 320^3 mixed-
+// precision solve 1305 -> 1288 ms, FP64 2331 -> 2260 ms, the 192^3 x 8 batch
+// 1106 -> 1081 ms.  The one exception is the batched smoother's z, which the
+// next colour passes re-read: there plain stores measured faster.
+template <typename S> __device__ __forceinline__ void st_stream(S *p, S v) { __builtin_nontemporal_store(v, p); }
+template <> __device__ __forceinline__ void st_stream<__half>(__half *p, __half v)
+{
+    __builtin_nontemporal_store(__half_as_ushort(v), reinterpret_cast<unsigned short *>(p));
+}
+template <> __device__ __forceinline__ void st_stream<bf16>(bf16 *p, bf16 v)
+{
+    __builtin_nontemporal_store(__bfloat16_as_ushort(v), reinterpret_cast<unsigned short *>(p));
+}
+
 template <typename T, typename V> __device__ __forceinline__ T to_t(V v) { return (T)v; }
 template <> __device__ __forceinline__ float to_t<float, __half>(__half v) { return __half2float(v); }
 template <> __device__ __forceinline__ float to_t<float, bf16>(bf16 v) { return __bfloat162float(v); }
@@ -429,6 +448,20 @@ template <typename T, int R> __device__ __forceinline__ Pack<T, R> ldp(const T *
 template <typename T, int R> __device__ __forceinline__ void stp(T *p, const Pack<T, R> &v)
 {
     *reinterpret_cast<Pack<T, R> *>(p) = v;
+}
+// As stp with a nontemporal store (results that a later kernel reads, see
+// st_stream).
+template <typename T, int R> __device__ __forceinline__ void stp_stream(T *p, const Pack<T, R> &v)
+{
+    if constexpr (R == 1) {
+        __builtin_nontemporal_store(v.v[0], p);
+    } else {
+        typedef T vt __attribute__((ext_vector_type(R)));
+        vt x;
+#pragma unroll
+        for (int r = 0; r < R; ++r) x[r] = v.v[r];
+        __builtin_nontemporal_store(x, reinterpret_cast<vt *>(p));
+    }
 }
 
 // Gathered neighbour values in flight per lane: about 256 bytes, so that a

@@ -247,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_cgs_norm(i64 M, const T *__restrict_
 #pragma unroll
             for (int j = 0; j < KB; ++j) v -= cj[j * K] * (double)q[j];
             const T vt = (T)v;
-            w[e] = vt;
+            __builtin_nontemporal_store(vt, w + e);
             acc[0] += (double)vt * (double)vt;
         }
         store_partials_g<1, K, 1>(acc, 1, partials);

@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_resid64(Geom g, int clog2, int remap
         const double rv = bp - spmv_row_value<double>(ld_stream(diag + p), x[p],
                                                       ell_row_dot<double, double, kAllSlots, C16>(offv, offc, x, er, p, Dc, N),
                                                       nullptr);
-        r[p] = rv;
+        __builtin_nontemporal_store(rv, r + p);
         acc[0] += rv * rv;
     }
     store_partials_g<1, 1, 1>(acc, 1, partials);
@@ -264,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_cast(i64 M, const double *__restrict
 {
     const double s = ctrl[rhs_of_thread<K>()].inv_rho;
     const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (e < M) q[e] = (T)(r[e] * s);
+    if (e < M) __builtin_nontemporal_store((T)(r[e] * s), q + e);
 }
 
 // ---- y = H(0:kk,0:kk)^{-1} t(0:kk) by back substitution (FP64) ----
@@ -306,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_gemv(i64 M, const T *__restrict__ Q,
     double v = 0.0;
 #pragma unroll 8
     for (int j = 0; j < kk; ++j) v += cj[j * K] * (double)ld_stream(Q + (i64)j * ldq + e);
-    u[e] = (T)v;
+    __builtin_nontemporal_store((T)v, u + e);
 }
 
 // ---- x += z with the sum in FP64 (Alg. 3: the update must be double) ----
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kBlock) void k_update(i64 M, const T *__restrict__ 
     const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
     if (e >= M) return;
     const double v = widen(z[e]);
-    x[e] += inv ? v * *inv : v;
+    __builtin_nontemporal_store(x[e] + (inv ? v * *inv : v), x + e);
 }
 
 // ---- the V-cycle input of the 16-bit hierarchy -----------------------------------------------

@@ -265,7 +265,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv(Geom g, i64 row0, i64 cnt, int 
     const EllRow er = ell_row(p, N, clog2);
     const T d = to_t<T>(ld_stream(diag + p)), xp = to_t<T>(x[p]);
     const int *Dc = C16 ? cm + row_colour(g, p) * kSlots : nullptr;
-    y[p] = spmv_row_value<T>(d, xp, ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N), scale);
+    const T acc = ell_row_dot<T, V, kAllSlots, C16>(offv, offc, x, er, p, Dc, N);
+    __builtin_nontemporal_store(spmv_row_value<T>(d, xp, acc, scale), y + p);
 }
 
 // Order of the single-vector SpMV.  With the default (kRemapSlab) the FP32
@@ -358,8 +359,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_colour(i64 row0, i64 cnt, i64 N
     const i64 p = row0 + t;
     const EllRow er = ell_row(p, N, clog2);
     const T d = to_t<T>(ld_stream(diag + p)), xp = to_t<T>(x[p]);
-    y[p] = spmv_row_value<T>(d, xp, split_row_sum<T, V, S, C, FWD, FUSED, C16>(offv, offc, x, er, p, cmapc, N, part),
-                             scale);
+    const T acc = split_row_sum<T, V, S, C, FWD, FUSED, C16>(offv, offc, x, er, p, cmapc, N, part);
+    __builtin_nontemporal_store(spmv_row_value<T>(d, xp, acc, scale), y + p);
 }
 
 template <typename V, typename S, bool C16, int POS, bool FWD, bool FUSED>
@@ -466,13 +467,14 @@ __global__ __launch_bounds__(kBlock) void k_gs(i64 row0, i64 cnt, i64 N, int clo
     if constexpr (WOUT == kWoutPart) {
         T accE;
         const T acc = ell_row_dot2<T, V, MASK, EMASK, C16>(offv, offc, z, er, p, cmapc, N, accE);
-        z[p] = from_t<S>((rp - acc) / dg);
-        w[p] = accE;
+        st_stream(z + p, from_t<S>((rp - acc) / dg));
+        __builtin_nontemporal_store(accE, w + p);
     } else {
         const T acc = ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmapc, N);
         const S zp = from_t<S>((rp - acc) / dg);
-        z[p] = zp;
-        if constexpr (WOUT == kWoutRow) w[p] = spmv_row_value<T>(dg, to_t<T>(zp), acc, scale);
+        st_stream(z + p, zp);
+        if constexpr (WOUT == kWoutRow)
+            __builtin_nontemporal_store(spmv_row_value<T>(dg, to_t<T>(zp), acc, scale), w + p);
     }
 }
 
@@ -584,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair_zero(i64 rowa, i64 rowb, i64
         const EllRow er = ell_row(p, N, clog2);
         const T rp = to_t<T>(r[p]);
         const T dg = to_t<T>(ld_stream(diag + p));
-        z[p] = from_t<S>((rp - ell_row_dot<T, V, MA, C16>(offv, offc, z, er, p, cmapa, N)) / dg);
+        st_stream(z + p, from_t<S>((rp - ell_row_dot<T, V, MA, C16>(offv, offc, z, er, p, cmapa, N)) / dg));
         return;
     }
     const i64 p = rowb + u;
@@ -604,7 +606,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_pair_zero(i64 rowa, i64 rowb, i64
     }
     const T rp = to_t<T>(r[p]);
     const T dg = to_t<T>(ld_stream(diag + p));
-    z[p] = from_t<S>((rp - ell_row_dot_x<T, V, MB, C16>(offv, offc, z, er, p, cmapb, N, xn[0], xn[1])) / dg);
+    const T acc = ell_row_dot_x<T, V, MB, C16>(offv, offc, z, er, p, cmapb, N, xn[0], xn[1]);
+    st_stream(z + p, from_t<S>((rp - acc) / dg));
 }
 
 template <typename V, typename S, int A_, bool FWD>
@@ -668,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict(Geom gf, Geom gc, int clog2
     const T acc = to_t<T>(ld_stream(diag + p)) * to_t<T>(z[p]) +
                   ell_row_dot<T, V, kAllSlots, C16>(offv, offc, z, er, p, cmap4, N);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
-    rc[to_internal(gc, I, J, K)] = from_t<S>(rp - acc);
+    st_stream(rc + to_internal(gc, I, J, K), from_t<S>(rp - acc));
 }
 
 void launch_restrict(const Matrix &Af, const Geom &gc, Prec p, const void *r, const void *z,
@@ -713,7 +716,7 @@ __global__ __launch_bounds__(kBlock) void k_restrict_after_sweep(Geom gf, Geom g
     const EllRow er = ell_row(p, N, clog2);
     const T acc = ell_row_dot<T, V, MASK, C16>(offv, offc, z, er, p, cmap4, N);
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
-    rc[to_internal(gc, I, J, K)] = from_t<S>(-acc);
+    st_stream(rc + to_internal(gc, I, J, K), from_t<S>(-acc));
 }
 
 void launch_restrict_after_sweep(const Matrix &Af, const Geom &gc, Prec p, bool forward, const void *z, void *rc,
@@ -749,7 +752,7 @@ __global__ __launch_bounds__(kBlock) void k_prolong(Geom gf, Geom gc, const S *_
     if (q >= gc.N) return;
     const int I = (int)(q % gc.nx), J = (int)((q / gc.nx) % gc.ny), K = (int)(q / ((i64)gc.nx * gc.ny));
     const i64 p = gf.off[4] + q;
-    z[p] = from_t<S>(to_t<T>(z[p]) + to_t<T>(zc[to_internal(gc, I, J, K)]));
+    st_stream(z + p, from_t<S>(to_t<T>(z[p]) + to_t<T>(zc[to_internal(gc, I, J, K)])));
 }
 
 void launch_prolong(const Geom &gf, const Geom &gc, Prec p, const void *zc, void *z, hipStream_t s)
