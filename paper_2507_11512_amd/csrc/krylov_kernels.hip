@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_cast_mg(i64 N, const float *__restri
     }
     const float sg = (float)sigma;
     const i64 e = (i64)blockIdx.x * kBlock + threadIdx.x;
-    if (e < N) r0[e] = from_t<S>(v[e] * sg);
+    if (e < N) st_stream(r0 + e, from_t<S>(v[e] * sg));  // read by the V-cycle that follows
 }
 
 // ---- streaming copy (bandwidth reference) -------------------------------------------------------------
