@@ -328,6 +328,11 @@ def test_solve_256_16bit_matrices(hp, p256, precision):
 
 
 BANDWIDTH_BAR = 0.70   # of the 8 TB/s HBM peak, in algorithmic bytes per HIP-event second
+# The read-only Krylov passes (h1 = Q^T w and the reorthogonalisation) stream
+# at 85-87 %: a vector written with plain stores just before a pass reads it
+# costs such a pass about 10 % (the SpMV's w before h1 = Q^T w did), so they
+# are held to a higher bar.
+READ_PASS_BAR = 0.80
 
 
 def test_bandwidth_320(hp, p320):
@@ -336,8 +341,8 @@ def test_bandwidth_320(hp, p320):
     algorithmic bytes.  Every level-0 SpMV, Gauss-Seidel (all slots, and
     from the zero guess) and orthogonalisation pass (h1 = Q^T w, the
     reorthogonalisation, the update with its norm) reaches 70 % of the HBM
-    peak; the one-workgroup finish kernels of the reductions are timed
-    apart.  Not held to the bar: the coarser levels (160^3 and below: a
+    peak, the two read-only passes 80 %; the one-workgroup finish kernels
+    of the reductions are timed apart.  Not held to the bar: the coarser levels (160^3 and below: a
     colour pass there takes a few microseconds, latency and launch bound),
     the restriction (eq. (6) at the 1/8 of points that are injection points:
     8 slots per coarse row, a short launch) and the FP64 outer residual (once
@@ -358,7 +363,8 @@ def test_bandwidth_320(hp, p320):
         assert n > 0, hp.KERNEL_NAMES[kid]
         rates[hp.KERNEL_NAMES[kid]] = table[(kid, 0)] / (t / 1e3) / 1e9 / peak
     print("[bandwidth 320^3] " + ", ".join(f"{k} {v:.3f}" for k, v in rates.items()), flush=True)
-    low = {k: v for k, v in rates.items() if v < BANDWIDTH_BAR}
+    bar = {hp.KERNEL_NAMES[hp.K_DOT]: READ_PASS_BAR, hp.KERNEL_NAMES[hp.K_CGS_DOT]: READ_PASS_BAR}
+    low = {k: v for k, v in rates.items() if v < bar.get(k, BANDWIDTH_BAR)}
     assert not low, low
 
 
