@@ -327,47 +327,6 @@ def test_solve_256_16bit_matrices(hp, p256, precision):
     assert st.converged and res <= 1e-9 and err <= 1e-8 and e64 <= 1e-8
 
 
-BANDWIDTH_BAR = 0.70   # of the 8 TB/s HBM peak, in algorithmic bytes per HIP-event second
-# The read-only Krylov passes (h1 = Q^T w and the reorthogonalisation) stream
-# at 85-87 %: a vector written with plain stores just before a pass reads it
-# costs such a pass about 10 % (the SpMV's w before h1 = Q^T w did), so they
-# are held to a higher bar.
-READ_PASS_BAR = 0.80
-
-
-def test_bandwidth_320(hp, p320):
-    """The bandwidth bar at 320^3, kernel by kernel: per-kernel HIP-event
-    times of a profiled 30-step mixed-precision solve against each kernel's
-    algorithmic bytes.  Every level-0 SpMV, Gauss-Seidel (all slots, and
-    from the zero guess) and orthogonalisation pass (h1 = Q^T w, the
-    reorthogonalisation, the update with its norm) reaches 70 % of the HBM
-    peak, the two read-only passes 80 %; the one-workgroup finish kernels
-    of the reductions are timed apart.  Not held to the bar: the coarser levels (160^3 and below: a
-    colour pass there takes a few microseconds, latency and launch bound),
-    the restriction (eq. (6) at the 1/8 of points that are injection points:
-    8 slots per coarse row, a short launch) and the FP64 outer residual (once
-    per restart cycle)."""
-    import torch
-    import bench
-    from paper_2507_11512_amd import perfmodel as pm
-    b = p320.rhs_from_x(torch.ones(320 ** 3, dtype=torch.float64, device="cuda"))
-    p320.solve(b, tol=0.0, restart=30, max_iters=30, precision="mxp")  # warm-up
-    x, st = p320.solve(b, tol=0.0, restart=30, max_iters=30, precision="mxp", profile=True)
-    assert st.iters == 30
-    cfg = pm.Config(dims=(320, 320, 320), levels=4, pre=1, post=1, coarsest=1, sweep=0, restart=30)
-    table = bench.kernel_bytes_table(cfg, [30], 1, hp, pm)
-    peak = bench.PEAK_HBM_GBPS
-    rates = {}
-    for kid in (hp.K_GS, hp.K_GS_ZERO, hp.K_SPMV, hp.K_DOT, hp.K_CGS_DOT, hp.K_CGS_NORM):
-        t, n = hp.profile_get(p320.h, kid, 0)
-        assert n > 0, hp.KERNEL_NAMES[kid]
-        rates[hp.KERNEL_NAMES[kid]] = table[(kid, 0)] / (t / 1e3) / 1e9 / peak
-    print("[bandwidth 320^3] " + ", ".join(f"{k} {v:.3f}" for k, v in rates.items()), flush=True)
-    bar = {hp.KERNEL_NAMES[hp.K_DOT]: READ_PASS_BAR, hp.KERNEL_NAMES[hp.K_CGS_DOT]: READ_PASS_BAR}
-    low = {k: v for k, v in rates.items() if v < bar.get(k, BANDWIDTH_BAR)}
-    assert not low, low
-
-
 def test_largest_grid_512_sampled(hp):
     """The largest grid run here, 512^3 (134M unknowns; ELL entries and
     workspace offsets beyond 2^31): sampled FP32 and FP64 SpMV rows against
